@@ -1,0 +1,319 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+None of these compares the oracle with itself: each check is a brute-force
+computation, a closed form, a textbook scalar recurrence, an invariant or
+an independent discretisation (forward-Euler finite differences).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import spectral
+from oracle.fd_euler import euler_n
+from paper_2109_02598_amd import inputs
+
+CONFIG_COEF = {
+    "allen_cahn": (1.0, 1.0, 1.0, 1.0),
+    "cahn_hilliard": (1.0, 1.0, 1.0, 1.0),
+    "pfc": (-0.25, 1.0, 0.0, 1.0),
+    "gray_scott": (0.16, 0.08, 0.035, 0.065),
+    "model_c": (1.0, 1.0, 1.0, 1.0, 1.0),
+}
+
+
+def naive_dft(x, inverse=False):
+    """O(N^2) DFT, one axis at a time, by explicit exponentials."""
+    x = np.asarray(x, dtype=np.complex128)
+    sign = 1.0 if inverse else -1.0
+    for ax in range(x.ndim):
+        n = x.shape[ax]
+        out = np.zeros_like(x)
+        xm = np.moveaxis(x, ax, 0)
+        om = np.moveaxis(out, ax, 0)
+        for k in range(n):
+            acc = 0
+            for j in range(n):
+                acc = acc + xm[j] * complex(math.cos(2 * math.pi * k * j / n),
+                                            sign * math.sin(2 * math.pi * k * j / n))
+            om[k] = acc / n if inverse else acc
+        x = out
+    return x
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def random_fields(model, shape, seed, lo=-0.3, hi=0.3):
+    nf = spectral.NFIELDS[model]
+    return [inputs.uniform_field(seed + 17 * i, shape, lo, hi) for i in range(nf)]
+
+
+# --------------------------------------------------------------------------
+# 1. The transform: brute force
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(8, 8), (8, 16), (4, 4, 4), (2, 4, 8)])
+def test_library_fft_matches_naive_dft(shape):
+    re = inputs.uniform_field(11, shape, -1, 1)
+    im = inputs.uniform_field(12, shape, -1, 1)
+    x = re + 1j * im
+    assert rel(np.fft.fftn(x), naive_dft(x)) < 1e-13
+    assert rel(np.fft.ifftn(x), naive_dft(x, inverse=True)) < 1e-13
+
+
+@pytest.mark.parametrize("model", sorted(CONFIG_COEF))
+@pytest.mark.parametrize("shape,dx", [((8, 16), (1.0, 0.7)), ((4, 4, 8), (0.9, 1.0, 1.1))])
+def test_step_with_naive_dft(model, shape, dx):
+    q0 = random_fields(model, shape, 5)
+    a = spectral.step_n(q0, model, CONFIG_COEF[model], 0.05, dx, 2)
+    b = spectral.step_n(q0, model, CONFIG_COEF[model], 0.05, dx, 2,
+                        fft=(naive_dft, lambda x: naive_dft(x, inverse=True)))
+    for fa, fb in zip(a, b):
+        assert rel(fa, fb) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# 2. A: exact per-mode decay of the linear operator on single modes
+# --------------------------------------------------------------------------
+
+def single_mode(shape, dx, ms, amp):
+    """amp * cos(k.x) and |k|^2 for integer mode numbers ms=(mx, my[, mz])."""
+    axes = [np.arange(s) * d for s, d in zip(shape, reversed(dx))]
+    g = np.meshgrid(*axes, indexing="ij")
+    lengths = [s * d for s, d in zip(shape, reversed(dx))]
+    ms_arr = list(reversed(ms))              # array-axis order
+    arg = sum(2 * math.pi * m * x / ln for m, x, ln in zip(ms_arr, g, lengths))
+    k2 = sum((2 * math.pi * m / ln) ** 2 for m, ln in zip(ms_arr, lengths))
+    return amp * np.cos(arg), k2
+
+
+def linear_symbol(model, coef, k2):
+    """L(k^2) written out from the model equations (closed form)."""
+    c = coef
+    if model == "allen_cahn":
+        return c[0] * (c[2] - c[1] * k2)
+    if model == "cahn_hilliard":
+        return c[0] * (c[2] * k2 - c[1] * k2 * k2)
+    if model == "pfc":
+        return -k2 * (c[0] + (c[1] ** 2 - k2) ** 2)
+    raise AssertionError
+
+
+LINEAR_OFF = {
+    "allen_cahn": (1.3, 0.8, 0.6, 0.0),
+    "cahn_hilliard": (0.9, 1.2, 0.7, 0.0),
+    "pfc": (-0.25, 0.8, 0.0, 0.0),
+}
+
+
+@pytest.mark.parametrize("model", sorted(LINEAR_OFF))
+@pytest.mark.parametrize("shape,dx,ms", [((32, 64), (1.0, 0.5), (3, -5)),
+                                         ((16, 8, 8), (math.pi / 4,) * 3, (1, 2, 3))])
+def test_single_mode_exact_decay(model, shape, dx, ms):
+    coef = LINEAR_OFF[model]
+    dt, n = 0.1, 7
+    q0, k2 = single_mode(shape, dx, ms, 0.4)
+    out = spectral.step_n([q0], model, coef, dt, dx, n)[0]
+    expect = q0 * math.exp(n * linear_symbol(model, coef, k2) * dt)
+    # roundoff of the transforms is relative to the initial amplitude
+    tol = 1e-13 * np.max(np.abs(expect)) + 1e-14 * np.max(np.abs(q0))
+    assert np.max(np.abs(out - expect)) <= tol
+
+
+@pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc"])
+def test_single_mode_small_amplitude_config_coefficients(model):
+    """With the workload coefficients and amplitude 1e-7 the nonlinearity is
+    ~1e-14 relative; the closed form of the linear part still holds."""
+    coef = CONFIG_COEF[model]
+    shape, dx = ((32, 32), (1.0, 1.0)) if model != "pfc" else ((32, 32), (math.pi / 4,) * 2)
+    q0, k2 = single_mode(shape, dx, (2, 1), 1e-7)
+    dt, n = 0.1, 5
+    out = spectral.step_n([q0], model, coef, dt, dx, n)[0]
+    expect = q0 * math.exp(n * linear_symbol(model, coef, k2) * dt)
+    assert rel(out, expect) < 1e-12
+
+
+def test_gray_scott_linear_forced_mode_is_exact():
+    """v = 0 makes u_t = Du lap u + F (1 - u) linear with a constant source:
+    ETD1 is exact, so u - 1 decays per mode as exp(-(Du k^2 + F) t)."""
+    coef = (0.16, 0.08, 0.035, 0.065)
+    shape, dx = (32, 16), (1.0, 1.0)
+    pert, k2 = single_mode(shape, dx, (2, 3), 0.2)
+    u0 = 1.0 + pert
+    v0 = np.zeros(shape)
+    dt, n = 1.0, 9
+    u, v = spectral.step_n([u0, v0], "gray_scott", coef, dt, dx, n)
+    expect = pert * math.exp(-(coef[0] * k2 + coef[2]) * n * dt)
+    assert np.max(np.abs((u - 1.0) - expect)) < 1e-14
+    assert np.max(np.abs(v)) == 0.0
+
+
+def test_model_c_linear_modes():
+    """Model C with the couplings and cubic terms off: psi decays with
+    c1 - k^2 and m with c3 k^2 - k^4."""
+    coef = (0.4, 0.0, 0.8, 0.0, 0.0)
+    shape, dx = (16, 32), (1.0, 1.0)
+    p0, k2p = single_mode(shape, dx, (3, 1), 0.3)
+    m0, k2m = single_mode(shape, dx, (1, 2), 0.2)
+    dt, n = 0.2, 6
+    p, m = spectral.step_n([p0, m0], "model_c", coef, dt, dx, n)
+    assert rel(p, p0 * math.exp(n * dt * (0.4 - k2p))) < 1e-13
+    assert rel(m, m0 * math.exp(n * dt * (0.8 * k2m - k2m ** 2))) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# 3. B at k = 0 with a nonlinear term: textbook scalar ETD1 recurrences
+# --------------------------------------------------------------------------
+
+def test_uniform_allen_cahn_scalar_recurrence():
+    M, kap, c1, c2 = 1.0, 1.0, 1.0, 1.0
+    dt, n, psi = 0.5, 12, 0.3
+    out = spectral.step_n([np.full((8, 16), psi)], "allen_cahn", (M, kap, c1, c2),
+                          dt, (1.0, 1.0), n)[0]
+    x = psi
+    for _ in range(n):
+        x = math.exp(c1 * dt) * x + (math.exp(c1 * dt) - 1.0) / c1 * (-c2 * x ** 3)
+    assert np.max(np.abs(out - x)) < 1e-14
+
+
+def test_uniform_gray_scott_scalar_recurrence():
+    du, dv, F, kk = 0.16, 0.08, 0.035, 0.065
+    dt, n = 1.0, 15
+    u, v = 0.7, 0.2
+    uo, vo = spectral.step_n([np.full((8, 8), u), np.full((8, 8), v)], "gray_scott",
+                             (du, dv, F, kk), dt, (1.0, 1.0), n)
+    for _ in range(n):
+        eu, ev = math.exp(-F * dt), math.exp(-(F + kk) * dt)
+        gu, gv = F - u * v * v, u * v * v
+        u, v = eu * u + (eu - 1.0) / (-F) * gu, ev * v + (ev - 1.0) / (-(F + kk)) * gv
+    assert np.max(np.abs(uo - u)) < 1e-14
+    assert np.max(np.abs(vo - v)) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# 4. Invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("model,shape,dx,dt,n", [
+    ("cahn_hilliard", (64, 64), (1.0, 1.0), 0.1, 1000),
+    ("pfc", (16, 16, 16), (math.pi / 4,) * 3, 0.5, 500),
+])
+def test_mass_conservation(model, shape, dx, dt, n):
+    if model == "pfc":
+        q0 = [-0.285 + inputs.uniform_field(3, shape, -0.05, 0.05)]
+    else:
+        q0 = [inputs.uniform_field(2, shape, -0.05, 0.05)]
+    m0 = float(np.mean(q0[0]))
+    log = []
+    spectral.step_n(q0, model, CONFIG_COEF[model], dt, dx, n, mass_log=log)
+    drift = max(abs(m[0] - m0) for m in log)
+    assert drift <= 1e-14
+
+
+@pytest.mark.parametrize("model", ["cahn_hilliard", "pfc"])
+def test_uniform_field_stays_uniform(model):
+    q = spectral.step_n([np.full((16, 16), -0.2)], model, CONFIG_COEF[model], 0.1,
+                        (1.0, 1.0), 20)[0]
+    assert np.max(q) - np.min(q) <= 1e-15
+    assert abs(float(np.mean(q)) + 0.2) <= 1e-15
+
+
+@pytest.mark.parametrize("model", sorted(CONFIG_COEF))
+def test_shift_equivariance(model):
+    shape = (16, 32)
+    q0 = random_fields(model, shape, 21)
+    if model == "gray_scott":
+        q0 = [1.0 + 0.2 * q0[0], 0.25 + q0[1]]
+    a = spectral.step_n(q0, model, CONFIG_COEF[model], 0.05, (1.0, 1.0), 4)
+    shifted = [np.roll(np.roll(f, 3, axis=1), -5, axis=0) for f in q0]
+    b = spectral.step_n(shifted, model, CONFIG_COEF[model], 0.05, (1.0, 1.0), 4)
+    for fa, fb in zip(a, b):
+        fa_s = np.roll(np.roll(fa, 3, axis=1), -5, axis=0)
+        assert np.max(np.abs(fa_s - fb)) <= 1e-13 * np.max(np.abs(fa))
+
+
+@pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard"])
+def test_odd_symmetry(model):
+    q0 = random_fields(model, (16, 16), 31)
+    a = spectral.step_n(q0, model, CONFIG_COEF[model], 0.1, (1.0, 1.0), 5)[0]
+    b = spectral.step_n([-q0[0]], model, CONFIG_COEF[model], 0.1, (1.0, 1.0), 5)[0]
+    assert np.max(np.abs(a + b)) <= 1e-15 * max(1.0, np.max(np.abs(a)))
+
+
+def test_gray_scott_fixed_point():
+    u, v = spectral.step_n([np.ones((16, 16)), np.zeros((16, 16))], "gray_scott",
+                           CONFIG_COEF["gray_scott"], 1.0, (1.0, 1.0), 10)
+    assert np.max(np.abs(u - 1.0)) <= 1e-15
+    assert np.max(np.abs(v)) == 0.0
+
+
+# --------------------------------------------------------------------------
+# 5. Independent discretisation: explicit forward-Euler finite differences
+# --------------------------------------------------------------------------
+
+FD_CASES = {
+    # model: (domain side, coarse n, dt, T, amplitude, offset)
+    "allen_cahn": (32.0, 32, 2.5e-4, 0.5, 0.3, 0.0),
+    "cahn_hilliard": (32.0, 32, 2e-4, 0.2, 0.3, 0.0),
+    "gray_scott": (32.0, 32, 2.5e-4, 0.5, 0.1, 0.0),
+    "pfc": (16 * math.pi, 32, 2e-5, 0.02, 0.1, -0.285),
+    "model_c": (32.0, 32, 2e-4, 0.2, 0.3, 0.0),
+}
+
+
+# q0 != 1 and g2 != 0 so that every PFC coefficient enters the comparison
+FD_COEF = {"pfc": (-0.25, 0.9, 0.3, 1.0)}
+
+
+def fd_increment_error(model, n):
+    side, _, dt, T, amp, off = FD_CASES[model]
+    h = side / n
+    dx = (h, h)
+    nsteps = int(round(T / dt))
+    shape = (n, n)
+    nf = spectral.NFIELDS[model]
+    q0 = [inputs.smooth_modes(shape, dx, 40 + i, amp=amp, mmax=3, offset=off)
+          for i in range(nf)]
+    if model == "gray_scott":
+        q0 = [1.0 + q0[0], 0.25 + q0[1]]
+    coef = FD_COEF.get(model, CONFIG_COEF[model])
+    s = spectral.step_n(q0, model, coef, dt, dx, nsteps)
+    f = euler_n(q0, model, coef, dt, dx, nsteps)
+    errs = []
+    for a, b, c in zip(s, f, q0):
+        ds, df = a - c, b - c
+        errs.append(float(np.linalg.norm(ds - df) / np.linalg.norm(ds)))
+    return max(errs)
+
+
+@pytest.mark.parametrize("model", sorted(FD_CASES))
+def test_fd_cross_check_second_order(model):
+    n = FD_CASES[model][1]
+    coarse = fd_increment_error(model, n)
+    fine = fd_increment_error(model, 2 * n)
+    assert coarse < 5e-2, coarse
+    ratio = coarse / fine
+    assert 3.0 < ratio < 5.0, (coarse, fine, ratio)
+
+
+# --------------------------------------------------------------------------
+# 6. Temporal order: first order (ETD1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("model", ["allen_cahn", "gray_scott"])
+def test_first_order_in_time(model):
+    shape, dx = (32, 32), (1.0, 1.0)
+    q0 = [inputs.smooth_modes(shape, dx, 60 + i, amp=0.5, mmax=3) for i in range(2)]
+    q0 = q0[:spectral.NFIELDS[model]]
+    if model == "gray_scott":
+        q0 = [1.0 + 0.3 * q0[0], 0.25 + 0.3 * q0[1]]
+    coef, T = CONFIG_COEF[model], 2.0
+    ref = spectral.step_n(q0, model, coef, T / 1024, dx, 1024)
+    errs = []
+    for n in (16, 32, 64):
+        out = spectral.step_n(q0, model, coef, T / n, dx, n)
+        errs.append(max(np.linalg.norm(a - b) for a, b in zip(out, ref)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.7 < r1 < 2.3 and 1.7 < r2 < 2.3, errs
