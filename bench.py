@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the semi-implicit Fourier spectral step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload ch2048] [--dtype f64]
+
+Workload (default): 2D Cahn-Hilliard on a 2048x2048 periodic grid, dx=1,
+dt=0.1, M=kappa=c1=c2=1, phi ~ U[-0.05, 0.05) from seed 2, with the
+per-step mass log on.  A "step" is one full spectral time step (nonlinear
+term, forward transforms, ETD1 update, inverse transforms, mass entry).
+Inputs are resident in HBM before the timed region; the K steps are
+bracketed by torch.cuda.synchronize() and HIP events on the stream the
+library launches on.  The metric is cell-updates/s = cells * K / time.
+
+Also reported: the roofline of the dominant kernel (its algorithmic bytes
+per launch divided by its mean launch time from per-launch HIP events),
+the FP32 run of the same workload, and the FP64 oracle on the host CPU
+over a bounded sample of steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+
+
+def workloads():
+    from paper_2109_02598_amd import inputs
+    return {
+        "ch2048": lambda: inputs.cahn_hilliard_2d(n=2048, seed=2, steps=1000),
+        "ac128": lambda: inputs.allen_cahn_2d(n=128, seed=1, steps=100),
+        "pfc256": lambda: inputs.pfc_3d(n=256, seed=3, steps=500),
+        "gs512": lambda: inputs.gray_scott_2d(n=512),
+    }
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2109_02598_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(pass_name, w, esz):
+    """HBM bytes one launch of a pass must move at minimum (read + write).
+
+    Every array is cells*esz bytes (half spectrum with the kx=0/Nyquist
+    packing).  x pass: reads the state of each field, writes the
+    nonlinear term of each field.  k-space pass: reads state and nonlinear
+    term, writes the state (one launch covers every field).  y passes:
+    read and write one array of one field.
+    """
+    n = w.cells * esz
+    nf = len(w.fields)
+    return {"xpass": 2 * nf * n, "kpass": 3 * nf * n,
+            "ypass_inv": 2 * n, "ypass_fwd": 2 * n}[pass_name]
+
+
+def run_gpu(w, dtype, steps, warmup, profile_steps):
+    import torch
+    from paper_2109_02598_amd import specstep
+    g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=w.dt)
+    for i, f in enumerate(w.fields):
+        g.set_field(i, torch.from_numpy(f).to("cuda:0"))
+    g.enable_mass_log(warmup + steps + profile_steps)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    prof = g.step_profiled(profile_steps)
+    mass = g.mass_log()
+    g.close()
+    return ms, wall, prof, mass
+
+
+def roofline(w, dtype, prof, traffic_rec):
+    esz = 8 if dtype == "f64" else 4
+    per = {k: (v[0] / v[1]) for k, v in prof.items()}
+    dom = max(per, key=per.get)
+    algo = algorithmic_bytes(dom, w, esz)
+    achieved = algo / (per[dom] * 1e-3) / 1e9
+    traffic = None
+    if traffic_rec and traffic_rec.get("kernel") == dom:
+        traffic = traffic_rec.get("bytes_per_launch")
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": algo,
+            "mean_launch_us": {k: round(v * 1e3, 2) for k, v in per.items()}}
+
+
+def load_traffic(workload, dtype):
+    """HBM bytes per launch from rocprofv3 counters, if taken on the current kernels."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, dtype))
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """FP64 oracle on the host over a bounded number of steps."""
+    from oracle import spectral
+    t = time.perf_counter()
+    q = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, 1)
+    one = time.perf_counter() - t
+    nsteps = int(max(1, min(200, budget_s // max(one, 1e-6))))
+    t = time.perf_counter()
+    spectral.step_n(q, w.model, w.coef, w.dt, w.dx, nsteps)
+    dt = time.perf_counter() - t
+    return {"value": round(w.cells * nsteps / dt, 1), "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d steps of the %s workload (after 1 untimed step), numpy FP64, "
+                      "single-threaded pocketfft on %s" % (nsteps, w.name, platform.processor() or platform.machine())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="ch2048", choices=sorted(workloads()))
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--profile-steps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(independent simulations shard with no communication; one large grid "
+              "would need an all-to-all transpose per FFT)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2109_02598_amd import specstep
+    if not os.path.exists(specstep.LIB_PATH):
+        from paper_2109_02598_amd import build
+        build.build()
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    w = workloads()[args.workload]()
+    print("bench: workload %s cells %d dtype %s steps %d warmup %d" %
+          (w.name, w.cells, args.dtype, args.steps, args.warmup), file=sys.stderr, flush=True)
+    ms, wall, prof, mass = run_gpu(w, args.dtype, args.steps, args.warmup, args.profile_steps)
+    value = w.cells * args.steps / (ms * 1e-3)
+    roof = roofline(w, args.dtype, prof, load_traffic(args.workload, args.dtype))
+    other = "f32" if args.dtype == "f64" else "f64"
+    print("bench: %s done, %.3f ms/step; running %s" % (args.dtype, ms / args.steps, other),
+          file=sys.stderr, flush=True)
+    ms2, _, prof2, _ = run_gpu(w, other, args.steps, args.warmup, args.profile_steps)
+    roof2 = roofline(w, other, prof2, load_traffic(args.workload, other))
+    drift = float(abs(mass[-1][0] - mass[0][0])) if len(mass) else None
+    out = {
+        "metric": "grid cell-updates/sec per spectral step + % peak HBM BW",
+        "value": round(value, 1),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded SplitMix64 uniform noise)",
+        "config": {"workload": w.name, "model": w.model, "grid": list(w.n), "dx": list(w.dx),
+                   "dt": w.dt, "coef": list(w.coef), "mass_log": True, "parallelism": "1 GPU"},
+        "roofline": roof,
+        "other_dtype": {"dtype": other, "value": round(w.cells * args.steps / (ms2 * 1e-3), 1),
+                        "ms_per_step": round(ms2 / args.steps, 5), "roofline": roof2},
+        "mass_drift_over_run": drift,
+        "wall_s_timed_region": round(wall, 4),
+    }
+    if not args.no_cpu:
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

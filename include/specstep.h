@@ -1,0 +1,155 @@
+/*
+ * specstep.h -- C ABI of the MI355X (gfx950) semi-implicit Fourier spectral
+ * step library (libspecstep.so).
+ *
+ * The method (Sec. 2.4.2 of Silber & Karttunen, "SymPhas -- general purpose
+ * software for phase-field, phase-field crystal and reaction-diffusion
+ * simulations"): an equation of motion d psi/dt = L{psi} + sum_i N_i{f_i(psi)}
+ * (Eq. 1) is Fourier transformed (Eq. 2) and advanced per wavevector by
+ *     psi^(t+dt) = A psi^(t) + B sum_i N_i f_i^(psi(t)),
+ *     A = exp(L dt),  B = (exp(L dt) - 1)/L                     (Eqs. 3, 4)
+ * with A and B computed once per model and time step (Sec. 2.4.2) and the
+ * nonlinear terms evaluated pointwise in real space every step.  Periodic
+ * boundaries are implied by the transform (Sec. 2.4.2).  Grids are
+ * row-major with x the fastest axis (Sec. 2.2.1).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an ss_status and never throws or exits.  On an
+ *     error the thread-local message is available from ss_last_error().
+ *   - The library never allocates device memory: the caller provides the
+ *     workspace (ss_bind_workspace) and the mass log buffer.  Handles are
+ *     created by ss_create_grid and freed by ss_destroy_grid.
+ *   - Device work is enqueued on the HIP stream given at creation
+ *     (ss_set_stream to change it).  ss_step_n never synchronises; calls
+ *     that read or write host memory synchronise the stream before they
+ *     return.  Host pointers are only read/written during the call.
+ *   - Field arrays are C-contiguous (nz, ny, nx) arrays of the grid's
+ *     element type (float for SS_F32, double for SS_F64), x fastest.
+ *   - Launch failures return SS_ERR_DEVICE; faults of earlier asynchronous
+ *     work surface at a later call.
+ */
+#ifndef SPECSTEP_H
+#define SPECSTEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ss_grid_s* ss_grid;
+
+typedef enum {
+  SS_OK = 0,
+  SS_ERR_ARG = 1,          /* invalid argument (null, range, non-finite) */
+  SS_ERR_UNSUPPORTED = 2,  /* valid but not implemented (e.g. axis not 2^k) */
+  SS_ERR_STATE = 3,        /* call out of order (no model, workspace, field) */
+  SS_ERR_DEVICE = 4,       /* HIP runtime error */
+  SS_ERR_NONFINITE = 5     /* a checked value is NaN or infinite */
+} ss_status;
+
+typedef enum { SS_F32 = 4, SS_F64 = 8 } ss_dtype;
+
+/* Models and their coefficient vectors (Sec. 3, Eqs. 9-13; Gray-Scott
+ * reaction-diffusion is named in Sec. 1 but not written out).
+ *   SS_ALLEN_CAHN    {M, kappa, c1, c2}   d psi/dt = M (kappa lap psi + c1 psi - c2 psi^3)
+ *   SS_CAHN_HILLIARD {M, kappa, c1, c2}   d psi/dt = M lap (c2 psi^3 - c1 psi - kappa lap psi)
+ *   SS_PFC           {r, q0, g2, g3}      d psi/dt = lap[(r + (q0^2 + lap)^2) psi + g2 psi^2 + g3 psi^3]
+ *   SS_GRAY_SCOTT    {Du, Dv, F, k}       u_t = Du lap u - u v^2 + F (1 - u)
+ *                                         v_t = Dv lap v + u v^2 - (F + k) v   (fields 0 = u, 1 = v)
+ *   SS_MODEL_C       {c1, c2, c3, c4, c5} psi_t = lap psi + c1 psi - c2 psi^3 + 2 c5 psi m
+ *                                         m_t = -lap^2 m - lap(c3 m - c4 m^3 + c5 psi^2)  (0 = psi, 1 = m)
+ * Every term linear in a field goes into L (solved exactly by A); the
+ * remaining terms are the explicit f_i. */
+typedef enum {
+  SS_ALLEN_CAHN = 1,
+  SS_CAHN_HILLIARD = 2,
+  SS_PFC = 3,
+  SS_GRAY_SCOTT = 4,
+  SS_MODEL_C = 5
+} ss_model;
+
+/* Create a grid handle.  ndim is 2 or 3; n[0] is the x extent (fastest),
+ * n[1] y, n[2] z; each a power of two in [8, 4096] (3D: z <= 1024).
+ * dx[] are the spacings (> 0, finite), same order.  stream is a
+ * hipStream_t (NULL = default stream).  The wavenumbers are
+ * k_j = 2 pi m_j / (n_j dx_j) (Sec. 2.4.2).
+ * Errors: SS_ERR_ARG, SS_ERR_UNSUPPORTED. */
+ss_status ss_create_grid(int ndim, const int64_t n[], const double dx[], ss_dtype dtype,
+                         void* stream, ss_grid* out);
+
+/* Choose the model, its coefficients (ncoef as listed above) and the time
+ * step dt > 0.  Plays the role of the solver's one-time set-up that forms
+ * the A and B operators a priori (Sec. 2.2.4, Sec. 2.4.2).  Changing the
+ * model drops the bound workspace and fields (SS_ERR_STATE afterwards
+ * until they are bound/set again); changing only coef or dt keeps them.
+ * Errors: SS_ERR_ARG (unknown model, ncoef, non-finite, dt <= 0). */
+ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef, double dt);
+
+/* Bytes of device workspace the grid needs (after ss_set_model). */
+ss_status ss_workspace_size(ss_grid g, size_t* bytes);
+
+/* Bind caller-owned device memory of at least ss_workspace_size bytes,
+ * 256-byte aligned.  The library keeps the pointer; the caller keeps it
+ * alive until the handle is destroyed or rebound.
+ * Errors: SS_ERR_STATE (no model), SS_ERR_ARG (null, too small, misaligned). */
+ss_status ss_bind_workspace(ss_grid g, void* device_ptr, size_t bytes);
+
+/* Load field `field` (0 .. nfields-1) from src, a (nz, ny, nx) array of
+ * the grid dtype on the device (src_on_device = 1) or the host (0).
+ * Errors: SS_ERR_STATE (no workspace), SS_ERR_ARG, SS_ERR_DEVICE. */
+ss_status ss_set_field(ss_grid g, int field, const void* src, int src_on_device);
+
+/* Write field `field` in real space to dst (device or host, as above).
+ * Errors: SS_ERR_STATE (field never set), SS_ERR_ARG, SS_ERR_DEVICE. */
+ss_status ss_get_field(ss_grid g, int field, void* dst, int dst_on_device);
+
+/* Advance every field by nsteps >= 0 semi-implicit spectral steps
+ * (Eq. 8): per step the nonlinear terms of all fields are evaluated from
+ * the current fields (Sec. 2.2.4, equation() before step()), transformed,
+ * and combined with the transformed fields through A and B N_i.
+ * Asynchronous on the grid's stream.
+ * Errors: SS_ERR_STATE (model, workspace or a field missing), SS_ERR_ARG,
+ * SS_ERR_DEVICE. */
+ss_status ss_step_n(ss_grid g, int64_t nsteps);
+
+/* Same as ss_step_n, and times every kernel launch with HIP events
+ * recorded on the grid's stream between consecutive launches.  On return
+ * (the stream is synchronised) pass_ms[i] holds the summed milliseconds of
+ * pass kind i and pass_count[i] the number of launches, for i <
+ * min(npass, SS_NPASS): 0 = x pass, 1 = k-space pass, 2 = inverse y pass,
+ * 3 = forward y pass (3D only).  For measurement; ss_step_n is the
+ * production entry point.
+ * Errors: as ss_step_n, plus SS_ERR_ARG for null outputs. */
+#define SS_NPASS 4
+ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t* pass_count,
+                             int npass);
+
+/* Bind a device buffer of capacity * nfields doubles for the per-step
+ * mass log (spatial mean of each field after each step; conserved for
+ * Cahn-Hilliard and PFC, Sec. 3).  Entry (i, f) is at [i*nfields + f]
+ * for the i-th step since the log was bound; steps beyond capacity are
+ * not logged.  device_ptr = NULL unbinds. */
+ss_status ss_bind_mass_log(ss_grid g, double* device_ptr, int64_t capacity);
+
+/* Number of steps taken since the mass log was bound. */
+ss_status ss_mass_log_count(ss_grid g, int64_t* count);
+
+/* Change the stream later calls enqueue on. */
+ss_status ss_set_stream(ss_grid g, void* stream);
+
+/* Free the handle (not the caller's device memory).  NULL is a no-op. */
+ss_status ss_destroy_grid(ss_grid g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ss_last_error(void);
+
+/* Library version string. */
+const char* ss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPECSTEP_H */

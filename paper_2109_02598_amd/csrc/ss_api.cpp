@@ -1,0 +1,533 @@
+// Host side of the C ABI declared in include/specstep.h.
+//
+// Sequencing per step (all on the grid's stream, no host synchronisation):
+//   2D:  xpass STEP  (state -> psi -> f -> x-spectrum of f, scratch)
+//        kpass       (y FFT of state and scratch, ETD1 update, inverse y FFT)
+//   3D:  ypass INV   (state -> scratch: back to real y)
+//        xpass STEP  (scratch in place: psi -> f -> x-spectrum of f)
+//        ypass FWD   (scratch in place)
+//        kpass       (z FFT, ETD1 update, inverse z FFT on the state)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/specstep.h"
+#include "ss_dispatch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+ss_status fail(ss_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ss_status fail(ss_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+ss_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(SS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return SS_OK;
+}
+
+bool pow2_in(int64_t v, int64_t lo, int64_t hi) {
+  return v >= lo && v <= hi && (v & (v - 1)) == 0;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct ss_grid_s {
+  int ndim = 0;
+  int64_t n[3] = {1, 1, 1};   // x, y, z
+  double dx[3] = {1, 1, 1};
+  ss_dtype dtype = SS_F64;
+  hipStream_t stream = nullptr;
+
+  bool has_model = false;
+  ss_model model = SS_ALLEN_CAHN;
+  int nf = 1;
+  double coef[8] = {0};
+  int ncoef = 0;
+  double dt = 0;
+  ss::KField kf[2];
+  int nlm = ss::NLIN_POLY;
+  double p[5] = {0};
+
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* state[2] = {nullptr, nullptr};
+  void* scratch[2] = {nullptr, nullptr};
+  void* staging = nullptr;
+  bool field_set[2] = {false, false};
+
+  double* mass_log = nullptr;
+  int64_t log_cap = 0;
+  int64_t log_count = 0;
+
+  int64_t cells() const { return n[0] * n[1] * n[2]; }
+  size_t esz() const { return (size_t)dtype; }
+  size_t field_bytes() const { return (size_t)cells() * esz(); }
+};
+
+namespace {
+
+int ncoef_of(ss_model m) {
+  switch (m) {
+    case SS_ALLEN_CAHN:
+    case SS_CAHN_HILLIARD:
+    case SS_PFC:
+    case SS_GRAY_SCOTT:
+      return 4;
+    case SS_MODEL_C:
+      return 5;
+  }
+  return -1;
+}
+
+// Linear symbol L(k^2) and operator N(k^2) of every field as polynomials
+// in k^2, and the pointwise nonlinearity (the split of Eq. 1 written out
+// for each model; every linear term, zeroth order included, is in L).
+void build_operators(ss_grid g) {
+  const double* c = g->coef;
+  for (auto& f : g->kf) {
+    for (double& v : f.l) v = 0;
+    for (double& v : f.n) v = 0;
+  }
+  for (double& v : g->p) v = 0;
+  switch (g->model) {
+    case SS_ALLEN_CAHN: {  // M (kappa lap + c1) psi - M c2 psi^3
+      const double M = c[0], kap = c[1], c1 = c[2], c2 = c[3];
+      g->kf[0].l[0] = M * c1;
+      g->kf[0].l[1] = -M * kap;
+      g->kf[0].n[0] = -M * c2;
+      g->nlm = ss::NLIN_POLY;
+      g->p[0] = 0.0;
+      g->p[1] = 1.0;
+      break;
+    }
+    case SS_CAHN_HILLIARD: {  // M lap(c2 psi^3 - c1 psi - kappa lap psi)
+      const double M = c[0], kap = c[1], c1 = c[2], c2 = c[3];
+      g->kf[0].l[1] = M * c1;
+      g->kf[0].l[2] = -M * kap;
+      g->kf[0].n[1] = -M * c2;
+      g->nlm = ss::NLIN_POLY;
+      g->p[0] = 0.0;
+      g->p[1] = 1.0;
+      break;
+    }
+    case SS_PFC: {  // lap[(r + (q0^2 + lap)^2) psi + g2 psi^2 + g3 psi^3]
+      const double r = c[0], q0 = c[1], g2 = c[2], g3 = c[3];
+      const double q2 = q0 * q0;
+      // -k^2 (r + (q0^2 - k^2)^2) = -(r + q0^4) k^2 + 2 q0^2 k^4 - k^6
+      g->kf[0].l[1] = -(r + q2 * q2);
+      g->kf[0].l[2] = 2.0 * q2;
+      g->kf[0].l[3] = -1.0;
+      g->kf[0].n[1] = -1.0;
+      g->nlm = ss::NLIN_POLY;
+      g->p[0] = g2;
+      g->p[1] = g3;
+      break;
+    }
+    case SS_GRAY_SCOTT: {  // u: Du lap - F, f = F - u v^2; v: Dv lap - (F+k), f = u v^2
+      const double du = c[0], dv = c[1], F = c[2], kk = c[3];
+      g->kf[0].l[0] = -F;
+      g->kf[0].l[1] = -du;
+      g->kf[0].n[0] = 1.0;
+      g->kf[1].l[0] = -(F + kk);
+      g->kf[1].l[1] = -dv;
+      g->kf[1].n[0] = 1.0;
+      g->nlm = ss::NLIN_GS;
+      g->p[0] = F;
+      break;
+    }
+    case SS_MODEL_C: {  // psi: c1 - k^2, f = -c2 psi^3 + 2 c5 psi m; m: c3 k^2 - k^4, N = k^2
+      const double c1 = c[0], c2 = c[1], c3 = c[2], c4 = c[3], c5 = c[4];
+      g->kf[0].l[0] = c1;
+      g->kf[0].l[1] = -1.0;
+      g->kf[0].n[0] = 1.0;
+      g->kf[1].l[1] = c3;
+      g->kf[1].l[2] = -1.0;
+      g->kf[1].n[1] = 1.0;
+      g->nlm = ss::NLIN_MODELC;
+      g->p[0] = c2;
+      g->p[1] = c4;
+      g->p[2] = c5;
+      break;
+    }
+  }
+}
+
+void carve_workspace(ss_grid g) {
+  char* b = (char*)g->ws;
+  const size_t fb = align_up(g->field_bytes());
+  for (int f = 0; f < 2; ++f) {
+    g->state[f] = f < g->nf ? b + (size_t)f * fb : nullptr;
+    g->scratch[f] = f < g->nf ? b + (size_t)(g->nf + f) * fb : nullptr;
+  }
+  g->staging = b + (size_t)(2 * g->nf) * fb;
+}
+
+template <typename T>
+ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void* in1, void* out0,
+                       void* out1, const void* real_in, void* real_out, double scale) {
+  ss::XArgs a;
+  memset(&a, 0, sizeof(a));
+  a.spec_in[0] = in0;
+  a.spec_in[1] = in1;
+  a.spec_out[0] = out0;
+  a.spec_out[1] = out1;
+  a.real_in = real_in;
+  a.real_out = real_out;
+  a.rows = g->n[1] * g->n[2];
+  a.nz = (int)g->n[2];
+  a.ny = (int)g->n[1];
+  a.xcd_remap = 1;
+  a.scale = scale;
+  for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+  return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, g->nlm, a, g->stream), "x pass launch");
+}
+
+template <typename T>
+ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double scale) {
+  ss::YArgs a;
+  memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.ny = (int)g->n[1];
+  a.nz = (int)g->n[2];
+  a.scale = scale;
+  return hip_check(ss::run_ypass<T>((int)g->n[1], dir, a, g->n[0] / 2, g->stream), "y pass launch");
+}
+
+template <typename T>
+ss_status launch_kpass(ss_grid g) {
+  ss::KArgs a;
+  memset(&a, 0, sizeof(a));
+  const bool three = g->ndim == 3;
+  for (int f = 0; f < g->nf; ++f) {
+    a.fld[f] = g->kf[f];
+    a.fld[f].state = g->state[f];
+    a.fld[f].nonlin = g->scratch[f];
+  }
+  a.J = three ? (int)g->n[1] : 1;
+  a.nlines = (int)(g->n[0] / 2) * a.J;
+  a.nx = (int)g->n[0];
+  const double two_pi = 6.283185307179586476925286766559;
+  a.sx = two_pi / ((double)g->n[0] * g->dx[0]);
+  a.sy = two_pi / ((double)g->n[1] * g->dx[1]);
+  a.sz = three ? two_pi / ((double)g->n[2] * g->dx[2]) : 0.0;
+  a.dt = g->dt;
+  const int64_t nlast = three ? g->n[2] : g->n[1];
+  a.a_scale = 1.0 / (double)nlast;
+  a.b_scale = 1.0 / (double)g->cells();
+  a.mass_log = g->mass_log;
+  a.log_index = g->log_count;
+  a.log_capacity = g->log_cap;
+  a.nf = g->nf;
+  a.three_d = three ? 1 : 0;
+  const int nl = (int)nlast;
+  return hip_check(ss::run_kpass<T>(nl, a, g->stream), "k-space pass launch");
+}
+
+// Optional per-launch timing: an event is recorded before the first launch
+// and after every launch; the gap between two events is charged to the
+// pass that was launched between them.
+struct PassTimer {
+  enum { kMaxEvents = 4096 };
+  hipEvent_t ev[kMaxEvents];
+  int kind[kMaxEvents];
+  int used = 0;
+  bool ok = true;
+};
+
+enum { PASS_X = 0, PASS_K = 1, PASS_YINV = 2, PASS_YFWD = 3 };
+
+ss_status mark(ss_grid g, PassTimer* pt, int kind) {
+  if (!pt) return SS_OK;
+  if (pt->used >= PassTimer::kMaxEvents) return fail(SS_ERR_ARG, "profiled run too long");
+  ss_status st = hip_check(hipEventRecord(pt->ev[pt->used], g->stream), "hipEventRecord");
+  pt->kind[pt->used] = kind;
+  pt->used++;
+  return st;
+}
+
+#define SS_TRY(x)                 \
+  do {                            \
+    ss_status st_ = (x);          \
+    if (st_ != SS_OK) return st_; \
+  } while (0)
+
+template <typename T>
+ss_status step_once(ss_grid g, PassTimer* pt) {
+  if (g->ndim == 2) {
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], g->scratch[0],
+                           g->scratch[1], nullptr, nullptr, 1.0));
+    SS_TRY(mark(g, pt, PASS_X));
+  } else {
+    for (int f = 0; f < g->nf; ++f) {
+      SS_TRY(launch_ypass<T>(g, +1, g->state[f], g->scratch[f], 1.0));
+      SS_TRY(mark(g, pt, PASS_YINV));
+    }
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->scratch[0], g->scratch[1], g->scratch[0],
+                           g->scratch[1], nullptr, nullptr, 1.0));
+    SS_TRY(mark(g, pt, PASS_X));
+    for (int f = 0; f < g->nf; ++f) {
+      SS_TRY(launch_ypass<T>(g, -1, g->scratch[f], g->scratch[f], 1.0));
+      SS_TRY(mark(g, pt, PASS_YFWD));
+    }
+  }
+  SS_TRY(launch_kpass<T>(g));
+  SS_TRY(mark(g, pt, PASS_K));
+  g->log_count++;
+  return SS_OK;
+}
+
+template <typename T>
+ss_status set_field_t(ss_grid g, int field, const void* dsrc) {
+  ss_status st = launch_xpass<T>(g, ss::XMODE_FWD, 1, nullptr, nullptr, g->state[field], nullptr,
+                                 dsrc, nullptr, 1.0 / (double)g->n[0]);
+  if (st != SS_OK) return st;
+  if (g->ndim == 3)
+    st = launch_ypass<T>(g, -1, g->state[field], g->state[field], 1.0 / (double)g->n[1]);
+  return st;
+}
+
+template <typename T>
+ss_status get_field_t(ss_grid g, int field, void* ddst) {
+  const void* spec = g->state[field];
+  if (g->ndim == 3) {
+    ss_status st = launch_ypass<T>(g, +1, g->state[field], g->scratch[field], 1.0);
+    if (st != SS_OK) return st;
+    spec = g->scratch[field];
+  }
+  return launch_xpass<T>(g, ss::XMODE_INV, 1, spec, nullptr, nullptr, nullptr, nullptr, ddst, 1.0);
+}
+
+bool finite_all(const double* v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ss_last_error(void) { return g_err.c_str(); }
+
+const char* ss_version(void) { return "specstep 0.1 gfx950"; }
+
+ss_status ss_create_grid(int ndim, const int64_t n[], const double dx[], ss_dtype dtype,
+                         void* stream, ss_grid* out) {
+  if (!out) return fail(SS_ERR_ARG, "ss_create_grid: out is null");
+  *out = nullptr;
+  if (!n || !dx) return fail(SS_ERR_ARG, "ss_create_grid: n or dx is null");
+  if (ndim != 2 && ndim != 3) return fail(SS_ERR_ARG, "ss_create_grid: ndim must be 2 or 3, got %d", ndim);
+  if (dtype != SS_F32 && dtype != SS_F64) return fail(SS_ERR_ARG, "ss_create_grid: dtype must be SS_F32 or SS_F64");
+  for (int d = 0; d < ndim; ++d) {
+    if (!(std::isfinite(dx[d]) && dx[d] > 0.0))
+      return fail(SS_ERR_ARG, "ss_create_grid: dx[%d] must be finite and > 0", d);
+    if (!pow2_in(n[d], 8, 4096))
+      return fail(SS_ERR_UNSUPPORTED, "ss_create_grid: n[%d] = %lld is not a power of two in [8, 4096]", d,
+                  (long long)n[d]);
+  }
+  if (ndim == 3 && n[2] > 1024)
+    return fail(SS_ERR_UNSUPPORTED, "ss_create_grid: 3D grids need n[2] <= 1024");
+  ss_grid g = new (std::nothrow) ss_grid_s();
+  if (!g) return fail(SS_ERR_ARG, "ss_create_grid: out of host memory");
+  g->ndim = ndim;
+  for (int d = 0; d < ndim; ++d) {
+    g->n[d] = n[d];
+    g->dx[d] = dx[d];
+  }
+  g->dtype = dtype;
+  g->stream = (hipStream_t)stream;
+  *out = g;
+  return SS_OK;
+}
+
+ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef, double dt) {
+  if (!g) return fail(SS_ERR_ARG, "ss_set_model: null grid");
+  const int want = ncoef_of(model);
+  if (want < 0) return fail(SS_ERR_ARG, "ss_set_model: unknown model %d", (int)model);
+  if (ncoef != want) return fail(SS_ERR_ARG, "ss_set_model: model %d takes %d coefficients, got %d", (int)model, want, ncoef);
+  if (!coef) return fail(SS_ERR_ARG, "ss_set_model: coef is null");
+  if (!finite_all(coef, ncoef)) return fail(SS_ERR_ARG, "ss_set_model: non-finite coefficient");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(SS_ERR_ARG, "ss_set_model: dt must be finite and > 0");
+  const int nf = (model == SS_GRAY_SCOTT || model == SS_MODEL_C) ? 2 : 1;
+  if (g->has_model && model != g->model) {
+    g->ws = nullptr;
+    g->ws_bytes = 0;
+    g->field_set[0] = g->field_set[1] = false;
+  }
+  g->model = model;
+  g->nf = nf;
+  g->ncoef = ncoef;
+  for (int i = 0; i < ncoef; ++i) g->coef[i] = coef[i];
+  g->dt = dt;
+  g->has_model = true;
+  build_operators(g);
+  return SS_OK;
+}
+
+ss_status ss_workspace_size(ss_grid g, size_t* bytes) {
+  if (!g || !bytes) return fail(SS_ERR_ARG, "ss_workspace_size: null argument");
+  if (!g->has_model) return fail(SS_ERR_STATE, "ss_workspace_size: call ss_set_model first");
+  *bytes = align_up(g->field_bytes()) * (size_t)(2 * g->nf + 1);
+  return SS_OK;
+}
+
+ss_status ss_bind_workspace(ss_grid g, void* device_ptr, size_t bytes) {
+  if (!g) return fail(SS_ERR_ARG, "ss_bind_workspace: null grid");
+  if (!g->has_model) return fail(SS_ERR_STATE, "ss_bind_workspace: call ss_set_model first");
+  size_t need = 0;
+  ss_workspace_size(g, &need);
+  if (!device_ptr) return fail(SS_ERR_ARG, "ss_bind_workspace: null pointer");
+  if (((uintptr_t)device_ptr) % kAlign) return fail(SS_ERR_ARG, "ss_bind_workspace: pointer not 256-byte aligned");
+  if (bytes < need) return fail(SS_ERR_ARG, "ss_bind_workspace: %zu bytes given, %zu needed", bytes, need);
+  if (device_ptr != g->ws) g->field_set[0] = g->field_set[1] = false;
+  g->ws = device_ptr;
+  g->ws_bytes = bytes;
+  carve_workspace(g);
+  return SS_OK;
+}
+
+ss_status ss_set_field(ss_grid g, int field, const void* src, int src_on_device) {
+  if (!g) return fail(SS_ERR_ARG, "ss_set_field: null grid");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_set_field: model and workspace must be set first");
+  if (field < 0 || field >= g->nf) return fail(SS_ERR_ARG, "ss_set_field: field %d out of range [0, %d)", field, g->nf);
+  if (!src) return fail(SS_ERR_ARG, "ss_set_field: src is null");
+  const void* dsrc = src;
+  ss_status st;
+  if (!src_on_device) {
+    st = hip_check(hipMemcpyAsync(g->staging, src, g->field_bytes(), hipMemcpyHostToDevice, g->stream),
+                   "ss_set_field: host to device copy");
+    if (st != SS_OK) return st;
+    dsrc = g->staging;
+  }
+  st = g->dtype == SS_F64 ? set_field_t<double>(g, field, dsrc) : set_field_t<float>(g, field, dsrc);
+  if (st != SS_OK) return st;
+  if (!src_on_device) {
+    st = hip_check(hipStreamSynchronize(g->stream), "ss_set_field: synchronise");
+    if (st != SS_OK) return st;
+  }
+  g->field_set[field] = true;
+  return SS_OK;
+}
+
+ss_status ss_get_field(ss_grid g, int field, void* dst, int dst_on_device) {
+  if (!g) return fail(SS_ERR_ARG, "ss_get_field: null grid");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_get_field: model and workspace must be set first");
+  if (field < 0 || field >= g->nf) return fail(SS_ERR_ARG, "ss_get_field: field %d out of range [0, %d)", field, g->nf);
+  if (!g->field_set[field]) return fail(SS_ERR_STATE, "ss_get_field: field %d was never set", field);
+  if (!dst) return fail(SS_ERR_ARG, "ss_get_field: dst is null");
+  void* ddst = dst_on_device ? dst : g->staging;
+  ss_status st = g->dtype == SS_F64 ? get_field_t<double>(g, field, ddst) : get_field_t<float>(g, field, ddst);
+  if (st != SS_OK) return st;
+  if (!dst_on_device) {
+    st = hip_check(hipMemcpyAsync(dst, g->staging, g->field_bytes(), hipMemcpyDeviceToHost, g->stream),
+                   "ss_get_field: device to host copy");
+    if (st != SS_OK) return st;
+    st = hip_check(hipStreamSynchronize(g->stream), "ss_get_field: synchronise");
+    if (st != SS_OK) return st;
+  }
+  return SS_OK;
+}
+
+ss_status ss_step_n(ss_grid g, int64_t nsteps) {
+  if (!g) return fail(SS_ERR_ARG, "ss_step_n: null grid");
+  if (nsteps < 0) return fail(SS_ERR_ARG, "ss_step_n: nsteps must be >= 0");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_step_n: model and workspace must be set first");
+  for (int f = 0; f < g->nf; ++f)
+    if (!g->field_set[f]) return fail(SS_ERR_STATE, "ss_step_n: field %d was never set", f);
+  for (int64_t i = 0; i < nsteps; ++i) {
+    ss_status st = g->dtype == SS_F64 ? step_once<double>(g, nullptr) : step_once<float>(g, nullptr);
+    if (st != SS_OK) return st;
+  }
+  return SS_OK;
+}
+
+ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t* pass_count,
+                             int npass) {
+  if (!g) return fail(SS_ERR_ARG, "ss_step_n_profiled: null grid");
+  if (!pass_ms || !pass_count || npass <= 0) return fail(SS_ERR_ARG, "ss_step_n_profiled: null outputs");
+  if (nsteps < 0) return fail(SS_ERR_ARG, "ss_step_n_profiled: nsteps must be >= 0");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_step_n_profiled: model and workspace must be set first");
+  for (int f = 0; f < g->nf; ++f)
+    if (!g->field_set[f]) return fail(SS_ERR_STATE, "ss_step_n_profiled: field %d was never set", f);
+  const int per_step = g->ndim == 2 ? 2 : 2 * g->nf + 2;
+  if ((nsteps + 1) * per_step + 1 > PassTimer::kMaxEvents)
+    return fail(SS_ERR_ARG, "ss_step_n_profiled: at most %d steps per call",
+                (int)(PassTimer::kMaxEvents / per_step - 2));
+  PassTimer* pt = new (std::nothrow) PassTimer();
+  if (!pt) return fail(SS_ERR_ARG, "ss_step_n_profiled: out of host memory");
+  const int nev = (int)((nsteps)*per_step + 1);
+  ss_status st = SS_OK;
+  int created = 0;
+  for (; created < nev; ++created) {
+    st = hip_check(hipEventCreate(&pt->ev[created]), "hipEventCreate");
+    if (st != SS_OK) break;
+  }
+  if (st == SS_OK) st = mark(g, pt, -1);
+  for (int64_t i = 0; st == SS_OK && i < nsteps; ++i)
+    st = g->dtype == SS_F64 ? step_once<double>(g, pt) : step_once<float>(g, pt);
+  if (st == SS_OK) st = hip_check(hipStreamSynchronize(g->stream), "ss_step_n_profiled: synchronise");
+  if (st == SS_OK) {
+    for (int i = 0; i < npass; ++i) {
+      pass_ms[i] = 0.0;
+      pass_count[i] = 0;
+    }
+    for (int e = 1; e < pt->used; ++e) {
+      float ms = 0.f;
+      st = hip_check(hipEventElapsedTime(&ms, pt->ev[e - 1], pt->ev[e]), "hipEventElapsedTime");
+      if (st != SS_OK) break;
+      const int k = pt->kind[e];
+      if (k >= 0 && k < npass) {
+        pass_ms[k] += ms;
+        pass_count[k] += 1;
+      }
+    }
+  }
+  for (int e = 0; e < created; ++e) hipEventDestroy(pt->ev[e]);
+  delete pt;
+  return st;
+}
+
+ss_status ss_bind_mass_log(ss_grid g, double* device_ptr, int64_t capacity) {
+  if (!g) return fail(SS_ERR_ARG, "ss_bind_mass_log: null grid");
+  if (device_ptr && capacity < 0) return fail(SS_ERR_ARG, "ss_bind_mass_log: negative capacity");
+  g->mass_log = device_ptr;
+  g->log_cap = device_ptr ? capacity : 0;
+  g->log_count = 0;
+  return SS_OK;
+}
+
+ss_status ss_mass_log_count(ss_grid g, int64_t* count) {
+  if (!g || !count) return fail(SS_ERR_ARG, "ss_mass_log_count: null argument");
+  *count = g->log_count;
+  return SS_OK;
+}
+
+ss_status ss_set_stream(ss_grid g, void* stream) {
+  if (!g) return fail(SS_ERR_ARG, "ss_set_stream: null grid");
+  g->stream = (hipStream_t)stream;
+  return SS_OK;
+}
+
+ss_status ss_destroy_grid(ss_grid g) {
+  delete g;
+  return SS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+// Register-resident Stockham FFT for gfx950, exchanged through LDS.
+//
+// One line of N (power of two, 8..4096) complex points is owned by S = N/8
+// consecutive threads; thread t holds the 8 points x[t + e*S], e = 0..7.
+// Every stage of the Stockham autosort reads that same set of positions,
+// so the first stage can take its operands straight from global memory
+// (coalesced) and, because the last stage writes each output back to the
+// thread that holds its position, the result is again x[t + e*S] in
+// natural order, in registers.  A forward transform followed by a
+// pointwise operation and an inverse transform therefore touches LDS only
+// between inner stages.
+//
+// Stage plan: one radix-2/4 stage first (no twiddles) when log2 N is not a
+// multiple of 3, then radix-8 stages.  The twiddles exp(-+2 pi i r k/(Ns 8))
+// of a radix-8 butterfly are powers of one base value per thread and stage
+// (computed once with sincospi); the powers are formed by multiplication.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { typedef float2 type; };
+template <> struct cplx_of<double> { typedef double2 type; };
+template <typename T> using C = typename cplx_of<T>::type;
+
+template <typename T>
+__device__ __forceinline__ C<T> mk(T x, T y) { C<T> r; r.x = x; r.y = y; return r; }
+template <typename T>
+__device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ C<T> cscale(C<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+template <typename T>
+__device__ __forceinline__ C<T> cconj(C<T> a) { return mk<T>(a.x, -a.y); }
+
+// (a.x + i a.y) * (DIR * i)
+template <typename T, int DIR>
+__device__ __forceinline__ C<T> mul_diri(C<T> a) {
+  return DIR > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+__device__ __forceinline__ double2 cis_pi(double x) {
+  double s, c;
+  sincospi(x, &s, &c);
+  return make_double2(c, s);
+}
+__device__ __forceinline__ float2 cis_pi(float x) {
+  float s, c;
+  sincospif(x, &s, &c);
+  return make_float2(c, s);
+}
+
+// LDS index padding: one spare slot every 8 (16-byte elements) or 16
+// (8-byte elements) points keeps the strided Stockham writes spread over
+// the banks.
+template <typename T>
+__device__ __forceinline__ int pidx(int i) {
+  return sizeof(T) == 8 ? i + (i >> 3) : i + (i >> 4);
+}
+template <typename T>
+__host__ __device__ constexpr int padded_len(int n) {
+  return sizeof(T) == 8 ? n + (n >> 3) + 1 : n + (n >> 4) + 1;
+}
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+template <int N>
+struct Plan {
+  static constexpr int LOG = ilog2c(N);
+  static constexpr int FIRST = (LOG % 3 == 0) ? 8 : ((LOG % 3 == 1) ? 2 : 4);
+  static constexpr int NST = (LOG % 3 == 0) ? LOG / 3 : LOG / 3 + 1;
+};
+
+// ---- small DFTs, in place, sign DIR (-1 forward, +1 inverse) ------------
+template <typename T, int DIR>
+__device__ __forceinline__ void dft2(C<T>* v) {
+  C<T> a = v[0];
+  v[0] = cadd<T>(a, v[1]);
+  v[1] = csub<T>(a, v[1]);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft4(C<T>& x0, C<T>& x1, C<T>& x2, C<T>& x3) {
+  C<T> t0 = cadd<T>(x0, x2), t1 = csub<T>(x0, x2);
+  C<T> t2 = cadd<T>(x1, x3), t3 = mul_diri<T, DIR>(csub<T>(x1, x3));
+  x0 = cadd<T>(t0, t2);
+  x2 = csub<T>(t0, t2);
+  x1 = cadd<T>(t1, t3);
+  x3 = csub<T>(t1, t3);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft4v(C<T>* v) { dft4<T, DIR>(v[0], v[1], v[2], v[3]); }
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft8(C<T>* v) {
+  // even/odd split: E = DFT4(v0,v2,v4,v6), O = DFT4(v1,v3,v5,v7)
+  C<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<T, DIR>(e0, e1, e2, e3);
+  dft4<T, DIR>(o0, o1, o2, o3);
+  const T r = (T)0.70710678118654752440084436210484903928;
+  // o1 *= w8, o2 *= w8^2, o3 *= w8^3 with w8 = exp(DIR 2 pi i / 8)
+  C<T> p1 = mk<T>(r * (o1.x - (T)DIR * o1.y), r * (o1.y + (T)DIR * o1.x));
+  C<T> p2 = mul_diri<T, DIR>(o2);
+  C<T> p3 = mk<T>(r * (-o3.x - (T)DIR * o3.y), r * ((T)DIR * o3.x - o3.y));
+  v[0] = cadd<T>(e0, o0);
+  v[4] = csub<T>(e0, o0);
+  v[1] = cadd<T>(e1, p1);
+  v[5] = csub<T>(e1, p1);
+  v[2] = cadd<T>(e2, p2);
+  v[6] = csub<T>(e2, p2);
+  v[3] = cadd<T>(e3, p3);
+  v[7] = csub<T>(e3, p3);
+}
+
+template <typename T, int DIR, int R>
+__device__ __forceinline__ void dftR(C<T>* v) {
+  if constexpr (R == 2) dft2<T, DIR>(v);
+  else if constexpr (R == 4) dft4v<T, DIR>(v);
+  else dft8<T, DIR>(v);
+}
+
+// Base twiddles of one thread: for every radix-8 stage after the first,
+// w = exp(-2 pi i k / (Ns 8)) with k = t mod Ns (forward sign; the inverse
+// uses the conjugate).  Computed once per kernel and reused for every line
+// the thread transforms.
+template <typename T, int N>
+struct Twiddles {
+  static constexpr int NW = Plan<N>::NST > 1 ? Plan<N>::NST - 1 : 1;
+  C<T> w[NW];
+};
+
+template <typename T, int N>
+__device__ __forceinline__ Twiddles<T, N> make_twiddles(int t) {
+  typedef Plan<N> P;
+  Twiddles<T, N> tw;
+#pragma unroll
+  for (int s = 1; s < P::NST; ++s) {
+    int ns = P::FIRST;
+#pragma unroll
+    for (int u = 1; u < s; ++u) ns *= 8;
+    const int k = t & (ns - 1);
+    tw.w[s - 1] = cis_pi((T)(-2 * k) / (T)(ns * 8));
+  }
+  if (P::NST == 1) tw.w[0] = mk<T>((T)1, (T)0);
+  return tw;
+}
+
+// Keeps the compiler from hoisting values derived from x out of the
+// caller's loops (which would hold every twiddle power live at once).
+template <typename T>
+__device__ __forceinline__ C<T> opaque(C<T> x) {
+  asm volatile("" : "+v"(x.x), "+v"(x.y));
+  return x;
+}
+
+// One Stockham stage of radix R over NL lines held by this thread.
+// x[l] is the LDS exchange region of line l (padded indices).  On entry
+// the regions must be free (no thread still reading them).  w1 is the
+// forward base twiddle of this thread for the stage (unused when NS = 1).
+template <typename T, int N, int DIR, int R, int NS, bool LAST, int NL>
+__device__ __forceinline__ void stockham_stage(C<T> (&c)[NL][8], C<T>* const (&x)[NL], int t,
+                                               C<T> w1) {
+  constexpr int S = N / 8;
+  constexpr int Q = 8 / R;
+  static_assert(NS == 1 || Q == 1, "only the first stage may have radix < 8");
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int j = t + q * S;
+    const int k = j & (NS - 1);
+    C<T> w[R];
+    if constexpr (NS > 1) {
+      w[1] = opaque<T>(DIR > 0 ? cconj<T>(w1) : w1);
+#pragma unroll
+      for (int r = 2; r < R; ++r) w[r] = cmul<T>(w[r >> 1], w[r - (r >> 1)]);
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      C<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = c[l][q + r * Q];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul<T>(v[r], w[r]);
+      }
+      dftR<T, DIR, R>(v);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) c[l][q + r * Q] = v[r];
+      } else {
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[l][pidx<T>(base + r * NS)] = v[r];
+      }
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) c[l][e] = x[l][pidx<T>(t + e * S)];
+    }
+    __syncthreads();
+  }
+}
+
+// Unnormalised DFT of NL lines of length N: sign DIR (-1 forward).
+template <typename T, int N, int DIR, int NL>
+__device__ __forceinline__ void fft_lines(C<T> (&c)[NL][8], C<T>* const (&x)[NL], int t,
+                                          const Twiddles<T, N>& tw) {
+  typedef Plan<N> P;
+  static_assert(N >= 8 && N <= 4096 && (N & (N - 1)) == 0, "power of two in [8, 4096]");
+  stockham_stage<T, N, DIR, P::FIRST, 1, P::NST == 1, NL>(c, x, t, tw.w[0]);
+  if constexpr (P::NST >= 2)
+    stockham_stage<T, N, DIR, 8, P::FIRST, P::NST == 2, NL>(c, x, t, tw.w[0]);
+  if constexpr (P::NST >= 3)
+    stockham_stage<T, N, DIR, 8, P::FIRST * 8, P::NST == 3, NL>(c, x, t, tw.w[1]);
+  if constexpr (P::NST >= 4)
+    stockham_stage<T, N, DIR, 8, P::FIRST * 64, P::NST == 4, NL>(c, x, t, tw.w[2]);
+}
+
+}  // namespace ss

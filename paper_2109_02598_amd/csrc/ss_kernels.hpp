@@ -1,0 +1,524 @@
+// Kernels of one semi-implicit Fourier spectral step (gfx950).
+//
+// Spectral state layout (both 2D and 3D): the field is kept transformed
+// along x (and along y in 3D) and scaled, in a transposed complex array
+//     T[kx][s],  kx = 0 .. Nx/2-1,  s = y*Nz + z  (Nz = 1 in 2D)
+// so that lines along the last axis (y in 2D, z in 3D) are contiguous.
+// Because the field is real, its kx = 0 and kx = Nx/2 planes are real in
+// the remaining coordinates; they are stored together as one complex plane
+// kx = 0 holding  S(0, .) + i S(Nx/2, .).  Every array is therefore exactly
+// Nx*Ny*Nz reals.
+//
+// Scaling: 2D state T = FFT_x(psi)/Nx;  3D state = FFT_xy(psi)/(Nx Ny).
+// The x pass inverts with an unnormalised transform, so psi comes out
+// directly; the k-space pass folds 1/N_last into A and 1/N into B N.
+//
+// Kernels
+//   xpass  rows along x, two real rows per complex FFT; modes
+//          FWD  (real rows -> spectral, set-up),
+//          INV  (spectral -> real rows, read-out),
+//          STEP (spectral -> psi -> nonlinear f -> spectral of f).
+//   ypass  3D only: complex FFT along y on chunks of consecutive z.
+//   kpass  lines along the last axis: forward FFT of the state and of the
+//          nonlinear term, ETD1 update  U = a T^ + b G^  (Sec. 2.4.2,
+//          Eqs. 3-4 and 8), inverse FFT, in place; the packed kx = 0
+//          lines are split into their two Hermitian parts with the mirror
+//          mode (-k) before the update.
+#pragma once
+
+#include "ss_fft.hpp"
+
+namespace ss {
+
+enum { XMODE_FWD = 0, XMODE_INV = 1, XMODE_STEP = 2 };
+enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2 };
+
+constexpr int LDS_BUDGET = 160 * 1024;
+
+// ---------------------------------------------------------------------------
+// x pass
+// ---------------------------------------------------------------------------
+struct XArgs {
+  const void* spec_in[2];   // per field, T[kx][s] (INV, STEP)
+  void* spec_out[2];        // per field, (FWD, STEP); may alias spec_in
+  const void* real_in;      // FWD: real field (z, y, x)
+  void* real_out;           // INV: real field (z, y, x)
+  int64_t rows;             // Ny*Nz = leading dimension of T
+  int nz, ny;               // s = y*nz + z ; real row offset (z*ny + y)*Nx
+  int rows_per_block;       // R at run time (even, divides rows)
+  int xcd_remap;            // 1: spread consecutive chunks over one XCD
+  double scale;             // multiplies the forward output (1/Nx for FWD)
+  double p[5];              // nonlinear coefficients
+};
+
+template <typename T, int NX>
+struct XCfg {
+  static constexpr int S = NX / 8;                  // threads per line
+  static constexpr int H = NX / 2;                  // stored kx count
+  static constexpr int ESZ = (int)sizeof(C<T>);
+  static constexpr int REG0 = padded_len<T>(NX);
+  // region stride: NF*REG = 2 (mod 8 or 16) keeps the staged rows on
+  // distinct banks; HB = H + 1 is the offset of the second row of a pair
+  static constexpr int MOD = ESZ == 16 ? 8 : 16;
+  static constexpr int reg_for(int nf) {
+    int r = REG0;
+    while (((nf * r) % MOD) != 2 % MOD) ++r;
+    return r;
+  }
+  static constexpr int HB = H + 1;
+  // rows per block: enough for 128 contiguous bytes and >= 256 threads,
+  // bounded by LDS
+  static constexpr int rmax(int nf) {
+    int r = 2;
+    const int want_bytes = 128 / ESZ;
+    const int want_threads = 2 * ((256 / S) > 1 ? (256 / S) : 1);
+    const int want = want_bytes > want_threads ? want_bytes : want_threads;
+    while (r * 2 <= want && (r * 2 / 2) * nf * reg_for(nf) * ESZ <= LDS_BUDGET && r * 2 <= 64) r *= 2;
+    return r;
+  }
+};
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap) {
+  // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+  // contiguous range of chunks so neighbours share its L2
+  if (!remap || (nb & 7)) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename T, int NLM>
+__device__ __forceinline__ void nonlinear(C<T>* c0, C<T>* c1, T p0, T p1, T p2) {
+  if constexpr (NLM == NLIN_POLY) {
+    // f = a2 psi^2 + a3 psi^3 on both packed rows
+    const T a2 = p0, a3 = p1;
+    T x = c0->x, y = c0->y;
+    c0->x = x * x * (a2 + a3 * x);
+    c0->y = y * y * (a2 + a3 * y);
+  } else if constexpr (NLM == NLIN_GS) {
+    // g_u = F - u v^2, g_v = u v^2
+    const T F = p0;
+    T ux = c0->x, uy = c0->y, vx = c1->x, vy = c1->y;
+    T wx = ux * vx * vx, wy = uy * vy * vy;
+    c0->x = F - wx; c0->y = F - wy;
+    c1->x = wx;     c1->y = wy;
+  } else {
+    // model C: f_psi = -c2 psi^3 + 2 c5 psi m ; f_m = -c4 m^3 + c5 psi^2
+    const T c2 = p0, c4 = p1, c5 = p2;
+    T px = c0->x, py = c0->y, mx = c1->x, my = c1->y;
+    c0->x = px * (-c2 * px * px + (T)2 * c5 * mx);
+    c0->y = py * (-c2 * py * py + (T)2 * c5 * my);
+    c1->x = mx * mx * (-c4 * mx) + c5 * px * px;
+    c1->y = my * my * (-c4 * my) + c5 * py * py;
+  }
+}
+
+// threads per block of the x pass: two FP64 fields need the registers of
+// 512-thread blocks
+template <typename T, int NF>
+struct XThreads {
+  static constexpr int value = (NF == 2 && sizeof(T) == 8) ? 512 : 1024;
+};
+
+template <typename T, int NX, int NF, int MODE, int NLM>
+__global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a) {
+  typedef XCfg<T, NX> K;
+  constexpr int S = K::S, H = K::H, HB = K::HB;
+  constexpr int REG = K::reg_for(NF);
+  constexpr int RMAX = K::rmax(NF);
+  constexpr int PMAX = RMAX / 2;
+  __shared__ C<T> lds[PMAX * NF * REG];
+
+  const int R = a.rows_per_block;
+  const int P = R >> 1;
+  const int G = (int)blockDim.x / S;         // thread groups (lines in flight)
+  const int tid = threadIdx.x;
+  const int g = tid / S, t = tid - g * S;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int64_t s0 = blk * R;
+  const int64_t rows = a.rows;
+  const Twiddles<T, NX> tw = make_twiddles<T, NX>(t);
+
+  if constexpr (MODE != XMODE_FWD) {
+    // staged load: element (f, kx, r) -> region(r/2, f) + (r&1)*HB + kx
+    const int total = NF * H * R;
+    for (int i = tid; i < total; i += blockDim.x) {
+      const int r = i % R;
+      const int kx = (i / R) % H;
+      const int f = i / (R * H);
+      const C<T>* src = (const C<T>*)(f == 0 ? a.spec_in[0] : a.spec_in[1]);
+      lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx] = src[(int64_t)kx * rows + s0 + r];
+    }
+    __syncthreads();
+  }
+
+  const int iters = P / G;
+  for (int it = 0; it < iters; ++it) {
+    const int pr = it * G + g;                 // row pair handled by this group
+    C<T>* x[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) x[f] = lds + (pr * NF + f) * REG;
+    C<T> c[NF][8];
+    const int64_t sa = s0 + 2 * pr;            // spectral row of the pair's first row
+
+    if constexpr (MODE == XMODE_FWD) {
+      const T* rin = (const T*)a.real_in;
+      const int64_t za = sa % a.nz, ya = sa / a.nz;
+      const int64_t zb = (sa + 1) % a.nz, yb = (sa + 1) / a.nz;
+      const T* ra = rin + (za * a.ny + ya) * NX;
+      const T* rb = rin + (zb * a.ny + yb) * NX;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) c[0][e] = mk<T>(ra[t + e * S], rb[t + e * S]);
+    } else {
+      // Z[k] = X_a[k] + i X_b[k] over the full length from the half spectra
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = t + e * S;
+          C<T> z;
+          if (k == 0) {
+            C<T> ta = x[f][0], tb = x[f][HB];
+            z = mk<T>(ta.x, tb.x);
+          } else if (k == H) {
+            C<T> ta = x[f][0], tb = x[f][HB];
+            z = mk<T>(ta.y, tb.y);
+          } else if (k < H) {
+            C<T> ta = x[f][k], tb = x[f][HB + k];
+            z = mk<T>(ta.x - tb.y, ta.y + tb.x);
+          } else {
+            C<T> ta = x[f][NX - k], tb = x[f][HB + NX - k];
+            z = mk<T>(ta.x + tb.y, tb.x - ta.y);
+          }
+          c[f][e] = z;
+        }
+      }
+      __syncthreads();
+      fft_lines<T, NX, +1, NF>(c, x, t, tw);
+      if constexpr (MODE == XMODE_INV) {
+        T* rout = (T*)a.real_out;
+        const int64_t za = sa % a.nz, ya = sa / a.nz;
+        const int64_t zb = (sa + 1) % a.nz, yb = (sa + 1) / a.nz;
+        T* ra = rout + (za * a.ny + ya) * NX;
+        T* rb = rout + (zb * a.ny + yb) * NX;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ra[t + e * S] = c[0][e].x;
+          rb[t + e * S] = c[0][e].y;
+        }
+        continue;
+      } else {
+        const T p0 = (T)a.p[0], p1 = (T)a.p[1], p2 = (T)a.p[2];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if constexpr (NF == 1) nonlinear<T, NLM>(&c[0][e], &c[0][e], p0, p1, p2);
+          else nonlinear<T, NLM>(&c[0][e], &c[NF - 1][e], p0, p1, p2);
+        }
+      }
+    }
+    if constexpr (MODE != XMODE_INV) {
+      fft_lines<T, NX, -1, NF>(c, x, t, tw);
+      // natural-order spectrum to LDS, then split the two rows
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[f][pidx<T>(t + e * S)] = c[f][e];
+      }
+      __syncthreads();
+      const T sc = (T)a.scale;
+      const T half = (T)0.5 * sc;
+      C<T> fa[NF][4], fb[NF][4];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = t + e * S;               // 0 .. H-1
+          C<T> w = x[f][pidx<T>(k)];
+          if (k == 0) {
+            C<T> wn = x[f][pidx<T>(H)];
+            fa[f][e] = mk<T>(w.x * sc, wn.x * sc);
+            fb[f][e] = mk<T>(w.y * sc, wn.y * sc);
+          } else {
+            C<T> wm = x[f][pidx<T>(NX - k)];
+            fa[f][e] = mk<T>((w.x + wm.x) * half, (w.y - wm.y) * half);
+            fb[f][e] = mk<T>((w.y + wm.y) * half, (wm.x - w.x) * half);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = t + e * S;
+          x[f][k] = fa[f][e];
+          x[f][HB + k] = fb[f][e];
+        }
+      }
+    }
+  }
+
+  if constexpr (MODE != XMODE_INV) {
+    __syncthreads();
+    const int total = NF * H * R;
+    for (int i = tid; i < total; i += blockDim.x) {
+      const int r = i % R;
+      const int kx = (i / R) % H;
+      const int f = i / (R * H);
+      C<T>* dst = (C<T>*)(f == 0 ? a.spec_out[0] : a.spec_out[1]);
+      dst[(int64_t)kx * rows + s0 + r] = lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y pass (3D): complex FFT along y of T[kx][y][z] on chunks of R
+// consecutive z; block = (kx, z chunk).  In place is allowed.
+// ---------------------------------------------------------------------------
+struct YArgs {
+  const void* in;
+  void* out;
+  int ny, nz;
+  int lines_per_block;     // R (divides nz)
+  double scale;
+};
+
+template <typename T, int NY>
+struct YCfg {
+  static constexpr int S = NY / 8;
+  static constexpr int ESZ = (int)sizeof(C<T>);
+  static constexpr int MOD = ESZ == 16 ? 8 : 16;
+  static constexpr int REG = [] {
+    int r = padded_len<T>(NY);
+    while ((r % MOD) != 1) ++r;
+    return r;
+  }();
+  static constexpr int rmax() {
+    int r = 1;
+    const int want_bytes = 128 / ESZ;
+    const int want_threads = (256 / S) > 1 ? (256 / S) : 1;
+    const int want = want_bytes > want_threads ? want_bytes : want_threads;
+    while (r * 2 <= want && r * 2 * REG * ESZ <= LDS_BUDGET && r * 2 <= 64) r *= 2;
+    return r;
+  }
+};
+
+template <typename T, int NY, int DIR>
+__global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
+  typedef YCfg<T, NY> K;
+  constexpr int S = K::S, REG = K::REG, RMAX = K::rmax();
+  __shared__ C<T> lds[RMAX * REG];
+  const int R = a.lines_per_block;
+  const int G = (int)blockDim.x / S;
+  const int tid = threadIdx.x;
+  const int g = tid / S, t = tid - g * S;
+  const int64_t chunks_per_kx = a.nz / R;
+  const int64_t kx = blockIdx.x / chunks_per_kx;
+  const int64_t z0 = (blockIdx.x - kx * chunks_per_kx) * R;
+  const int64_t base = kx * (int64_t)a.ny * a.nz + z0;
+  const C<T>* src = (const C<T>*)a.in;
+  C<T>* dst = (C<T>*)a.out;
+  const Twiddles<T, NY> tw = make_twiddles<T, NY>(t);
+
+  for (int i = tid; i < NY * R; i += blockDim.x) {
+    const int r = i % R, y = i / R;
+    lds[r * REG + y] = src[base + (int64_t)y * a.nz + r];
+  }
+  __syncthreads();
+  const T sc = (T)a.scale;
+  const int iters = R / G;
+  for (int it = 0; it < iters; ++it) {
+    const int ln = it * G + g;
+    C<T>* x[1] = {lds + ln * REG};
+    C<T> c[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) c[0][e] = x[0][t + e * S];
+    __syncthreads();
+    fft_lines<T, NY, DIR, 1>(c, x, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[0][t + e * S] = cscale<T>(c[0][e], sc);
+  }
+  __syncthreads();
+  for (int i = tid; i < NY * R; i += blockDim.x) {
+    const int r = i % R, y = i / R;
+    dst[base + (int64_t)y * a.nz + r] = lds[r * REG + y];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k-space pass: lines along the last axis (length NL), ETD1 update.
+// ---------------------------------------------------------------------------
+struct KField {
+  void* state;              // T, updated in place
+  const void* nonlin;       // G
+  double l[4];              // L(k^2) = l0 + l1 k^2 + l2 k^4 + l3 k^6
+  double n[2];              // N(k^2) = n0 + n1 k^2
+};
+
+struct KArgs {
+  KField fld[2];
+  int nlines;               // Nx/2 * J  (J = Ny in 3D, 1 in 2D)
+  int J;                    // lines per kx plane
+  int lines_per_block;
+  int nx;                   // grid size along x (for the Nyquist plane)
+  double sx, sy, sz;        // 2 pi / (N_axis dx_axis)
+  double dt;
+  double a_scale, b_scale;  // 1/N_last and 1/N
+  double* mass_log;         // may be null
+  int64_t log_index;        // row of mass_log for this step (per field stride nf)
+  int64_t log_capacity;
+  int nf;
+  int three_d;
+};
+
+template <typename T>
+__device__ __forceinline__ void etd1_coeffs(const KField& f, double k2, double dt, double as,
+                                            double bs, T& ao, T& bo) {
+  if constexpr (sizeof(T) == 8) {
+    const double L = f.l[0] + k2 * (f.l[1] + k2 * (f.l[2] + k2 * f.l[3]));
+    const double z = L * dt;
+    // one expm1 serves both factors: A = 1 + expm1(z), B = dt expm1(z)/z
+    // (B = dt where z = 0, the limit of Eq. 4)
+    const double em = expm1(z);
+    const double phi = (z != 0.0) ? em / z : 1.0;
+    ao = (1.0 + em) * as;
+    bo = dt * phi * (f.n[0] + f.n[1] * k2) * bs;
+  } else {
+    const float k2f = (float)k2;
+    const float L = (float)f.l[0] + k2f * ((float)f.l[1] + k2f * ((float)f.l[2] + k2f * (float)f.l[3]));
+    const float z = L * (float)dt;
+    const float A = expf(z);
+    const float phi = (z != 0.0f) ? expm1f(z) / z : 1.0f;
+    ao = A * (float)as;
+    bo = (float)dt * phi * ((float)f.n[0] + (float)f.n[1] * k2f) * (float)bs;
+  }
+}
+
+template <typename T, int NL>
+struct KCfg {
+  static constexpr int S = NL / 8;
+  static constexpr int LPW = (256 / S) > 1 ? (256 / S) : 1;   // lines per block
+  static constexpr int REG = padded_len<T>(NL);
+};
+
+template <typename T, int NL>
+__global__ void __launch_bounds__(512) kpass_kernel(KArgs a) {
+  typedef KCfg<T, NL> K;
+  constexpr int S = K::S, LPW = K::LPW, REG = K::REG;
+  __shared__ C<T> lds[LPW * 2 * REG];
+  const int tid = threadIdx.x;
+  const int ls = tid / S, t = tid - ls * S;
+  const KField F = blockIdx.y == 0 ? a.fld[0] : a.fld[1];
+  const int line0 = blockIdx.x * a.lines_per_block;
+  const int slot = line0 + ls;                     // global line slot
+  const bool packed_block = line0 < a.J;     // block holds kx = 0 lines
+  // plane-0 slots are ordered so that each line sits next to its mirror
+  int kxi, kyi;
+  if (slot < a.J) {
+    kxi = 0;
+    if (!a.three_d) kyi = 0;
+    else {
+      const int pi = slot >> 1, mem = slot & 1;
+      kyi = (pi == 0) ? (mem ? a.J / 2 : 0) : (mem ? a.J - pi : pi);
+    }
+  } else {
+    kxi = slot / a.J;
+    kyi = slot - kxi * a.J;
+  }
+  const int64_t lbase = ((int64_t)kxi * a.J + kyi) * NL;
+  C<T>* st = (C<T>*)F.state + lbase;
+  const C<T>* gn = (const C<T>*)F.nonlin + lbase;
+
+  C<T> c[2][8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    c[0][e] = st[t + e * S];
+    c[1][e] = gn[t + e * S];
+  }
+  C<T>* x[2] = {lds + (ls * 2) * REG, lds + (ls * 2 + 1) * REG};
+  const Twiddles<T, NL> tw = make_twiddles<T, NL>(t);
+  fft_lines<T, NL, -1, 2>(c, x, t, tw);
+
+  // wavenumbers: k_last from the position, k_mid from kyi (3D), k_x from kxi
+  const double kxv = (double)kxi * a.sx;
+  double kmid2 = 0.0;
+  if (a.three_d) {
+    const int m = kyi <= a.J / 2 ? kyi : kyi - a.J;
+    kmid2 = ((double)m * a.sy) * ((double)m * a.sy);
+  }
+  const double klast_s = a.three_d ? a.sz : a.sy;
+
+  if (packed_block) {
+    // the kx = 0 lines hold S(0) + i S(Nx/2): split with the mirror mode
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      x[0][pidx<T>(t + e * S)] = c[0][e];
+      x[1][pidx<T>(t + e * S)] = c[1][e];
+    }
+    __syncthreads();
+    if (slot < a.J) {
+      int mslot_ls = ls;
+      if (a.three_d && (slot >> 1) != 0) mslot_ls = ls ^ 1;
+      C<T>* xm0 = lds + (mslot_ls * 2) * REG;
+      C<T>* xm1 = lds + (mslot_ls * 2 + 1) * REG;
+      const double kny = (double)(a.nx / 2) * a.sx;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int p = t + e * S;
+        const int pm = (NL - p) & (NL - 1);
+        const int m = p <= NL / 2 ? p : p - NL;
+        const double kl = (double)m * klast_s;
+        const double k2_0 = kmid2 + kl * kl;
+        const double k2_n = k2_0 + kny * kny;
+        T a0, b0, an, bn;
+        etd1_coeffs<T>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
+        etd1_coeffs<T>(F, k2_n, a.dt, a.a_scale, a.b_scale, an, bn);
+        const C<T> cm = cconj<T>(xm0[pidx<T>(pm)]);
+        const C<T> dm = cconj<T>(xm1[pidx<T>(pm)]);
+        const T ap = (T)0.5 * (a0 + an), am = (T)0.5 * (a0 - an);
+        const T bp = (T)0.5 * (b0 + bn), bmn = (T)0.5 * (b0 - bn);
+        C<T> u;
+        u.x = ap * c[0][e].x + am * cm.x + bp * c[1][e].x + bmn * dm.x;
+        u.y = ap * c[0][e].y + am * cm.y + bp * c[1][e].y + bmn * dm.y;
+        c[0][e] = u;
+      }
+      if (a.mass_log && kyi == 0 && t == 0 && a.log_index < a.log_capacity)
+        a.mass_log[a.log_index * a.nf + blockIdx.y] = (double)c[0][0].x;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int p = t + e * S;
+        const int m = p <= NL / 2 ? p : p - NL;
+        const double kl = (double)m * klast_s;
+        const double k2 = kxv * kxv + kmid2 + kl * kl;
+        T av, bv;
+        etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
+        c[0][e] = mk<T>(av * c[0][e].x + bv * c[1][e].x, av * c[0][e].y + bv * c[1][e].y);
+      }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __builtin_amdgcn_sched_barrier(0);
+      const int p = t + e * S;
+      const int m = p <= NL / 2 ? p : p - NL;
+      const double kl = (double)m * klast_s;
+      const double k2 = kxv * kxv + kmid2 + kl * kl;
+      T av, bv;
+      etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
+      c[0][e] = mk<T>(av * c[0][e].x + bv * c[1][e].x, av * c[0][e].y + bv * c[1][e].y);
+    }
+  }
+
+  C<T> c1[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) c1[0][e] = c[0][e];
+  C<T>* x1[1] = {x[0]};
+  fft_lines<T, NL, +1, 1>(c1, x1, t, tw);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) st[t + e * S] = c1[0][e];
+}
+
+}  // namespace ss

@@ -1,0 +1,265 @@
+"""Thin Python binding of libspecstep.so (the C ABI in include/specstep.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels of the library.  PyTorch supplies device memory (the workspace
+and field tensors) and the stream.  If the library is not built this
+module raises ImportError-derived errors on first use; there is no
+fallback path.
+
+The functions ``ss_*`` mirror the C entry points one to one; ``Grid`` is
+a convenience owner of a handle and its workspace tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspecstep.so")
+
+SS_OK, SS_ERR_ARG, SS_ERR_UNSUPPORTED, SS_ERR_STATE, SS_ERR_DEVICE, SS_ERR_NONFINITE = range(6)
+SS_F32, SS_F64 = 4, 8
+MODELS = {"allen_cahn": 1, "cahn_hilliard": 2, "pfc": 3, "gray_scott": 4, "model_c": 5}
+NFIELDS = {1: 1, 2: 1, 3: 1, 4: 2, 5: 2}
+
+_lib = None
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+class SpecStepError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("specstep error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libspecstep.so (importing torch first so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing("libspecstep.so is not built (%s); run "
+                             "python -m paper_2109_02598_amd.build" % LIB_PATH)
+    import torch  # noqa: F401  (loads the HIP runtime the library will bind to)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    sig = {
+        "ss_create_grid": [cint, ctypes.POINTER(i64), ctypes.POINTER(dbl), cint, vp, ctypes.POINTER(vp)],
+        "ss_set_model": [vp, cint, ctypes.POINTER(dbl), cint, dbl],
+        "ss_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "ss_bind_workspace": [vp, vp, ctypes.c_size_t],
+        "ss_set_field": [vp, cint, vp, cint],
+        "ss_get_field": [vp, cint, vp, cint],
+        "ss_step_n": [vp, i64],
+        "ss_step_n_profiled": [vp, i64, ctypes.POINTER(dbl), ctypes.POINTER(i64), cint],
+        "ss_bind_mass_log": [vp, vp, i64],
+        "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
+        "ss_set_stream": [vp, vp],
+        "ss_destroy_grid": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = cint
+    L.ss_last_error.restype = ctypes.c_char_p
+    L.ss_last_error.argtypes = []
+    L.ss_version.restype = ctypes.c_char_p
+    L.ss_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != SS_OK:
+        raise SpecStepError(st, lib().ss_last_error().decode())
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor / numpy array / int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+# ---- one-to-one wrappers of the C entry points ---------------------------
+
+def ss_create_grid(n, dx, dtype, stream=None):
+    n = list(n)
+    h = ctypes.c_void_p()
+    _check(lib().ss_create_grid(len(n), (ctypes.c_int64 * len(n))(*n),
+                                (ctypes.c_double * len(n))(*map(float, dx)),
+                                int(dtype), stream, ctypes.byref(h)))
+    return h.value
+
+
+def ss_set_model(h, model, coef, dt):
+    coef = [float(c) for c in coef]
+    _check(lib().ss_set_model(h, int(model), (ctypes.c_double * len(coef))(*coef),
+                              len(coef), float(dt)))
+
+
+def ss_workspace_size(h):
+    b = ctypes.c_size_t()
+    _check(lib().ss_workspace_size(h, ctypes.byref(b)))
+    return b.value
+
+
+def ss_bind_workspace(h, ptr, nbytes):
+    _check(lib().ss_bind_workspace(h, ptr, nbytes))
+
+
+def ss_set_field(h, field, src_ptr, on_device):
+    _check(lib().ss_set_field(h, int(field), src_ptr, int(bool(on_device))))
+
+
+def ss_get_field(h, field, dst_ptr, on_device):
+    _check(lib().ss_get_field(h, int(field), dst_ptr, int(bool(on_device))))
+
+
+def ss_step_n(h, nsteps):
+    _check(lib().ss_step_n(h, int(nsteps)))
+
+
+SS_NPASS = 4
+PASS_NAMES = ("xpass", "kpass", "ypass_inv", "ypass_fwd")
+
+
+def ss_step_n_profiled(h, nsteps):
+    """Run nsteps with per-launch HIP events; returns {pass: (ms_total, launches)}."""
+    ms = (ctypes.c_double * SS_NPASS)()
+    cnt = (ctypes.c_int64 * SS_NPASS)()
+    _check(lib().ss_step_n_profiled(h, int(nsteps), ms, cnt, SS_NPASS))
+    return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(SS_NPASS) if cnt[i]}
+
+
+def ss_bind_mass_log(h, ptr, capacity):
+    _check(lib().ss_bind_mass_log(h, ptr, int(capacity)))
+
+
+def ss_mass_log_count(h):
+    c = ctypes.c_int64()
+    _check(lib().ss_mass_log_count(h, ctypes.byref(c)))
+    return c.value
+
+
+def ss_set_stream(h, stream):
+    _check(lib().ss_set_stream(h, stream))
+
+
+def ss_destroy_grid(h):
+    _check(lib().ss_destroy_grid(h))
+
+
+def ss_last_error():
+    return lib().ss_last_error().decode()
+
+
+def ss_version():
+    return lib().ss_version().decode()
+
+
+# ---- convenience owner ----------------------------------------------------
+
+class Grid:
+    """A simulation grid on one GPU: handle + torch-owned workspace.
+
+    ``n`` is (nx, ny[, nz]); fields are torch tensors shaped (.., ny, nx).
+    """
+
+    def __init__(self, n, dx, dtype="f64", model="allen_cahn", coef=(1, 1, 1, 1),
+                 dt=0.1, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.n = tuple(int(v) for v in n)
+        self.dx = tuple(float(v) for v in dx)
+        self.device = torch.device(device)
+        self.tdtype = torch.float64 if dtype in ("f64", "float64", torch.float64) else torch.float32
+        self.ss_dtype = SS_F64 if self.tdtype == torch.float64 else SS_F32
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.stream = stream
+        self.h = ss_create_grid(self.n, self.dx, self.ss_dtype, stream)
+        self.model_id = MODELS[model] if isinstance(model, str) else int(model)
+        self.nfields = NFIELDS[self.model_id]
+        ss_set_model(self.h, self.model_id, coef, dt)
+        nbytes = ss_workspace_size(self.h)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ss_bind_workspace(self.h, self.workspace.data_ptr(), nbytes)
+        self.mass_buf = None
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n))
+
+    def set_model(self, model, coef, dt):
+        mid = MODELS[model] if isinstance(model, str) else int(model)
+        ss_set_model(self.h, mid, coef, dt)
+        if mid != self.model_id:
+            self.model_id = mid
+            self.nfields = NFIELDS[mid]
+            nbytes = ss_workspace_size(self.h)
+            self.workspace = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            ss_bind_workspace(self.h, self.workspace.data_ptr(), nbytes)
+
+    def set_field(self, field, data):
+        """data: numpy array (host path) or CUDA tensor (device path)."""
+        torch = self.torch
+        if isinstance(data, np.ndarray):
+            arr = np.ascontiguousarray(data, dtype=np.float64 if self.tdtype == torch.float64 else np.float32)
+            if arr.shape != self.shape:
+                raise ValueError("field shape %s != grid shape %s" % (arr.shape, self.shape))
+            ss_set_field(self.h, field, arr.ctypes.data, False)
+        else:
+            t = data.to(device=self.device, dtype=self.tdtype).contiguous()
+            if tuple(t.shape) != self.shape:
+                raise ValueError("field shape %s != grid shape %s" % (tuple(t.shape), self.shape))
+            ss_set_field(self.h, field, t.data_ptr(), True)
+            self._keep = t           # alive until the stream has consumed it
+            torch.cuda.current_stream(self.device).synchronize()
+
+    def get_field(self, field, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+        ss_get_field(self.h, field, out.data_ptr(), True)
+        return out
+
+    def get_field_host(self, field):
+        out = np.empty(self.shape, dtype=np.float64 if self.tdtype == self.torch.float64 else np.float32)
+        ss_get_field(self.h, field, out.ctypes.data, False)
+        return out
+
+    def step(self, nsteps):
+        ss_step_n(self.h, nsteps)
+
+    def step_profiled(self, nsteps):
+        return ss_step_n_profiled(self.h, nsteps)
+
+    def enable_mass_log(self, capacity):
+        self.mass_buf = self.torch.zeros(capacity * self.nfields, dtype=self.torch.float64,
+                                         device=self.device)
+        ss_bind_mass_log(self.h, self.mass_buf.data_ptr(), capacity)
+
+    def mass_log(self):
+        cnt = min(ss_mass_log_count(self.h), self.mass_buf.numel() // self.nfields)
+        return self.mass_buf[: cnt * self.nfields].view(cnt, self.nfields).cpu().numpy()
+
+    def close(self):
+        if getattr(self, "h", None):
+            ss_destroy_grid(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,97 @@
+"""C-ABI library: loads, exports every declared symbol, validates arguments.
+
+No compute call is made: everything here runs without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2109_02598_amd import specstep as ss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "specstep.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ss_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ss.LIB_PATH):
+        pytest.skip("library not built")
+    return ss.lib()
+
+
+def test_header_declares_the_abi():
+    syms = declared_symbols()
+    for s in ("ss_create_grid", "ss_set_model", "ss_workspace_size", "ss_bind_workspace",
+              "ss_set_field", "ss_get_field", "ss_step_n", "ss_destroy_grid", "ss_last_error"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(L):
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+
+
+def test_version(L):
+    assert "gfx950" in ss.ss_version()
+
+
+def code_of(fn, *a):
+    with pytest.raises(ss.SpecStepError) as e:
+        fn(*a)
+    return e.value.code
+
+
+def test_create_grid_validation(L):
+    assert code_of(ss.ss_create_grid, (64, 48), (1, 1), ss.SS_F64) == ss.SS_ERR_UNSUPPORTED
+    assert code_of(ss.ss_create_grid, (64, 8192), (1, 1), ss.SS_F64) == ss.SS_ERR_UNSUPPORTED
+    assert code_of(ss.ss_create_grid, (4, 64), (1, 1), ss.SS_F64) == ss.SS_ERR_UNSUPPORTED
+    assert code_of(ss.ss_create_grid, (64, 64, 2048), (1, 1, 1), ss.SS_F32) == ss.SS_ERR_UNSUPPORTED
+    assert code_of(ss.ss_create_grid, (64, 64), (1, 0), ss.SS_F64) == ss.SS_ERR_ARG
+    assert code_of(ss.ss_create_grid, (64, 64), (1, float("nan")), ss.SS_F64) == ss.SS_ERR_ARG
+    assert code_of(ss.ss_create_grid, (64,), (1,), ss.SS_F64) == ss.SS_ERR_ARG
+    assert code_of(ss.ss_create_grid, (64, 64), (1, 1), 5) == ss.SS_ERR_ARG
+    h = ss.ss_create_grid((64, 32), (1, 0.5), ss.SS_F32)
+    ss.ss_destroy_grid(h)
+
+
+def test_model_and_workspace_validation(L):
+    h = ss.ss_create_grid((64, 32), (1, 1), ss.SS_F64)
+    try:
+        assert code_of(ss.ss_workspace_size, h) == ss.SS_ERR_STATE
+        assert code_of(ss.ss_set_model, h, 9, (1, 1, 1, 1), 0.1) == ss.SS_ERR_ARG
+        assert code_of(ss.ss_set_model, h, 1, (1, 1, 1), 0.1) == ss.SS_ERR_ARG
+        assert code_of(ss.ss_set_model, h, 1, (1, 1, 1, float("inf")), 0.1) == ss.SS_ERR_ARG
+        assert code_of(ss.ss_set_model, h, 1, (1, 1, 1, 1), 0.0) == ss.SS_ERR_ARG
+        assert code_of(ss.ss_set_model, h, 5, (1, 1, 1, 1), 0.1) == ss.SS_ERR_ARG
+        ss.ss_set_model(h, 1, (1, 1, 1, 1), 0.5)
+        need = ss.ss_workspace_size(h)
+        assert need >= 3 * 64 * 32 * 8
+        ss.ss_set_model(h, 4, (0.16, 0.08, 0.035, 0.065), 1.0)
+        assert ss.ss_workspace_size(h) >= 5 * 64 * 32 * 8
+        fake = 1 << 40                         # never dereferenced by these calls
+        assert code_of(ss.ss_bind_workspace, h, fake + 8, 1 << 30) == ss.SS_ERR_ARG
+        assert code_of(ss.ss_bind_workspace, h, fake, 16) == ss.SS_ERR_ARG
+        ss.ss_bind_workspace(h, fake, ss.ss_workspace_size(h))
+        # no field set yet: the step and read-out refuse before touching the GPU
+        assert code_of(ss.ss_step_n, h, 1) == ss.SS_ERR_STATE
+        assert code_of(ss.ss_get_field, h, 0, fake, True) == ss.SS_ERR_STATE
+        assert code_of(ss.ss_set_field, h, 2, fake, True) == ss.SS_ERR_ARG
+        assert code_of(ss.ss_step_n, h, -1) == ss.SS_ERR_ARG
+        assert "nsteps" in ss.ss_last_error()
+    finally:
+        ss.ss_destroy_grid(h)
+
+
+def test_null_handles(L):
+    assert L.ss_step_n(None, 1) == ss.SS_ERR_ARG
+    assert L.ss_destroy_grid(None) == ss.SS_OK
+    out = ctypes.c_void_p()
+    assert L.ss_create_grid(2, None, None, 8, None, ctypes.byref(out)) == ss.SS_ERR_ARG

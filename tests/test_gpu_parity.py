@@ -1,0 +1,74 @@
+"""HIP path vs the FP64 oracle, element by element (relative L2 per field).
+
+Bars: 1e-10 (FP64) and 1e-4 (FP32) after 50 steps.  Sizes span several
+blocks of every kernel, non-square grids, the smallest supported axis
+(8) and the largest (4096), 2D and 3D, every model.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests._common import (COEF, TOL, as_input, oracle_run, rel_l2, run_gpu, say,
+                           synth_fields)
+
+pytestmark = pytest.mark.gpu
+
+SHAPES_2D = [(8, 8), (16, 64), (64, 16), (256, 32), (128, 128), (32, 512), (2048, 16),
+             (4096, 8), (8, 1024)]
+SHAPES_3D = [(8, 8, 8), (16, 32, 8), (32, 16, 64), (64, 8, 32)]
+DX = {"pfc": math.pi / 4}
+
+
+def case(model, n, dtype, steps=50, dt=None, seed=11):
+    h = DX.get(model, 1.0)
+    dx = tuple(h * (1.0 + 0.1 * i) for i in range(len(n)))   # anisotropic spacing
+    dt = dt if dt is not None else {"allen_cahn": 0.5, "cahn_hilliard": 0.1, "pfc": 0.5,
+                                    "gray_scott": 1.0, "model_c": 0.05}[model]
+    say("case", model, n, dtype, "steps", steps, "dt", dt)
+    f0 = as_input(synth_fields(model, n, dx, seed), dtype)
+    got, _ = run_gpu(model, n, dx, dt, steps, f0, dtype)
+    want = oracle_run(model, n, dx, dt, steps, f0)
+    for i, (a, b) in enumerate(zip(got, want)):
+        err = rel_l2(a, b)
+        say("  field", i, "rel_l2", "%.3e" % err)
+        assert err <= TOL[dtype], (model, n, dtype, i, err)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", SHAPES_2D)
+@pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc"])
+def test_parity_2d_single_field(model, n, dtype):
+    case(model, n, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(8, 8), (64, 16), (128, 256), (512, 32)])
+@pytest.mark.parametrize("model", ["gray_scott", "model_c"])
+def test_parity_2d_two_fields(model, n, dtype):
+    case(model, n, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", SHAPES_3D)
+@pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc", "gray_scott", "model_c"])
+def test_parity_3d(model, n, dtype):
+    case(model, n, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(8, 8), (64, 32), (2048, 8), (16, 8, 32)])
+def test_set_get_round_trip(n, dtype):
+    import torch
+    from tests._common import need_gpu
+    torch, specstep = need_gpu()
+    f = as_input(synth_fields("allen_cahn", n, (1.0,) * len(n), 5), dtype)[0]
+    g = specstep.Grid(n, (1.0,) * len(n), dtype=dtype, model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1)
+    g.set_field(0, f.astype(np.float32) if dtype == "f32" else f)        # host path
+    back = g.get_field_host(0).astype(np.float64)
+    tol = 1e-14 if dtype == "f64" else 1e-6
+    assert np.max(np.abs(back - f)) <= tol * np.max(np.abs(f))
+    g.step(0)
+    back2 = g.get_field(0).double().cpu().numpy()
+    assert np.array_equal(back, back2)
+    g.close()
