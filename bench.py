@@ -68,10 +68,11 @@ def algorithmic_bytes(pass_name, w, esz):
             "ypass_inv": 2 * n, "ypass_fwd": 2 * n}[pass_name]
 
 
-def run_gpu(w, dtype, steps, warmup, profile_steps):
+def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
     import torch
     from paper_2109_02598_amd import specstep
     g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=w.dt)
+    tiles = g.autotune(5) if autotune else g.tiles()
     for i, f in enumerate(w.fields):
         g.set_field(i, torch.from_numpy(f).to("cuda:0"))
     g.enable_mass_log(warmup + steps + profile_steps)
@@ -91,11 +92,13 @@ def run_gpu(w, dtype, steps, warmup, profile_steps):
     prof = g.step_profiled(profile_steps)
     mass = g.mass_log()
     g.close()
+    prof["tiles"] = tiles
     return ms, wall, prof, mass
 
 
 def roofline(w, dtype, prof, traffic_rec):
     esz = 8 if dtype == "f64" else 4
+    tiles = prof.pop("tiles", None)
     per = {k: (v[0] / v[1]) for k, v in prof.items()}
     dom = max(per, key=per.get)
     algo = algorithmic_bytes(dom, w, esz)
@@ -106,7 +109,8 @@ def roofline(w, dtype, prof, traffic_rec):
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": algo,
-            "mean_launch_us": {k: round(v * 1e3, 2) for k, v in per.items()}}
+            "mean_launch_us": {k: round(v * 1e3, 2) for k, v in per.items()},
+            "tiles": tiles}
 
 
 def load_traffic(workload, dtype):
@@ -144,8 +148,22 @@ def main():
     ap.add_argument("--workload", default="ch2048", choices=sorted(workloads()))
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default tiles")
     ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run 20 plain device copies of MB megabytes (for scaling "
+                         "the memory counters of a profiler) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration * 1024 * 1024
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 20}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(independent simulations shard with no communication; one large grid "
@@ -164,13 +182,15 @@ def main():
     w = workloads()[args.workload]()
     print("bench: workload %s cells %d dtype %s steps %d warmup %d" %
           (w.name, w.cells, args.dtype, args.steps, args.warmup), file=sys.stderr, flush=True)
-    ms, wall, prof, mass = run_gpu(w, args.dtype, args.steps, args.warmup, args.profile_steps)
+    ms, wall, prof, mass = run_gpu(w, args.dtype, args.steps, args.warmup, args.profile_steps,
+                                   not args.no_autotune)
     value = w.cells * args.steps / (ms * 1e-3)
     roof = roofline(w, args.dtype, prof, load_traffic(args.workload, args.dtype))
     other = "f32" if args.dtype == "f64" else "f64"
     print("bench: %s done, %.3f ms/step; running %s" % (args.dtype, ms / args.steps, other),
           file=sys.stderr, flush=True)
-    ms2, _, prof2, _ = run_gpu(w, other, args.steps, args.warmup, args.profile_steps)
+    ms2, _, prof2, _ = run_gpu(w, other, args.steps, args.warmup, args.profile_steps,
+                               not args.no_autotune)
     roof2 = roofline(w, other, prof2, load_traffic(args.workload, other))
     drift = float(abs(mass[-1][0] - mass[0][0])) if len(mass) else None
     out = {

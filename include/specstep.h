@@ -126,6 +126,25 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps);
 ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t* pass_count,
                              int npass);
 
+/* Choose the work decomposition of every kernel of the step for this
+ * grid by timing each valid tiling (rows or lines per workgroup) `reps`
+ * times on the grid's stream and keeping the fastest.  The tilings do not
+ * change any result (each line is transformed by the same code whatever
+ * its workgroup).  The choice is also remembered for later grids of the
+ * same shape, dtype and model field count.  Only the scratch and staging
+ * parts of the workspace are written: the fields are untouched.
+ * Synchronises the stream.  Errors: SS_ERR_STATE (no model/workspace),
+ * SS_ERR_ARG (reps outside [1, 1000]), SS_ERR_DEVICE. */
+ss_status ss_autotune(ss_grid g, int reps);
+
+/* Read / override the tiling: tiles[0] = rows per x-pass workgroup (step),
+ * tiles[1] = lines per k-space workgroup, tiles[2] = lines per y-pass
+ * workgroup (3D), tiles[3] = rows per x-pass workgroup for set/get field.
+ * In ss_set_tiles a 0 entry keeps the default; an invalid entry is
+ * SS_ERR_ARG. */
+ss_status ss_get_tiles(ss_grid g, int tiles[4]);
+ss_status ss_set_tiles(ss_grid g, const int tiles[4]);
+
 /* Bind a device buffer of capacity * nfields doubles for the per-step
  * mass log (spatial mean of each field after each step; conserved for
  * Cahn-Hilliard and PFC, Sec. 3).  Entry (i, f) is at [i*nfields + f]

@@ -13,7 +13,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "../../include/specstep.h"
 #include "ss_dispatch.hpp"
@@ -74,6 +78,9 @@ struct ss_grid_s {
   double* mass_log = nullptr;
   int64_t log_cap = 0;
   int64_t log_count = 0;
+
+  // tiling of each pass (rows or lines per workgroup); 0 = not chosen yet
+  int tile_x_step = 0, tile_x_io = 0, tile_y = 0, tile_k = 0;
 
   int64_t cells() const { return n[0] * n[1] * n[2]; }
   size_t esz() const { return (size_t)dtype; }
@@ -178,9 +185,70 @@ void carve_workspace(ss_grid g) {
   g->staging = b + (size_t)(2 * g->nf) * fb;
 }
 
+// Optional per-launch timing: a pair of events is recorded around each
+// kernel by the launch itself, so the pair brackets kernel time only.
+struct PassTimer {
+  enum { kMaxLaunches = 2048 };
+  hipEvent_t ev[2 * kMaxLaunches];
+  int kind[kMaxLaunches];
+  int used = 0;
+};
+
+enum { PASS_X = 0, PASS_K = 1, PASS_YINV = 2, PASS_YFWD = 3 };
+
+ss::LaunchEvents take_events(PassTimer* pt, int kind) {
+  ss::LaunchEvents e;
+  if (pt && pt->used < PassTimer::kMaxLaunches) {
+    e.start = pt->ev[2 * pt->used];
+    e.stop = pt->ev[2 * pt->used + 1];
+    pt->kind[pt->used] = kind;
+    pt->used++;
+  }
+  return e;
+}
+
+#define SS_TRY(x)                 \
+  do {                            \
+    ss_status st_ = (x);          \
+    if (st_ != SS_OK) return st_; \
+  } while (0)
+
+// Tiles chosen by ss_autotune, shared by every grid of the same shape.
+typedef std::tuple<int, int, int64_t, int64_t, int64_t, int> TileKey;  // ndim, esz, nx, ny, nz, nf
+struct Tiles {
+  int x_step, y, k;
+};
+std::mutex g_tile_mu;
+std::map<TileKey, Tiles> g_tile_cache;
+
+TileKey tile_key(ss_grid g) {
+  return TileKey(g->ndim, (int)(2 * g->esz()), g->n[0], g->n[1], g->n[2], g->nf);
+}
+
+int esz_of(ss_grid g) { return (int)(2 * g->esz()); }
+int64_t nlines_k(ss_grid g) { return (g->n[0] / 2) * (g->ndim == 3 ? g->n[1] : 1); }
+int nlast(ss_grid g) { return (int)(g->ndim == 3 ? g->n[2] : g->n[1]); }
+
+void ensure_tiles(ss_grid g) {
+  const int esz = esz_of(g);
+  if (!g->tile_x_io) g->tile_x_io = ss::x_tile_default(esz, (int)g->n[0], 1, g->n[1] * g->n[2]);
+  if (g->tile_x_step && g->tile_k && (g->ndim == 2 || g->tile_y)) return;
+  Tiles t = {0, 0, 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tile_cache.find(tile_key(g));
+    if (it != g_tile_cache.end()) t = it->second;
+  }
+  if (!g->tile_x_step)
+    g->tile_x_step = t.x_step ? t.x_step : ss::x_tile_default(esz, (int)g->n[0], g->nf, g->n[1] * g->n[2]);
+  if (!g->tile_k) g->tile_k = t.k ? t.k : ss::k_tile_default(esz, nlast(g), nlines_k(g), g->ndim == 3);
+  if (g->ndim == 3 && !g->tile_y) g->tile_y = t.y ? t.y : ss::y_tile_default(esz, (int)g->n[1], g->n[2]);
+}
+
 template <typename T>
 ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void* in1, void* out0,
-                       void* out1, const void* real_in, void* real_out, double scale) {
+                       void* out1, const void* real_in, void* real_out, double scale,
+                       PassTimer* pt = nullptr) {
   ss::XArgs a;
   memset(&a, 0, sizeof(a));
   a.spec_in[0] = in0;
@@ -194,12 +262,16 @@ ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void*
   a.ny = (int)g->n[1];
   a.xcd_remap = 1;
   a.scale = scale;
+  ensure_tiles(g);
+  a.rows_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_step : g->tile_x_io;
   for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
-  return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, g->nlm, a, g->stream), "x pass launch");
+  return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, g->nlm, a, g->stream, take_events(pt, PASS_X)),
+                   "x pass launch");
 }
 
 template <typename T>
-ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double scale) {
+ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double scale,
+                       PassTimer* pt = nullptr) {
   ss::YArgs a;
   memset(&a, 0, sizeof(a));
   a.in = in;
@@ -207,11 +279,15 @@ ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double sca
   a.ny = (int)g->n[1];
   a.nz = (int)g->n[2];
   a.scale = scale;
-  return hip_check(ss::run_ypass<T>((int)g->n[1], dir, a, g->n[0] / 2, g->stream), "y pass launch");
+  ensure_tiles(g);
+  a.lines_per_block = g->tile_y;
+  return hip_check(ss::run_ypass<T>((int)g->n[1], dir, a, g->n[0] / 2, g->stream,
+                                    take_events(pt, dir < 0 ? PASS_YFWD : PASS_YINV)),
+                   "y pass launch");
 }
 
 template <typename T>
-ss_status launch_kpass(ss_grid g) {
+ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr) {
   ss::KArgs a;
   memset(&a, 0, sizeof(a));
   const bool three = g->ndim == 3;
@@ -236,59 +312,24 @@ ss_status launch_kpass(ss_grid g) {
   a.log_capacity = g->log_cap;
   a.nf = g->nf;
   a.three_d = three ? 1 : 0;
+  ensure_tiles(g);
+  a.lines_per_block = g->tile_k;
   const int nl = (int)nlast;
-  return hip_check(ss::run_kpass<T>(nl, a, g->stream), "k-space pass launch");
+  return hip_check(ss::run_kpass<T>(nl, a, g->stream, take_events(pt, PASS_K)), "k-space pass launch");
 }
-
-// Optional per-launch timing: an event is recorded before the first launch
-// and after every launch; the gap between two events is charged to the
-// pass that was launched between them.
-struct PassTimer {
-  enum { kMaxEvents = 4096 };
-  hipEvent_t ev[kMaxEvents];
-  int kind[kMaxEvents];
-  int used = 0;
-  bool ok = true;
-};
-
-enum { PASS_X = 0, PASS_K = 1, PASS_YINV = 2, PASS_YFWD = 3 };
-
-ss_status mark(ss_grid g, PassTimer* pt, int kind) {
-  if (!pt) return SS_OK;
-  if (pt->used >= PassTimer::kMaxEvents) return fail(SS_ERR_ARG, "profiled run too long");
-  ss_status st = hip_check(hipEventRecord(pt->ev[pt->used], g->stream), "hipEventRecord");
-  pt->kind[pt->used] = kind;
-  pt->used++;
-  return st;
-}
-
-#define SS_TRY(x)                 \
-  do {                            \
-    ss_status st_ = (x);          \
-    if (st_ != SS_OK) return st_; \
-  } while (0)
 
 template <typename T>
 ss_status step_once(ss_grid g, PassTimer* pt) {
   if (g->ndim == 2) {
     SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], g->scratch[0],
-                           g->scratch[1], nullptr, nullptr, 1.0));
-    SS_TRY(mark(g, pt, PASS_X));
+                           g->scratch[1], nullptr, nullptr, 1.0, pt));
   } else {
-    for (int f = 0; f < g->nf; ++f) {
-      SS_TRY(launch_ypass<T>(g, +1, g->state[f], g->scratch[f], 1.0));
-      SS_TRY(mark(g, pt, PASS_YINV));
-    }
+    for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, +1, g->state[f], g->scratch[f], 1.0, pt));
     SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->scratch[0], g->scratch[1], g->scratch[0],
-                           g->scratch[1], nullptr, nullptr, 1.0));
-    SS_TRY(mark(g, pt, PASS_X));
-    for (int f = 0; f < g->nf; ++f) {
-      SS_TRY(launch_ypass<T>(g, -1, g->scratch[f], g->scratch[f], 1.0));
-      SS_TRY(mark(g, pt, PASS_YFWD));
-    }
+                           g->scratch[1], nullptr, nullptr, 1.0, pt));
+    for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, -1, g->scratch[f], g->scratch[f], 1.0, pt));
   }
-  SS_TRY(launch_kpass<T>(g));
-  SS_TRY(mark(g, pt, PASS_K));
+  SS_TRY(launch_kpass<T>(g, pt));
   g->log_count++;
   return SS_OK;
 }
@@ -312,6 +353,139 @@ ss_status get_field_t(ss_grid g, int field, void* ddst) {
     spec = g->scratch[field];
   }
   return launch_xpass<T>(g, ss::XMODE_INV, 1, spec, nullptr, nullptr, nullptr, nullptr, ddst, 1.0);
+}
+
+// Time one launch configuration: one warm-up launch, then `reps` launches
+// each bracketed by its own events; returns the fastest in milliseconds.
+template <typename F>
+ss_status time_launch(ss_grid g, F launch, int reps, float* best_ms) {
+  hipEvent_t e[2];
+  SS_TRY(hip_check(hipEventCreate(&e[0]), "hipEventCreate"));
+  ss_status st = hip_check(hipEventCreate(&e[1]), "hipEventCreate");
+  if (st != SS_OK) {
+    hipEventDestroy(e[0]);
+    return st;
+  }
+  float best = 1e30f;
+  st = launch(ss::LaunchEvents());
+  for (int r = 0; st == SS_OK && r < reps; ++r) {
+    ss::LaunchEvents ev;
+    ev.start = e[0];
+    ev.stop = e[1];
+    st = launch(ev);
+    if (st == SS_OK) st = hip_check(hipEventSynchronize(e[1]), "hipEventSynchronize");
+    float ms = 0.f;
+    if (st == SS_OK) st = hip_check(hipEventElapsedTime(&ms, e[0], e[1]), "hipEventElapsedTime");
+    if (st == SS_OK && ms < best) best = ms;
+  }
+  hipEventDestroy(e[0]);
+  hipEventDestroy(e[1]);
+  *best_ms = best;
+  return st;
+}
+
+template <typename T>
+ss_status autotune_t(ss_grid g, int reps) {
+  const int esz = esz_of(g);
+  const int nx = (int)g->n[0];
+  const int64_t rows = g->n[1] * g->n[2];
+  // x pass (STEP): reads the state, writes the scratch arrays only
+  {
+    int best_r = 0;
+    float best = 1e30f;
+    for (int r = 2; r <= 64; r *= 2) {
+      if (!ss::x_tile_ok(esz, nx, g->nf, rows, r)) continue;
+      auto launch = [&](ss::LaunchEvents ev) {
+        ss::XArgs a;
+        memset(&a, 0, sizeof(a));
+        a.spec_in[0] = g->state[0];
+        a.spec_in[1] = g->state[1];
+        a.spec_out[0] = g->scratch[0];
+        a.spec_out[1] = g->scratch[1];
+        a.rows = rows;
+        a.nz = (int)g->n[2];
+        a.ny = (int)g->n[1];
+        a.xcd_remap = 1;
+        a.scale = 1.0;
+        a.rows_per_block = r;
+        for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+        return hip_check(ss::run_xpass<T>(nx, g->nf, ss::XMODE_STEP, g->nlm, a, g->stream, ev), "autotune x");
+      };
+      float ms;
+      SS_TRY(time_launch(g, launch, reps, &ms));
+      if (ms < best) {
+        best = ms;
+        best_r = r;
+      }
+    }
+    g->tile_x_step = best_r;
+  }
+  // k-space pass: run on the scratch arrays as "state" and the staging
+  // array as nonlinear term, so the fields are untouched
+  {
+    const int nl = nlast(g);
+    const int64_t nlines = nlines_k(g);
+    int best_l = 0;
+    float best = 1e30f;
+    for (int l = 1; l <= 512; l *= 2) {
+      if (!ss::k_tile_ok(esz, nl, nlines, g->ndim == 3, l)) continue;
+      auto launch = [&](ss::LaunchEvents ev) {
+        ss::KArgs a;
+        memset(&a, 0, sizeof(a));
+        for (int f = 0; f < g->nf; ++f) {
+          a.fld[f] = g->kf[f];
+          a.fld[f].state = g->scratch[f];
+          a.fld[f].nonlin = g->staging;
+        }
+        a.J = g->ndim == 3 ? (int)g->n[1] : 1;
+        a.nlines = (int)nlines;
+        a.nx = nx;
+        a.sx = a.sy = a.sz = 0.1;
+        a.dt = g->dt;
+        a.a_scale = 1.0 / nl;
+        a.b_scale = 1.0 / (double)g->cells();
+        a.nf = g->nf;
+        a.three_d = g->ndim == 3;
+        a.lines_per_block = l;
+        return hip_check(ss::run_kpass<T>(nl, a, g->stream, ev), "autotune k");
+      };
+      float ms;
+      SS_TRY(time_launch(g, launch, reps, &ms));
+      if (ms < best) {
+        best = ms;
+        best_l = l;
+      }
+    }
+    g->tile_k = best_l;
+  }
+  if (g->ndim == 3) {
+    int best_y = 0;
+    float best = 1e30f;
+    for (int l = 1; l <= 64; l *= 2) {
+      if (!ss::y_tile_ok(esz, (int)g->n[1], g->n[2], l)) continue;
+      auto launch = [&](ss::LaunchEvents ev) {
+        ss::YArgs a;
+        memset(&a, 0, sizeof(a));
+        a.in = g->scratch[0];
+        a.out = g->scratch[0];
+        a.ny = (int)g->n[1];
+        a.nz = (int)g->n[2];
+        a.scale = 1.0;
+        a.lines_per_block = l;
+        return hip_check(ss::run_ypass<T>((int)g->n[1], -1, a, g->n[0] / 2, g->stream, ev), "autotune y");
+      };
+      float ms;
+      SS_TRY(time_launch(g, launch, reps, &ms));
+      if (ms < best) {
+        best = ms;
+        best_y = l;
+      }
+    }
+    g->tile_y = best_y;
+  }
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k};
+  return SS_OK;
 }
 
 bool finite_all(const double* v, int n) {
@@ -371,6 +545,7 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
     g->ws_bytes = 0;
     g->field_set[0] = g->field_set[1] = false;
   }
+  if (!g->has_model || nf != g->nf) g->tile_x_step = g->tile_y = g->tile_k = 0;
   g->model = model;
   g->nf = nf;
   g->ncoef = ncoef;
@@ -467,19 +642,18 @@ ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t
   for (int f = 0; f < g->nf; ++f)
     if (!g->field_set[f]) return fail(SS_ERR_STATE, "ss_step_n_profiled: field %d was never set", f);
   const int per_step = g->ndim == 2 ? 2 : 2 * g->nf + 2;
-  if ((nsteps + 1) * per_step + 1 > PassTimer::kMaxEvents)
+  if (nsteps * per_step > PassTimer::kMaxLaunches)
     return fail(SS_ERR_ARG, "ss_step_n_profiled: at most %d steps per call",
-                (int)(PassTimer::kMaxEvents / per_step - 2));
+                (int)(PassTimer::kMaxLaunches / per_step));
   PassTimer* pt = new (std::nothrow) PassTimer();
   if (!pt) return fail(SS_ERR_ARG, "ss_step_n_profiled: out of host memory");
-  const int nev = (int)((nsteps)*per_step + 1);
+  const int nev = (int)(2 * nsteps * per_step);
   ss_status st = SS_OK;
   int created = 0;
   for (; created < nev; ++created) {
     st = hip_check(hipEventCreate(&pt->ev[created]), "hipEventCreate");
     if (st != SS_OK) break;
   }
-  if (st == SS_OK) st = mark(g, pt, -1);
   for (int64_t i = 0; st == SS_OK && i < nsteps; ++i)
     st = g->dtype == SS_F64 ? step_once<double>(g, pt) : step_once<float>(g, pt);
   if (st == SS_OK) st = hip_check(hipStreamSynchronize(g->stream), "ss_step_n_profiled: synchronise");
@@ -488,11 +662,11 @@ ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t
       pass_ms[i] = 0.0;
       pass_count[i] = 0;
     }
-    for (int e = 1; e < pt->used; ++e) {
+    for (int u = 0; u < pt->used; ++u) {
       float ms = 0.f;
-      st = hip_check(hipEventElapsedTime(&ms, pt->ev[e - 1], pt->ev[e]), "hipEventElapsedTime");
+      st = hip_check(hipEventElapsedTime(&ms, pt->ev[2 * u], pt->ev[2 * u + 1]), "hipEventElapsedTime");
       if (st != SS_OK) break;
-      const int k = pt->kind[e];
+      const int k = pt->kind[u];
       if (k >= 0 && k < npass) {
         pass_ms[k] += ms;
         pass_count[k] += 1;
@@ -502,6 +676,46 @@ ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t
   for (int e = 0; e < created; ++e) hipEventDestroy(pt->ev[e]);
   delete pt;
   return st;
+}
+
+ss_status ss_autotune(ss_grid g, int reps) {
+  if (!g) return fail(SS_ERR_ARG, "ss_autotune: null grid");
+  if (reps < 1 || reps > 1000) return fail(SS_ERR_ARG, "ss_autotune: reps must be in [1, 1000]");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_autotune: model and workspace must be set first");
+  ensure_tiles(g);
+  return g->dtype == SS_F64 ? autotune_t<double>(g, reps) : autotune_t<float>(g, reps);
+}
+
+ss_status ss_get_tiles(ss_grid g, int tiles[4]) {
+  if (!g || !tiles) return fail(SS_ERR_ARG, "ss_get_tiles: null argument");
+  if (!g->has_model) return fail(SS_ERR_STATE, "ss_get_tiles: call ss_set_model first");
+  ensure_tiles(g);
+  tiles[0] = g->tile_x_step;
+  tiles[1] = g->tile_k;
+  tiles[2] = g->tile_y;
+  tiles[3] = g->tile_x_io;
+  return SS_OK;
+}
+
+ss_status ss_set_tiles(ss_grid g, const int tiles[4]) {
+  if (!g || !tiles) return fail(SS_ERR_ARG, "ss_set_tiles: null argument");
+  if (!g->has_model) return fail(SS_ERR_STATE, "ss_set_tiles: call ss_set_model first");
+  const int esz = esz_of(g);
+  const int64_t rows = g->n[1] * g->n[2];
+  if (tiles[0] && !ss::x_tile_ok(esz, (int)g->n[0], g->nf, rows, tiles[0]))
+    return fail(SS_ERR_ARG, "ss_set_tiles: x tile %d not valid for this grid", tiles[0]);
+  if (tiles[1] && !ss::k_tile_ok(esz, nlast(g), nlines_k(g), g->ndim == 3, tiles[1]))
+    return fail(SS_ERR_ARG, "ss_set_tiles: k tile %d not valid for this grid", tiles[1]);
+  if (g->ndim == 3 && tiles[2] && !ss::y_tile_ok(esz, (int)g->n[1], g->n[2], tiles[2]))
+    return fail(SS_ERR_ARG, "ss_set_tiles: y tile %d not valid for this grid", tiles[2]);
+  if (tiles[3] && !ss::x_tile_ok(esz, (int)g->n[0], 1, rows, tiles[3]))
+    return fail(SS_ERR_ARG, "ss_set_tiles: x io tile %d not valid for this grid", tiles[3]);
+  g->tile_x_step = tiles[0];
+  g->tile_k = tiles[1];
+  g->tile_y = g->ndim == 3 ? tiles[2] : 0;
+  g->tile_x_io = tiles[3];
+  ensure_tiles(g);
+  return SS_OK;
 }
 
 ss_status ss_bind_mass_log(ss_grid g, double* device_ptr, int64_t capacity) {

@@ -1,44 +1,133 @@
-// Launch geometry and run-time dispatch of the templated kernels.
-// The launch functions are instantiated once per element type in
-// ss_kernels_f32.hip / ss_kernels_f64.hip.
+// Launch planning and run-time dispatch of the templated kernels.
+//
+// Every kernel takes its tiling (rows or lines per workgroup) at run time
+// and sizes its LDS dynamically, so one compiled kernel serves every tile
+// choice and the autotuner can time the alternatives.  The launch
+// functions are instantiated once per element type in ss_kernels_f32.hip /
+// ss_kernels_f64.hip.
 #pragma once
+
+#include <hip/hip_ext.h>
 
 #include "ss_kernels.hpp"
 
 namespace ss {
 
+// Optional start/stop events recorded around a launch (kernel time only).
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
+// Threads per block limits (register budgets of the kernels).
+constexpr int x_max_threads(int esz) { return esz == 16 ? 512 : 1024; }
+constexpr int k_max_threads() { return 512; }
+constexpr int y_max_threads() { return 1024; }
+
+// ---- tile validity and defaults (host side, no templates) -----------------
+inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// x pass: `rows` rows (even) per block, as R/2 row pairs
+inline bool x_tile_ok(int esz, int nx, int nf, int64_t nrows, int rows) {
+  return is_pow2(rows) && rows >= 2 && rows <= 64 && rows <= nrows && nrows % rows == 0 &&
+         x_lds(esz, nx, nf, rows) <= LDS_BUDGET;
+}
+inline int x_threads(int esz, int nx, int rows) {
+  const int S = nx / 8;
+  int G = x_max_threads(esz) / S;
+  if (G > rows / 2) G = rows / 2;
+  if (G < 1) G = 1;
+  return G * S;
+}
+inline int x_tile_default(int esz, int nx, int nf, int64_t nrows) {
+  // at most 128 contiguous bytes per staged chunk, at most half the LDS
+  // (two blocks per CU), and enough blocks to cover the CUs twice
+  int best = 2;
+  for (int r = 2; r <= 64; r *= 2) {
+    if (!x_tile_ok(esz, nx, nf, nrows, r)) break;
+    if (r * esz > 128 || x_lds(esz, nx, nf, r) > LDS_BUDGET / 2) break;
+    if (r > 2 && nrows / r < 256) break;
+    best = r;
+  }
+  return best;
+}
+
+// y pass: `lines` lines (consecutive z) per block
+inline bool y_tile_ok(int esz, int ny, int64_t nz, int lines) {
+  return is_pow2(lines) && lines <= 64 && lines <= nz && nz % lines == 0 &&
+         y_lds(esz, ny, lines) <= LDS_BUDGET;
+}
+inline int y_threads(int ny, int lines) {
+  const int S = ny / 8;
+  int G = y_max_threads() / S;
+  if (G > lines) G = lines;
+  if (G < 1) G = 1;
+  return G * S;
+}
+inline int y_tile_default(int esz, int ny, int64_t nz) {
+  int best = 1;
+  for (int r = 1; r <= 64; r *= 2) {
+    if (!y_tile_ok(esz, ny, nz, r)) break;
+    if (r * esz > 128 || y_lds(esz, ny, r) > LDS_BUDGET / 2) break;
+    best = r;
+  }
+  return best;
+}
+
+// k-space pass: `lines` lines per block (even in 3D: mirror pairs)
+inline bool k_tile_ok(int esz, int nl, int64_t nlines, bool three_d, int lines) {
+  const int S = nl / 8;
+  return is_pow2(lines) && lines <= nlines && nlines % lines == 0 && lines * S <= k_max_threads() &&
+         (!three_d || lines >= 2) && k_lds(esz, nl, lines) <= LDS_BUDGET;
+}
+inline int k_tile_default(int esz, int nl, int64_t nlines, bool three_d) {
+  const int S = nl / 8;
+  int l = 256 / S > 1 ? 256 / S : 1;
+  if (three_d && l < 2) l = 2;
+  while (l > 1 && !k_tile_ok(esz, nl, nlines, three_d, l)) l /= 2;
+  return l;
+}
+
 template <typename T>
-hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s);
+hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s, LaunchEvents ev);
 template <typename T>
-hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s);
+hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s, LaunchEvents ev);
 template <typename T>
-hipError_t run_kpass(int nl, KArgs a, hipStream_t s);
+hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev);
 
 #ifdef SS_DISPATCH_IMPL
 
-template <typename T, int NX, int NF, int MODE, int NLM>
-hipError_t launch_x(XArgs a, hipStream_t s) {
-  typedef XCfg<T, NX> K;
-  constexpr int RMAX = K::rmax(NF);
-  const int R = (int)(a.rows < RMAX ? a.rows : RMAX);
-  const int P = R / 2;
-  int G = XThreads<T, NF>::value / K::S;
-  if (G > P) G = P;
-  if (G < 1) G = 1;
-  a.rows_per_block = R;
-  dim3 grid((unsigned)(a.rows / R)), block((unsigned)(G * K::S));
-  hipLaunchKernelGGL((xpass_kernel<T, NX, NF, MODE, NLM>), grid, block, 0, s, a);
+template <typename K, typename A>
+hipError_t launch_with(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, LaunchEvents ev,
+                       const A& a) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (ev.start || ev.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ev.start, ev.stop, 0, a);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int NX, int NF, int MODE, int NLM>
+hipError_t launch_x(XArgs a, hipStream_t s, LaunchEvents ev) {
+  constexpr int ESZ = (int)sizeof(C<T>);
+  const int R = a.rows_per_block;
+  if (!x_tile_ok(ESZ, NX, NF, a.rows, R)) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(a.rows / R)), block((unsigned)x_threads(ESZ, NX, R));
+  return launch_with(xpass_kernel<T, NX, NF, MODE, NLM>, grid, block, (uint32_t)x_lds(ESZ, NX, NF, R), s,
+                     ev, a);
 }
 
 #define SS_POW2_CASES(M) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)
 
 template <typename T, int NF, int MODE, int NLM>
-hipError_t xdisp(int nx, const XArgs& a, hipStream_t s) {
+hipError_t xdisp(int nx, const XArgs& a, hipStream_t s, LaunchEvents ev) {
   switch (nx) {
 #define SS_CASE(n) \
   case n:          \
-    return launch_x<T, n, NF, MODE, NLM>(a, s);
+    return launch_x<T, n, NF, MODE, NLM>(a, s, ev);
     SS_POW2_CASES(SS_CASE)
 #undef SS_CASE
   }
@@ -46,34 +135,29 @@ hipError_t xdisp(int nx, const XArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s) {
-  if (mode == XMODE_FWD) return xdisp<T, 1, XMODE_FWD, NLIN_POLY>(nx, a, s);
-  if (mode == XMODE_INV) return xdisp<T, 1, XMODE_INV, NLIN_POLY>(nx, a, s);
-  if (nf == 1) return xdisp<T, 1, XMODE_STEP, NLIN_POLY>(nx, a, s);
-  if (nlm == NLIN_GS) return xdisp<T, 2, XMODE_STEP, NLIN_GS>(nx, a, s);
-  return xdisp<T, 2, XMODE_STEP, NLIN_MODELC>(nx, a, s);
+hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s, LaunchEvents ev) {
+  if (mode == XMODE_FWD) return xdisp<T, 1, XMODE_FWD, NLIN_POLY>(nx, a, s, ev);
+  if (mode == XMODE_INV) return xdisp<T, 1, XMODE_INV, NLIN_POLY>(nx, a, s, ev);
+  if (nf == 1) return xdisp<T, 1, XMODE_STEP, NLIN_POLY>(nx, a, s, ev);
+  if (nlm == NLIN_GS) return xdisp<T, 2, XMODE_STEP, NLIN_GS>(nx, a, s, ev);
+  return xdisp<T, 2, XMODE_STEP, NLIN_MODELC>(nx, a, s, ev);
 }
 
 template <typename T, int NY, int DIR>
-hipError_t launch_y(YArgs a, int64_t nkx, hipStream_t s) {
-  typedef YCfg<T, NY> K;
-  constexpr int RMAX = K::rmax();
-  const int R = a.nz < RMAX ? a.nz : RMAX;
-  int G = 1024 / K::S;
-  if (G > R) G = R;
-  if (G < 1) G = 1;
-  a.lines_per_block = R;
-  dim3 grid((unsigned)(nkx * (a.nz / R))), block((unsigned)(G * K::S));
-  hipLaunchKernelGGL((ypass_kernel<T, NY, DIR>), grid, block, 0, s, a);
-  return hipGetLastError();
+hipError_t launch_y(YArgs a, int64_t nkx, hipStream_t s, LaunchEvents ev) {
+  constexpr int ESZ = (int)sizeof(C<T>);
+  const int R = a.lines_per_block;
+  if (!y_tile_ok(ESZ, NY, a.nz, R)) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(nkx * (a.nz / R))), block((unsigned)y_threads(NY, R));
+  return launch_with(ypass_kernel<T, NY, DIR>, grid, block, (uint32_t)y_lds(ESZ, NY, R), s, ev, a);
 }
 
 template <typename T>
-hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s) {
+hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s, LaunchEvents ev) {
   switch (ny) {
 #define SS_CASE(n)                                                       \
   case n:                                                                \
-    return dir < 0 ? launch_y<T, n, -1>(a, nkx, s) : launch_y<T, n, +1>(a, nkx, s);
+    return dir < 0 ? launch_y<T, n, -1>(a, nkx, s, ev) : launch_y<T, n, +1>(a, nkx, s, ev);
     SS_POW2_CASES(SS_CASE)
 #undef SS_CASE
   }
@@ -81,31 +165,30 @@ hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s) {
 }
 
 template <typename T, int NL>
-hipError_t launch_k(KArgs a, hipStream_t s) {
-  typedef KCfg<T, NL> K;
-  const int L = a.nlines < K::LPW ? a.nlines : K::LPW;
-  a.lines_per_block = L;
-  dim3 grid((unsigned)(a.nlines / L), (unsigned)a.nf), block((unsigned)(L * K::S));
-  hipLaunchKernelGGL((kpass_kernel<T, NL>), grid, block, 0, s, a);
-  return hipGetLastError();
+hipError_t launch_k(KArgs a, hipStream_t s, LaunchEvents ev) {
+  constexpr int ESZ = (int)sizeof(C<T>);
+  const int L = a.lines_per_block;
+  if (!k_tile_ok(ESZ, NL, a.nlines, a.three_d != 0, L)) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(a.nlines / L), (unsigned)a.nf), block((unsigned)(L * (NL / 8)));
+  return launch_with(kpass_kernel<T, NL>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
 }
 
 template <typename T>
-hipError_t run_kpass(int nl, KArgs a, hipStream_t s) {
+hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev) {
   switch (nl) {
 #define SS_CASE(n) \
   case n:          \
-    return launch_k<T, n>(a, s);
+    return launch_k<T, n>(a, s, ev);
     SS_POW2_CASES(SS_CASE)
 #undef SS_CASE
   }
   return hipErrorInvalidValue;
 }
 
-#define SS_INSTANTIATE(T)                                                               \
-  template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t);            \
-  template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t);             \
-  template hipError_t run_kpass<T>(int, KArgs, hipStream_t);
+#define SS_INSTANTIATE(T)                                                                  \
+  template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t, LaunchEvents); \
+  template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t, LaunchEvents);  \
+  template hipError_t run_kpass<T>(int, KArgs, hipStream_t, LaunchEvents);
 
 #endif  // SS_DISPATCH_IMPL
 

@@ -35,6 +35,29 @@ enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2 };
 
 constexpr int LDS_BUDGET = 160 * 1024;
 
+// LDS geometry shared by the kernels and the host-side launch planning
+// (esz = bytes of one complex element: 8 for FP32, 16 for FP64).
+constexpr int padded_len_e(int esz, int n) { return esz == 16 ? n + (n >> 3) + 1 : n + (n >> 4) + 1; }
+// x pass region stride: NF*REG = 2 (mod 8 or 16) keeps the staged rows of a
+// block on distinct banks
+constexpr int x_reg(int esz, int nx, int nf) {
+  int r = padded_len_e(esz, nx);
+  const int mod = esz == 16 ? 8 : 16;
+  while (((nf * r) % mod) != 2 % mod) ++r;
+  return r;
+}
+constexpr int64_t x_lds(int esz, int nx, int nf, int rows) { return (int64_t)(rows / 2) * nf * x_reg(esz, nx, nf) * esz; }
+// y pass region stride = 1 (mod 8 or 16)
+constexpr int y_reg(int esz, int ny) {
+  int r = padded_len_e(esz, ny);
+  const int mod = esz == 16 ? 8 : 16;
+  while ((r % mod) != 1) ++r;
+  return r;
+}
+constexpr int64_t y_lds(int esz, int ny, int lines) { return (int64_t)lines * y_reg(esz, ny) * esz; }
+constexpr int k_reg(int esz, int nl) { return padded_len_e(esz, nl); }
+constexpr int64_t k_lds(int esz, int nl, int lines) { return (int64_t)lines * 2 * k_reg(esz, nl) * esz; }
+
 // ---------------------------------------------------------------------------
 // x pass
 // ---------------------------------------------------------------------------
@@ -56,26 +79,9 @@ struct XCfg {
   static constexpr int S = NX / 8;                  // threads per line
   static constexpr int H = NX / 2;                  // stored kx count
   static constexpr int ESZ = (int)sizeof(C<T>);
-  static constexpr int REG0 = padded_len<T>(NX);
-  // region stride: NF*REG = 2 (mod 8 or 16) keeps the staged rows on
-  // distinct banks; HB = H + 1 is the offset of the second row of a pair
-  static constexpr int MOD = ESZ == 16 ? 8 : 16;
-  static constexpr int reg_for(int nf) {
-    int r = REG0;
-    while (((nf * r) % MOD) != 2 % MOD) ++r;
-    return r;
-  }
+  // HB = H + 1 is the offset of the second row of a pair in its region
   static constexpr int HB = H + 1;
-  // rows per block: enough for 128 contiguous bytes and >= 256 threads,
-  // bounded by LDS
-  static constexpr int rmax(int nf) {
-    int r = 2;
-    const int want_bytes = 128 / ESZ;
-    const int want_threads = 2 * ((256 / S) > 1 ? (256 / S) : 1);
-    const int want = want_bytes > want_threads ? want_bytes : want_threads;
-    while (r * 2 <= want && (r * 2 / 2) * nf * reg_for(nf) * ESZ <= LDS_BUDGET && r * 2 <= 64) r *= 2;
-    return r;
-  }
+  static constexpr int reg_for(int nf) { return x_reg(ESZ, NX, nf); }
 };
 
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap) {
@@ -111,11 +117,11 @@ __device__ __forceinline__ void nonlinear(C<T>* c0, C<T>* c1, T p0, T p1, T p2) 
   }
 }
 
-// threads per block of the x pass: two FP64 fields need the registers of
-// 512-thread blocks
+// threads per block of the x pass: FP64 needs the registers of 512-thread
+// blocks
 template <typename T, int NF>
 struct XThreads {
-  static constexpr int value = (NF == 2 && sizeof(T) == 8) ? 512 : 1024;
+  static constexpr int value = sizeof(T) == 8 ? 512 : 1024;
 };
 
 template <typename T, int NX, int NF, int MODE, int NLM>
@@ -123,9 +129,8 @@ __global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a
   typedef XCfg<T, NX> K;
   constexpr int S = K::S, H = K::H, HB = K::HB;
   constexpr int REG = K::reg_for(NF);
-  constexpr int RMAX = K::rmax(NF);
-  constexpr int PMAX = RMAX / 2;
-  __shared__ C<T> lds[PMAX * NF * REG];
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
 
   const int R = a.rows_per_block;
   const int P = R >> 1;
@@ -285,27 +290,15 @@ template <typename T, int NY>
 struct YCfg {
   static constexpr int S = NY / 8;
   static constexpr int ESZ = (int)sizeof(C<T>);
-  static constexpr int MOD = ESZ == 16 ? 8 : 16;
-  static constexpr int REG = [] {
-    int r = padded_len<T>(NY);
-    while ((r % MOD) != 1) ++r;
-    return r;
-  }();
-  static constexpr int rmax() {
-    int r = 1;
-    const int want_bytes = 128 / ESZ;
-    const int want_threads = (256 / S) > 1 ? (256 / S) : 1;
-    const int want = want_bytes > want_threads ? want_bytes : want_threads;
-    while (r * 2 <= want && r * 2 * REG * ESZ <= LDS_BUDGET && r * 2 <= 64) r *= 2;
-    return r;
-  }
+  static constexpr int REG = y_reg(ESZ, NY);
 };
 
 template <typename T, int NY, int DIR>
 __global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
   typedef YCfg<T, NY> K;
-  constexpr int S = K::S, REG = K::REG, RMAX = K::rmax();
-  __shared__ C<T> lds[RMAX * REG];
+  constexpr int S = K::S, REG = K::REG;
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
   const int R = a.lines_per_block;
   const int G = (int)blockDim.x / S;
   const int tid = threadIdx.x;
@@ -396,15 +389,16 @@ __device__ __forceinline__ void etd1_coeffs(const KField& f, double k2, double d
 template <typename T, int NL>
 struct KCfg {
   static constexpr int S = NL / 8;
-  static constexpr int LPW = (256 / S) > 1 ? (256 / S) : 1;   // lines per block
-  static constexpr int REG = padded_len<T>(NL);
+  static constexpr int ESZ = (int)sizeof(C<T>);
+  static constexpr int REG = k_reg(ESZ, NL);
 };
 
 template <typename T, int NL>
 __global__ void __launch_bounds__(512) kpass_kernel(KArgs a) {
   typedef KCfg<T, NL> K;
-  constexpr int S = K::S, LPW = K::LPW, REG = K::REG;
-  __shared__ C<T> lds[LPW * 2 * REG];
+  constexpr int S = K::S, REG = K::REG;
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
   const int tid = threadIdx.x;
   const int ls = tid / S, t = tid - ls * S;
   const KField F = blockIdx.y == 0 ? a.fld[0] : a.fld[1];

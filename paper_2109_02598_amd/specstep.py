@@ -58,6 +58,9 @@ def lib():
         "ss_step_n": [vp, i64],
         "ss_step_n_profiled": [vp, i64, ctypes.POINTER(dbl), ctypes.POINTER(i64), cint],
         "ss_bind_mass_log": [vp, vp, i64],
+        "ss_autotune": [vp, cint],
+        "ss_get_tiles": [vp, ctypes.POINTER(cint)],
+        "ss_set_tiles": [vp, ctypes.POINTER(cint)],
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
         "ss_set_stream": [vp, vp],
         "ss_destroy_grid": [vp],
@@ -139,6 +142,21 @@ def ss_step_n_profiled(h, nsteps):
     cnt = (ctypes.c_int64 * SS_NPASS)()
     _check(lib().ss_step_n_profiled(h, int(nsteps), ms, cnt, SS_NPASS))
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(SS_NPASS) if cnt[i]}
+
+
+def ss_autotune(h, reps=5):
+    _check(lib().ss_autotune(h, int(reps)))
+
+
+def ss_get_tiles(h):
+    t = (ctypes.c_int * 4)()
+    _check(lib().ss_get_tiles(h, t))
+    return list(t)
+
+
+def ss_set_tiles(h, tiles):
+    t = (ctypes.c_int * 4)(*[int(v) for v in tiles])
+    _check(lib().ss_set_tiles(h, t))
 
 
 def ss_bind_mass_log(h, ptr, capacity):
@@ -240,6 +258,16 @@ class Grid:
 
     def step(self, nsteps):
         ss_step_n(self.h, nsteps)
+
+    def autotune(self, reps=5):
+        ss_autotune(self.h, reps)
+        return ss_get_tiles(self.h)
+
+    def tiles(self):
+        return ss_get_tiles(self.h)
+
+    def set_tiles(self, tiles):
+        ss_set_tiles(self.h, tiles)
 
     def step_profiled(self, nsteps):
         return ss_step_n_profiled(self.h, nsteps)

@@ -1,0 +1,124 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (the same library entry points and kernels).
+
+Where the oracle cannot follow a whole run in seconds, the comparison is
+element by element over the first steps, and the rest of the run is
+checked through properties that hold at any size (conservation).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import spectral
+from paper_2109_02598_amd import inputs
+from tests._common import TOL, need_gpu, rel_l2, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_chunked(w, steps, chunk=10, fields=None):
+    q = w.fields if fields is None else fields
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        q = spectral.step_n(q, w.model, w.coef, w.dt, w.dx, k)
+        done += k
+        say("  oracle", w.name, "step", done)
+    return q
+
+
+@pytest.fixture(scope="module")
+def ch2048_oracle50():
+    w = inputs.cahn_hilliard_2d(n=2048, seed=2)
+    return w, oracle_chunked(w, 50)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_allen_cahn_128(dtype):
+    w = inputs.allen_cahn_2d(n=128, seed=1)
+    for steps in (50, 100):
+        got, _ = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef)
+        want = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, steps)
+        err = rel_l2(got[0], want[0])
+        say("allen_cahn 128^2", dtype, steps, "steps rel_l2 %.3e" % err)
+        assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_cahn_hilliard_2048_parity_50_steps(ch2048_oracle50, dtype):
+    """The FP32 run starts from the float32-rounded input; the bar 1e-4
+    covers that rounding (3e-8 relative) with four decades to spare."""
+    w, want = ch2048_oracle50
+    got, mass = run_gpu(w.model, w.n, w.dx, w.dt, 50, w.fields, dtype, coef=w.coef,
+                        mass_capacity=50)
+    err = rel_l2(got[0], want[0])
+    say("cahn_hilliard 2048^2", dtype, "50 steps rel_l2 %.3e" % err)
+    assert err <= TOL[dtype]
+    m0 = float(np.mean(w.fields[0]))
+    assert np.max(np.abs(mass[:, 0] - m0)) <= (1e-15 if dtype == "f64" else 1e-8)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_cahn_hilliard_2048_mass_1000_steps(dtype):
+    """Mass log over the whole 1000-step run: the k = 0 mode has A = 1 and
+    B N = 0, so the mean changes only by transform roundoff."""
+    w = inputs.cahn_hilliard_2d(n=2048, seed=2)
+    got, mass = run_gpu(w.model, w.n, w.dx, w.dt, 1000, w.fields, dtype, coef=w.coef,
+                        mass_capacity=1000)
+    m0 = float(np.mean(np.asarray(w.fields[0], dtype=np.float32 if dtype == "f32" else np.float64)))
+    drift = float(np.max(np.abs(mass[:, 0] - m0)))
+    rms = float(np.sqrt(np.mean(got[0] ** 2)))
+    say("cahn_hilliard 2048^2", dtype, "1000 steps: max mean drift %.3e, rms %.3e" % (drift, rms))
+    eps = 2.2e-16 if dtype == "f64" else 1.2e-7
+    # per step the DC mode is one sum over N values: roundoff ~ eps * rms,
+    # accumulating at most linearly over the run
+    assert drift <= 10 * eps * rms * 1000
+    assert len(mass) == 1000
+    assert np.all(np.isfinite(got[0]))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pfc_256_parity_first_steps(dtype):
+    w = inputs.pfc_3d(n=256, seed=3)
+    steps = 2
+    got, mass = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef,
+                        mass_capacity=steps)
+    want = oracle_chunked(w, steps, chunk=1)
+    err = rel_l2(got[0], want[0])
+    say("pfc 256^3", dtype, steps, "steps rel_l2 %.3e" % err)
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pfc_64_parity_50_steps(dtype):
+    w = inputs.pfc_3d(n=64, seed=3)
+    got, _ = run_gpu(w.model, w.n, w.dx, w.dt, 50, w.fields, dtype, coef=w.coef)
+    want = oracle_chunked(w, 50, chunk=25)
+    err = rel_l2(got[0], want[0])
+    say("pfc 64^3", dtype, "50 steps rel_l2 %.3e" % err)
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pfc_256_mass_500_steps(dtype):
+    w = inputs.pfc_3d(n=256, seed=3)
+    got, mass = run_gpu(w.model, w.n, w.dx, w.dt, 500, w.fields, dtype, coef=w.coef,
+                        mass_capacity=500)
+    m0 = float(np.mean(np.asarray(w.fields[0], dtype=np.float32 if dtype == "f32" else np.float64)))
+    drift = float(np.max(np.abs(mass[:, 0] - m0)))
+    say("pfc 256^3", dtype, "500 steps: max mean drift %.3e" % drift)
+    assert drift <= (1e-13 if dtype == "f64" else 2e-5)
+    assert np.all(np.isfinite(got[0]))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gray_scott_512(dtype):
+    w = inputs.gray_scott_2d(n=512)
+    steps = 200 if dtype == "f64" else 50
+    got, _ = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef)
+    want = oracle_chunked(w, steps, chunk=50)
+    for i in range(2):
+        err = rel_l2(got[i], want[i])
+        say("gray_scott 512^2", dtype, steps, "steps field", i, "rel_l2 %.3e" % err)
+        assert err <= TOL[dtype]

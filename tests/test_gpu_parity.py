@@ -72,3 +72,45 @@ def test_set_get_round_trip(n, dtype):
     back2 = g.get_field(0).double().cpu().numpy()
     assert np.array_equal(back, back2)
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,model", [((256, 64), "cahn_hilliard"), ((64, 128), "gray_scott"),
+                                     ((32, 16, 64), "pfc")])
+def test_tilings_are_bitwise_identical(n, model, dtype):
+    """Every valid tiling of every pass gives bit-identical fields, and the
+    autotuner's pick is one of them."""
+    from tests._common import need_gpu
+    torch, specstep = need_gpu()
+    dx = (1.0,) * len(n)
+    f0 = as_input(synth_fields(model, n, dx, 3), dtype)
+    g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model], dt=0.05)
+    base = None
+    esz = 16 if dtype == "f64" else 8
+    cands = [(r, l, y) for r in (2, 4, 8, 16, 32, 64) for l in (1, 2, 4, 8, 16, 32, 64)
+             for y in ((1, 2, 4, 8, 16) if len(n) == 3 else (0,))]
+    tried = 0
+    for r, l, y in cands:
+        try:
+            g.set_tiles([r, l, y, 0])
+        except specstep.SpecStepError:
+            continue
+        for i, f in enumerate(f0):
+            g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
+        g.step(7)
+        out = [g.get_field(i).cpu().numpy() for i in range(len(f0))]
+        if base is None:
+            base = out
+        else:
+            for a, b in zip(out, base):
+                assert np.array_equal(a, b), (r, l, y)
+        tried += 1
+    assert tried >= 3
+    tiles = g.autotune(2)
+    for i, f in enumerate(f0):
+        g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
+    g.step(7)
+    for i, b in enumerate(base):
+        assert np.array_equal(g.get_field(i).cpu().numpy(), b), tiles
+    say("tilings tried", tried, "autotuned", tiles)
+    g.close()
