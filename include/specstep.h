@@ -145,6 +145,57 @@ ss_status ss_autotune(ss_grid g, int reps);
 ss_status ss_get_tiles(ss_grid g, int tiles[4]);
 ss_status ss_set_tiles(ss_grid g, const int tiles[4]);
 
+/* ---- Batched step: many independent grids in grouped launches ----------
+ *
+ * A batch advances several independent simulations together, the way the
+ * paper's driver runs a list of models from one configuration one after
+ * another (Sec. 2.4, Fig. 2), but with every member's tiles in the same
+ * kernel launches: per step one grouped x-pass launch and one grouped
+ * k-space launch cover all members, whatever their sizes and
+ * coefficients.  A run of n steps can be captured into one HIP graph and
+ * replayed with a single launch.
+ *
+ * Members: 2D grids of one dtype, single-field models (Allen-Cahn,
+ * Cahn-Hilliard, PFC), nx and ny powers of two in [64, 2048], all
+ * sharing the batch's stream, each with model, workspace and field set.
+ * Results are bitwise those of ss_step_n on each member.  The mass log is
+ * not written by batched steps.  Members must stay alive and keep their
+ * workspaces while the batch exists. */
+typedef struct ss_batch_s* ss_batch;
+
+/* Create a batch over count >= 1 grids (copied handle list); the stream is
+ * that of the first grid.  Errors: SS_ERR_ARG (null, mixed dtype or
+ * stream), SS_ERR_UNSUPPORTED (3D, two-field model, size), SS_ERR_STATE
+ * (member without model or workspace). */
+ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out);
+
+/* Device bytes the batch needs for its member tables (caller-owned,
+ * 256-byte aligned, bound with ss_batch_bind_workspace). */
+ss_status ss_batch_workspace_size(ss_batch b, size_t* bytes);
+ss_status ss_batch_bind_workspace(ss_batch b, void* device_ptr, size_t bytes);
+
+/* Time each valid block size (128, 256, 512 threads) for the grouped
+ * launches `reps` times and keep the fastest.  Fields are untouched (the
+ * timed k-space launches run on the members' scratch arrays).
+ * Synchronises the stream. */
+ss_status ss_batch_autotune(ss_batch b, int reps);
+
+/* Advance every member by nsteps (eager launches on the stream). */
+ss_status ss_batch_step_n(ss_batch b, int64_t nsteps);
+
+/* Capture nsteps batched steps into a HIP graph (replaces a previous
+ * capture).  The batch's stream must not be the null stream. */
+ss_status ss_batch_capture(ss_batch b, int64_t nsteps);
+
+/* Replay the captured graph once on the batch's stream (nsteps steps). */
+ss_status ss_batch_launch(ss_batch b);
+
+/* Threads per block in use and the number of blocks of the grouped x and
+ * k launches: info[0..2]. */
+ss_status ss_batch_info(ss_batch b, int info[3]);
+
+ss_status ss_batch_destroy(ss_batch b);
+
 /* Bind a device buffer of capacity * nfields doubles for the per-step
  * mass log (spatial mean of each field after each step; conserved for
  * Cahn-Hilliard and PFC, Sec. 3).  Entry (i, f) is at [i*nfields + f]

@@ -24,7 +24,7 @@ SOURCES = ["ss_kernels_f32.hip", "ss_kernels_f64.hip", "ss_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
-         "-mcode-object-version=5",
+         "-mcode-object-version=5", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]
 

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -488,6 +489,143 @@ ss_status autotune_t(ss_grid g, int reps) {
   return SS_OK;
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched step: grouped launches over many grids
+// ---------------------------------------------------------------------------
+struct ss_batch_s {
+  std::vector<ss_grid> grids;
+  std::vector<int> order;  // table order: largest grids first
+  ss_dtype dtype = SS_F32;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int threads = 256;
+  bool uploaded = false;
+  std::vector<ss::BatchMember> table, table_tune;
+  std::vector<void*> state_at_build;
+  int x_total = 0, k_total = 0;
+  uint32_t lds_x = 0, lds_k = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t graph_steps = 0;
+};
+
+namespace {
+
+bool batch_size_ok(int64_t n) { return n >= 64 && n <= 2048 && ss::is_pow2(n); }
+
+// Member table for `threads` threads per block; false if a member cannot
+// be tiled with that block size.
+bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& tab,
+                       std::vector<ss::BatchMember>& tune, int& x_total, int& k_total, uint32_t& lds_x,
+                       uint32_t& lds_k) {
+  tab.clear();
+  tune.clear();
+  x_total = k_total = 0;
+  lds_x = lds_k = 0;
+  for (int idx : b->order) {
+    ss_grid g = b->grids[idx];
+    const int esz = esz_of(g);
+    const int nx = (int)g->n[0], ny = (int)g->n[1];
+    const int R = 2 * threads / (nx / 8);
+    const int L = threads / (ny / 8);
+    if (R < 2 || !ss::x_tile_ok(esz, nx, 1, ny, R) || ss::x_threads(esz, nx, R) != threads) return false;
+    if (L < 1 || !ss::k_tile_ok(esz, ny, nx / 2, false, L)) return false;
+    ss::BatchMember m;
+    memset(&m, 0, sizeof(m));
+    m.x.spec_in[0] = g->state[0];
+    m.x.spec_out[0] = g->scratch[0];
+    m.x.rows = ny;
+    m.x.nz = 1;
+    m.x.ny = ny;
+    m.x.rows_per_block = R;
+    m.x.xcd_remap = 0;
+    m.x.scale = 1.0;
+    for (int i = 0; i < 5; ++i) m.x.p[i] = g->p[i];
+    m.k.fld[0] = g->kf[0];
+    m.k.fld[0].state = g->state[0];
+    m.k.fld[0].nonlin = g->scratch[0];
+    m.k.nlines = nx / 2;
+    m.k.J = 1;
+    m.k.lines_per_block = L;
+    m.k.nx = nx;
+    const double two_pi = 6.283185307179586476925286766559;
+    m.k.sx = two_pi / ((double)nx * g->dx[0]);
+    m.k.sy = two_pi / ((double)ny * g->dx[1]);
+    m.k.dt = g->dt;
+    m.k.a_scale = 1.0 / (double)ny;
+    m.k.b_scale = 1.0 / (double)g->cells();
+    m.k.nf = 1;
+    m.nx = nx;
+    m.ny = ny;
+    m.x_first = x_total;
+    m.x_tiles = ny / R;
+    m.k_first = k_total;
+    m.k_tiles = (nx / 2) / L;
+    x_total += m.x_tiles;
+    k_total += m.k_tiles;
+    const uint32_t lx = (uint32_t)ss::x_lds(esz, nx, 1, R), lk = (uint32_t)ss::k_lds(esz, ny, L);
+    if (lx > lds_x) lds_x = lx;
+    if (lk > lds_k) lds_k = lk;
+    tab.push_back(m);
+    // tuning copy: the k pass runs on the scratch and staging arrays
+    m.k.fld[0].state = g->scratch[0];
+    m.k.fld[0].nonlin = g->staging;
+    tune.push_back(m);
+  }
+  return true;
+}
+
+size_t batch_table_bytes(ss_batch b) { return align_up(sizeof(ss::BatchMember) * b->grids.size()); }
+
+ss_status batch_upload(ss_batch b, int threads) {
+  if (!build_batch_table(b, threads, b->table, b->table_tune, b->x_total, b->k_total, b->lds_x, b->lds_k))
+    return fail(SS_ERR_UNSUPPORTED, "batch: a member cannot be tiled with %d threads per block", threads);
+  const size_t tb = batch_table_bytes(b);
+  SS_TRY(hip_check(hipMemcpyAsync(b->ws, b->table.data(), sizeof(ss::BatchMember) * b->table.size(),
+                                  hipMemcpyHostToDevice, b->stream), "batch table upload"));
+  SS_TRY(hip_check(hipMemcpyAsync((char*)b->ws + tb, b->table_tune.data(),
+                                  sizeof(ss::BatchMember) * b->table_tune.size(), hipMemcpyHostToDevice, b->stream),
+                   "batch table upload"));
+  SS_TRY(hip_check(hipStreamSynchronize(b->stream), "batch table upload"));
+  b->threads = threads;
+  b->uploaded = true;
+  b->state_at_build.clear();
+  for (ss_grid g : b->grids) b->state_at_build.push_back(g->state[0]);
+  return SS_OK;
+}
+
+ss_status batch_check_members(ss_batch b) {
+  for (size_t i = 0; i < b->grids.size(); ++i) {
+    ss_grid g = b->grids[i];
+    if (!g->ws || !g->field_set[0]) return fail(SS_ERR_STATE, "batch member %zu: workspace or field not set", i);
+    if (b->uploaded && b->state_at_build[i] != g->state[0])
+      return fail(SS_ERR_STATE, "batch member %zu: workspace was rebound after the batch table was built", i);
+  }
+  return SS_OK;
+}
+
+template <typename T>
+ss_status batch_launch_step(ss_batch b, bool tune_table, ss::LaunchEvents evx, ss::LaunchEvents evk) {
+  ss::BatchArgs a;
+  a.m = (const ss::BatchMember*)((char*)b->ws + (tune_table ? batch_table_bytes(b) : 0));
+  a.count = (int)b->grids.size();
+  a.x_total = b->x_total;
+  a.k_total = b->k_total;
+  SS_TRY(hip_check(ss::run_batch_x<T>(a, b->threads, b->x_total, b->lds_x, b->stream, evx), "batch x launch"));
+  return hip_check(ss::run_batch_k<T>(a, b->threads, b->k_total, b->lds_k, b->stream, evk), "batch k launch");
+}
+
+ss_status batch_step_once(ss_batch b) {
+  return b->dtype == SS_F64 ? batch_launch_step<double>(b, false, {}, {}) : batch_launch_step<float>(b, false, {}, {});
+}
+
+}  // namespace
+
+namespace {
+
 bool finite_all(const double* v, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
@@ -736,6 +874,149 @@ ss_status ss_mass_log_count(ss_grid g, int64_t* count) {
 ss_status ss_set_stream(ss_grid g, void* stream) {
   if (!g) return fail(SS_ERR_ARG, "ss_set_stream: null grid");
   g->stream = (hipStream_t)stream;
+  return SS_OK;
+}
+
+ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out) {
+  if (!out) return fail(SS_ERR_ARG, "ss_batch_create: out is null");
+  *out = nullptr;
+  if (!grids || count < 1 || count > 65536) return fail(SS_ERR_ARG, "ss_batch_create: need 1..65536 grids");
+  for (int i = 0; i < count; ++i) {
+    ss_grid g = grids[i];
+    if (!g) return fail(SS_ERR_ARG, "ss_batch_create: grid %d is null", i);
+    if (g->ndim != 2) return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d is not 2D", i);
+    if (!g->has_model) return fail(SS_ERR_STATE, "ss_batch_create: grid %d has no model", i);
+    if (g->nf != 1) return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d has a two-field model", i);
+    if (!g->ws) return fail(SS_ERR_STATE, "ss_batch_create: grid %d has no workspace", i);
+    if (!batch_size_ok(g->n[0]) || !batch_size_ok(g->n[1]))
+      return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d size outside [64, 2048]", i);
+    if (g->dtype != grids[0]->dtype) return fail(SS_ERR_ARG, "ss_batch_create: mixed dtypes");
+    if (g->stream != grids[0]->stream) return fail(SS_ERR_ARG, "ss_batch_create: mixed streams");
+  }
+  ss_batch b = new (std::nothrow) ss_batch_s();
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_create: out of host memory");
+  b->grids.assign(grids, grids + count);
+  b->dtype = grids[0]->dtype;
+  b->stream = grids[0]->stream;
+  for (int i = 0; i < count; ++i) b->order.push_back(i);
+  // largest members first: their tiles start early, the small ones fill the tail
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int a, int c) { return b->grids[a]->cells() > b->grids[c]->cells(); });
+  *out = b;
+  return SS_OK;
+}
+
+ss_status ss_batch_workspace_size(ss_batch b, size_t* bytes) {
+  if (!b || !bytes) return fail(SS_ERR_ARG, "ss_batch_workspace_size: null argument");
+  *bytes = 2 * batch_table_bytes(b);
+  return SS_OK;
+}
+
+ss_status ss_batch_bind_workspace(ss_batch b, void* device_ptr, size_t bytes) {
+  if (!b || !device_ptr) return fail(SS_ERR_ARG, "ss_batch_bind_workspace: null argument");
+  if (((uintptr_t)device_ptr) % kAlign) return fail(SS_ERR_ARG, "ss_batch_bind_workspace: pointer not 256-byte aligned");
+  if (bytes < 2 * batch_table_bytes(b)) return fail(SS_ERR_ARG, "ss_batch_bind_workspace: workspace too small");
+  b->ws = device_ptr;
+  b->ws_bytes = bytes;
+  b->uploaded = false;
+  return SS_OK;
+}
+
+ss_status ss_batch_autotune(ss_batch b, int reps) {
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_autotune: null batch");
+  if (reps < 1 || reps > 1000) return fail(SS_ERR_ARG, "ss_batch_autotune: reps must be in [1, 1000]");
+  if (!b->ws) return fail(SS_ERR_STATE, "ss_batch_autotune: bind the batch workspace first");
+  int best_t = 0;
+  float best = 1e30f;
+  for (int threads : {128, 256, 512}) {
+    std::vector<ss::BatchMember> t1, t2;
+    int xt, kt;
+    uint32_t lx, lk;
+    if (!build_batch_table(b, threads, t1, t2, xt, kt, lx, lk)) continue;
+    SS_TRY(batch_upload(b, threads));
+    auto launch = [&](ss::LaunchEvents ev) {
+      // x launch and k launch (on the tuning table) timed together
+      ss::LaunchEvents ex, ek;
+      ex.start = ev.start;
+      ek.stop = ev.stop;
+      return b->dtype == SS_F64 ? batch_launch_step<double>(b, true, ex, ek)
+                                : batch_launch_step<float>(b, true, ex, ek);
+    };
+    float ms;
+    SS_TRY(time_launch(b->grids[0], launch, reps, &ms));
+    if (ms < best) {
+      best = ms;
+      best_t = threads;
+    }
+  }
+  if (!best_t) return fail(SS_ERR_UNSUPPORTED, "ss_batch_autotune: no block size fits every member");
+  return batch_upload(b, best_t);
+}
+
+ss_status ss_batch_step_n(ss_batch b, int64_t nsteps) {
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_step_n: null batch");
+  if (nsteps < 0) return fail(SS_ERR_ARG, "ss_batch_step_n: nsteps must be >= 0");
+  if (!b->ws) return fail(SS_ERR_STATE, "ss_batch_step_n: bind the batch workspace first");
+  SS_TRY(batch_check_members(b));
+  if (!b->uploaded) SS_TRY(batch_upload(b, b->threads));
+  for (int64_t i = 0; i < nsteps; ++i) SS_TRY(batch_step_once(b));
+  for (ss_grid g : b->grids) g->log_count += nsteps;
+  return SS_OK;
+}
+
+ss_status ss_batch_capture(ss_batch b, int64_t nsteps) {
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_capture: null batch");
+  if (nsteps < 1) return fail(SS_ERR_ARG, "ss_batch_capture: nsteps must be >= 1");
+  if (!b->stream) return fail(SS_ERR_ARG, "ss_batch_capture: the null stream cannot be captured");
+  if (!b->ws) return fail(SS_ERR_STATE, "ss_batch_capture: bind the batch workspace first");
+  SS_TRY(batch_check_members(b));
+  if (!b->uploaded) SS_TRY(batch_upload(b, b->threads));
+  if (b->exec) {
+    hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  SS_TRY(hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"));
+  ss_status st = SS_OK;
+  for (int64_t i = 0; st == SS_OK && i < nsteps; ++i) st = batch_step_once(b);
+  hipGraph_t graph = nullptr;
+  ss_status st2 = hip_check(hipStreamEndCapture(b->stream, &graph), "hipStreamEndCapture");
+  if (st != SS_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (st2 != SS_OK) return st2;
+  b->graph = graph;
+  SS_TRY(hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate"));
+  b->graph_steps = nsteps;
+  return SS_OK;
+}
+
+ss_status ss_batch_launch(ss_batch b) {
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_launch: null batch");
+  if (!b->exec) return fail(SS_ERR_STATE, "ss_batch_launch: nothing captured");
+  SS_TRY(batch_check_members(b));
+  SS_TRY(hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch"));
+  for (ss_grid g : b->grids) g->log_count += b->graph_steps;
+  return SS_OK;
+}
+
+ss_status ss_batch_info(ss_batch b, int info[3]) {
+  if (!b || !info) return fail(SS_ERR_ARG, "ss_batch_info: null argument");
+  info[0] = b->threads;
+  info[1] = b->x_total;
+  info[2] = b->k_total;
+  return SS_OK;
+}
+
+ss_status ss_batch_destroy(ss_batch b) {
+  if (!b) return SS_OK;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  delete b;
   return SS_OK;
 }
 

@@ -9,6 +9,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "ss_batch.hpp"
 #include "ss_kernels.hpp"
 
 namespace ss {
@@ -86,6 +87,12 @@ inline int k_tile_default(int esz, int nl, int64_t nlines, bool three_d) {
   while (l > 1 && !k_tile_ok(esz, nl, nlines, three_d, l)) l /= 2;
   return l;
 }
+
+// batched (grouped) launches: `threads` per block, `blocks` blocks
+template <typename T>
+hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev);
+template <typename T>
+hipError_t run_batch_k(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev);
 
 template <typename T>
 hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s, LaunchEvents ev);
@@ -185,7 +192,18 @@ hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev) {
   return hipErrorInvalidValue;
 }
 
+template <typename T>
+hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev) {
+  return launch_with(xpass_grouped<T>, dim3(blocks), dim3(threads), lds, s, ev, b);
+}
+template <typename T>
+hipError_t run_batch_k(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev) {
+  return launch_with(kpass_grouped<T>, dim3(blocks), dim3(threads), lds, s, ev, b);
+}
+
 #define SS_INSTANTIATE(T)                                                                  \
+  template hipError_t run_batch_x<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
+  template hipError_t run_batch_k<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t, LaunchEvents); \
   template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t, LaunchEvents);  \
   template hipError_t run_kpass<T>(int, KArgs, hipStream_t, LaunchEvents);

@@ -178,7 +178,8 @@ __device__ __forceinline__ void stockham_stage(C<T> (&c)[NL][8], C<T>* const (&x
     const int j = t + q * S;
     const int k = j & (NS - 1);
     C<T> w[R];
-    if constexpr (NS > 1) {
+    if constexpr (NS > 1 && NL > 1) {
+      // several lines share the powers: form them once
       w[1] = opaque<T>(DIR > 0 ? cconj<T>(w1) : w1);
 #pragma unroll
       for (int r = 2; r < R; ++r) w[r] = cmul<T>(w[r >> 1], w[r - (r >> 1)]);
@@ -188,9 +189,18 @@ __device__ __forceinline__ void stockham_stage(C<T> (&c)[NL][8], C<T>* const (&x
       C<T> v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = c[l][q + r * Q];
-      if constexpr (NS > 1) {
+      if constexpr (NS > 1 && NL > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) v[r] = cmul<T>(v[r], w[r]);
+      } else if constexpr (NS > 1) {
+        // one line: walk the powers while applying them (two live values)
+        const C<T> wb = opaque<T>(DIR > 0 ? cconj<T>(w1) : w1);
+        C<T> wr = wb;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[r] = cmul<T>(v[r], wr);
+          if (r + 1 < R) wr = cmul<T>(wr, wb);
+        }
       }
       dftR<T, DIR, R>(v);
       if constexpr (LAST) {

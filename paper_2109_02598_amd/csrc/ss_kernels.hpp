@@ -35,6 +35,10 @@ enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2 };
 
 constexpr int LDS_BUDGET = 160 * 1024;
 
+#ifndef SS_KWAVES
+#define SS_KWAVES 2
+#endif
+
 // LDS geometry shared by the kernels and the host-side launch planning
 // (esz = bytes of one complex element: 8 for FP32, 16 for FP64).
 constexpr int padded_len_e(int esz, int n) { return esz == 16 ? n + (n >> 3) + 1 : n + (n >> 4) + 1; }
@@ -56,7 +60,7 @@ constexpr int y_reg(int esz, int ny) {
 }
 constexpr int64_t y_lds(int esz, int ny, int lines) { return (int64_t)lines * y_reg(esz, ny) * esz; }
 constexpr int k_reg(int esz, int nl) { return padded_len_e(esz, nl); }
-constexpr int64_t k_lds(int esz, int nl, int lines) { return (int64_t)lines * 2 * k_reg(esz, nl) * esz; }
+constexpr int64_t k_lds(int esz, int nl, int lines) { return (int64_t)lines * k_reg(esz, nl) * esz; }
 
 // ---------------------------------------------------------------------------
 // x pass
@@ -124,20 +128,19 @@ struct XThreads {
   static constexpr int value = sizeof(T) == 8 ? 512 : 1024;
 };
 
+// One x-pass tile: rows blk*R .. blk*R+R-1 of the spectral layout.  The
+// block's threads form G = blockDim/S groups of S threads, G dividing R/2.
 template <typename T, int NX, int NF, int MODE, int NLM>
-__global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a) {
+__device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* lds) {
   typedef XCfg<T, NX> K;
   constexpr int S = K::S, H = K::H, HB = K::HB;
   constexpr int REG = K::reg_for(NF);
-  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
-  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
 
   const int R = a.rows_per_block;
   const int P = R >> 1;
   const int G = (int)blockDim.x / S;         // thread groups (lines in flight)
   const int tid = threadIdx.x;
   const int g = tid / S, t = tid - g * S;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
   const int64_t s0 = blk * R;
   const int64_t rows = a.rows;
   const Twiddles<T, NX> tw = make_twiddles<T, NX>(t);
@@ -274,6 +277,13 @@ __global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a
   }
 }
 
+template <typename T, int NX, int NF, int MODE, int NLM>
+__global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a) {
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  xpass_body<T, NX, NF, MODE, NLM>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap),
+                                   reinterpret_cast<C<T>*>(ss_dyn_lds));
+}
+
 // ---------------------------------------------------------------------------
 // y pass (3D): complex FFT along y of T[kx][y][z] on chunks of R
 // consecutive z; block = (kx, z chunk).  In place is allowed.
@@ -393,17 +403,16 @@ struct KCfg {
   static constexpr int REG = k_reg(ESZ, NL);
 };
 
+// One k-space tile: lines bx*L .. bx*L+L-1 of field `fi`.
 template <typename T, int NL>
-__global__ void __launch_bounds__(512) kpass_kernel(KArgs a) {
+__device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>* lds) {
   typedef KCfg<T, NL> K;
   constexpr int S = K::S, REG = K::REG;
-  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
-  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
   const int tid = threadIdx.x;
   const int ls = tid / S, t = tid - ls * S;
-  const KField F = blockIdx.y == 0 ? a.fld[0] : a.fld[1];
-  const int line0 = blockIdx.x * a.lines_per_block;
-  const int slot = line0 + ls;                     // global line slot
+  const KField F = fi == 0 ? a.fld[0] : a.fld[1];
+  const int line0 = bx * a.lines_per_block;
+  const int slot = line0 + ls;               // global line slot
   const bool packed_block = line0 < a.J;     // block holds kx = 0 lines
   // plane-0 slots are ordered so that each line sits next to its mirror
   int kxi, kyi;
@@ -422,15 +431,16 @@ __global__ void __launch_bounds__(512) kpass_kernel(KArgs a) {
   C<T>* st = (C<T>*)F.state + lbase;
   const C<T>* gn = (const C<T>*)F.nonlin + lbase;
 
-  C<T> c[2][8];
+  C<T> ct[1][8], cg[1][8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    c[0][e] = st[t + e * S];
-    c[1][e] = gn[t + e * S];
-  }
-  C<T>* x[2] = {lds + (ls * 2) * REG, lds + (ls * 2 + 1) * REG};
+  for (int e = 0; e < 8; ++e) ct[0][e] = st[t + e * S];
+  // one LDS region per line serves all three transforms in turn
+  C<T>* x[1] = {lds + ls * REG};
   const Twiddles<T, NL> tw = make_twiddles<T, NL>(t);
-  fft_lines<T, NL, -1, 2>(c, x, t, tw);
+  fft_lines<T, NL, -1, 1>(ct, x, t, tw);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) cg[0][e] = gn[t + e * S];
+  fft_lines<T, NL, -1, 1>(cg, x, t, tw);
 
   // wavenumbers: k_last from the position, k_mid from kyi (3D), k_x from kxi
   const double kxv = (double)kxi * a.sx;
@@ -442,55 +452,62 @@ __global__ void __launch_bounds__(512) kpass_kernel(KArgs a) {
   const double klast_s = a.three_d ? a.sz : a.sy;
 
   if (packed_block) {
-    // the kx = 0 lines hold S(0) + i S(Nx/2): split with the mirror mode
+    // The kx = 0 lines hold S(0) + i S(Nx/2).  With the mirror mode m(-k):
+    //   U = (a0+an)/2 C + (a0-an)/2 conj(C(-k)) + (b0+bn)/2 D + (b0-bn)/2 conj(D(-k))
+    // (C, D: transformed state and nonlinear term).  The two halves are
+    // formed one after the other through the single LDS region.
+    const bool packed = slot < a.J;
+    int mls = ls;
+    if (a.three_d && (slot >> 1) != 0) mls = ls ^ 1;
+    const C<T>* xm = lds + mls * REG;
+    const double kny = (double)(a.nx / 2) * a.sx;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      x[0][pidx<T>(t + e * S)] = c[0][e];
-      x[1][pidx<T>(t + e * S)] = c[1][e];
-    }
+    for (int e = 0; e < 8; ++e) x[0][pidx<T>(t + e * S)] = ct[0][e];
     __syncthreads();
-    if (slot < a.J) {
-      int mslot_ls = ls;
-      if (a.three_d && (slot >> 1) != 0) mslot_ls = ls ^ 1;
-      C<T>* xm0 = lds + (mslot_ls * 2) * REG;
-      C<T>* xm1 = lds + (mslot_ls * 2 + 1) * REG;
-      const double kny = (double)(a.nx / 2) * a.sx;
+    if (packed) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         __builtin_amdgcn_sched_barrier(0);
         const int p = t + e * S;
-        const int pm = (NL - p) & (NL - 1);
         const int m = p <= NL / 2 ? p : p - NL;
         const double kl = (double)m * klast_s;
         const double k2_0 = kmid2 + kl * kl;
-        const double k2_n = k2_0 + kny * kny;
         T a0, b0, an, bn;
         etd1_coeffs<T>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
-        etd1_coeffs<T>(F, k2_n, a.dt, a.a_scale, a.b_scale, an, bn);
-        const C<T> cm = cconj<T>(xm0[pidx<T>(pm)]);
-        const C<T> dm = cconj<T>(xm1[pidx<T>(pm)]);
+        etd1_coeffs<T>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
+        const C<T> cm = cconj<T>(xm[pidx<T>((NL - p) & (NL - 1))]);
         const T ap = (T)0.5 * (a0 + an), am = (T)0.5 * (a0 - an);
-        const T bp = (T)0.5 * (b0 + bn), bmn = (T)0.5 * (b0 - bn);
-        C<T> u;
-        u.x = ap * c[0][e].x + am * cm.x + bp * c[1][e].x + bmn * dm.x;
-        u.y = ap * c[0][e].y + am * cm.y + bp * c[1][e].y + bmn * dm.y;
-        c[0][e] = u;
+        ct[0][e] = mk<T>(ap * ct[0][e].x + am * cm.x, ap * ct[0][e].y + am * cm.y);
       }
-      if (a.mass_log && kyi == 0 && t == 0 && a.log_index < a.log_capacity)
-        a.mass_log[a.log_index * a.nf + blockIdx.y] = (double)c[0][0].x;
-    } else {
+    }
+    __syncthreads();
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        __builtin_amdgcn_sched_barrier(0);
-        const int p = t + e * S;
-        const int m = p <= NL / 2 ? p : p - NL;
-        const double kl = (double)m * klast_s;
+    for (int e = 0; e < 8; ++e) x[0][pidx<T>(t + e * S)] = cg[0][e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __builtin_amdgcn_sched_barrier(0);
+      const int p = t + e * S;
+      const int m = p <= NL / 2 ? p : p - NL;
+      const double kl = (double)m * klast_s;
+      if (packed) {
+        const double k2_0 = kmid2 + kl * kl;
+        T a0, b0, an, bn;
+        etd1_coeffs<T>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
+        etd1_coeffs<T>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
+        const C<T> dm = cconj<T>(xm[pidx<T>((NL - p) & (NL - 1))]);
+        const T bp = (T)0.5 * (b0 + bn), bmn = (T)0.5 * (b0 - bn);
+        ct[0][e] = mk<T>(ct[0][e].x + bp * cg[0][e].x + bmn * dm.x,
+                         ct[0][e].y + bp * cg[0][e].y + bmn * dm.y);
+      } else {
         const double k2 = kxv * kxv + kmid2 + kl * kl;
         T av, bv;
         etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
-        c[0][e] = mk<T>(av * c[0][e].x + bv * c[1][e].x, av * c[0][e].y + bv * c[1][e].y);
+        ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
       }
     }
+    if (packed && a.mass_log && kyi == 0 && t == 0 && a.log_index < a.log_capacity)
+      a.mass_log[a.log_index * a.nf + fi] = (double)ct[0][0].x;
     __syncthreads();
   } else {
 #pragma unroll
@@ -502,17 +519,19 @@ __global__ void __launch_bounds__(512) kpass_kernel(KArgs a) {
       const double k2 = kxv * kxv + kmid2 + kl * kl;
       T av, bv;
       etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
-      c[0][e] = mk<T>(av * c[0][e].x + bv * c[1][e].x, av * c[0][e].y + bv * c[1][e].y);
+      ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
     }
   }
 
-  C<T> c1[1][8];
+  fft_lines<T, NL, +1, 1>(ct, x, t, tw);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) c1[0][e] = c[0][e];
-  C<T>* x1[1] = {x[0]};
-  fft_lines<T, NL, +1, 1>(c1, x1, t, tw);
-#pragma unroll
-  for (int e = 0; e < 8; ++e) st[t + e * S] = c1[0][e];
+  for (int e = 0; e < 8; ++e) st[t + e * S] = ct[0][e];
+}
+
+template <typename T, int NL>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SS_KWAVES))) kpass_kernel(KArgs a) {
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  kpass_body<T, NL>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
 
 }  // namespace ss

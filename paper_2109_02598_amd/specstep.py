@@ -64,6 +64,15 @@ def lib():
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
         "ss_set_stream": [vp, vp],
         "ss_destroy_grid": [vp],
+        "ss_batch_create": [ctypes.POINTER(vp), cint, ctypes.POINTER(vp)],
+        "ss_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "ss_batch_bind_workspace": [vp, vp, ctypes.c_size_t],
+        "ss_batch_autotune": [vp, cint],
+        "ss_batch_step_n": [vp, i64],
+        "ss_batch_capture": [vp, i64],
+        "ss_batch_launch": [vp],
+        "ss_batch_info": [vp, ctypes.POINTER(cint)],
+        "ss_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -177,6 +186,49 @@ def ss_destroy_grid(h):
     _check(lib().ss_destroy_grid(h))
 
 
+def ss_batch_create(handles):
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    b = ctypes.c_void_p()
+    _check(lib().ss_batch_create(arr, len(handles), ctypes.byref(b)))
+    return b.value
+
+
+def ss_batch_workspace_size(b):
+    n = ctypes.c_size_t()
+    _check(lib().ss_batch_workspace_size(b, ctypes.byref(n)))
+    return n.value
+
+
+def ss_batch_bind_workspace(b, ptr, nbytes):
+    _check(lib().ss_batch_bind_workspace(b, ptr, nbytes))
+
+
+def ss_batch_autotune(b, reps=5):
+    _check(lib().ss_batch_autotune(b, int(reps)))
+
+
+def ss_batch_step_n(b, nsteps):
+    _check(lib().ss_batch_step_n(b, int(nsteps)))
+
+
+def ss_batch_capture(b, nsteps):
+    _check(lib().ss_batch_capture(b, int(nsteps)))
+
+
+def ss_batch_launch(b):
+    _check(lib().ss_batch_launch(b))
+
+
+def ss_batch_info(b):
+    i = (ctypes.c_int * 3)()
+    _check(lib().ss_batch_info(b, i))
+    return list(i)
+
+
+def ss_batch_destroy(b):
+    _check(lib().ss_batch_destroy(b))
+
+
 def ss_last_error():
     return lib().ss_last_error().decode()
 
@@ -241,14 +293,15 @@ class Grid:
             if tuple(t.shape) != self.shape:
                 raise ValueError("field shape %s != grid shape %s" % (tuple(t.shape), self.shape))
             ss_set_field(self.h, field, t.data_ptr(), True)
-            self._keep = t           # alive until the stream has consumed it
-            torch.cuda.current_stream(self.device).synchronize()
+            torch.cuda.synchronize(self.device)   # t must outlive the copy
 
     def get_field(self, field, out=None):
         torch = self.torch
         if out is None:
             out = torch.empty(self.shape, dtype=self.tdtype, device=self.device)
         ss_get_field(self.h, field, out.data_ptr(), True)
+        if self.stream != torch.cuda.current_stream(self.device).cuda_stream:
+            torch.cuda.synchronize(self.device)
         return out
 
     def get_field_host(self, field):
@@ -285,6 +338,43 @@ class Grid:
         if getattr(self, "h", None):
             ss_destroy_grid(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several 2D single-field grids advanced together by grouped launches."""
+
+    def __init__(self, grids, autotune=True, reps=3):
+        import torch
+        self.grids = list(grids)
+        self.b = ss_batch_create([g.h for g in self.grids])
+        nbytes = ss_batch_workspace_size(self.b)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.grids[0].device)
+        ss_batch_bind_workspace(self.b, self.workspace.data_ptr(), nbytes)
+        if autotune:
+            ss_batch_autotune(self.b, reps)
+
+    def step(self, nsteps):
+        ss_batch_step_n(self.b, nsteps)
+
+    def capture(self, nsteps):
+        ss_batch_capture(self.b, nsteps)
+
+    def launch(self):
+        ss_batch_launch(self.b)
+
+    def info(self):
+        return ss_batch_info(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            ss_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -95,3 +95,38 @@ def test_null_handles(L):
     assert L.ss_destroy_grid(None) == ss.SS_OK
     out = ctypes.c_void_p()
     assert L.ss_create_grid(2, None, None, 8, None, ctypes.byref(out)) == ss.SS_ERR_ARG
+
+
+def test_batch_validation(L):
+    fake = 1 << 40
+    hs = []
+    try:
+        for n, model in [((64, 128), 2), ((256, 256), 2), ((32, 64), 2)]:
+            h = ss.ss_create_grid(n, (1, 1), ss.SS_F32)
+            ss.ss_set_model(h, model, (1, 1, 1, 1), 0.1)
+            ss.ss_bind_workspace(h, fake, ss.ss_workspace_size(h))
+            hs.append(h)
+        b = ss.ss_batch_create(hs[:2])
+        assert ss.ss_batch_workspace_size(b) >= 2 * 2 * 100
+        assert code_of(ss.ss_batch_step_n, b, 1) == ss.SS_ERR_STATE     # no workspace
+        assert code_of(ss.ss_batch_capture, b, 1) == ss.SS_ERR_ARG      # null stream
+        assert code_of(ss.ss_batch_launch, b) == ss.SS_ERR_STATE
+        ss.ss_batch_destroy(b)
+        assert code_of(ss.ss_batch_create, hs) == ss.SS_ERR_UNSUPPORTED  # 32 < 64
+        h64 = ss.ss_create_grid((64, 64), (1, 1), ss.SS_F64)
+        ss.ss_set_model(h64, 2, (1, 1, 1, 1), 0.1)
+        ss.ss_bind_workspace(h64, fake, ss.ss_workspace_size(h64))
+        hs.append(h64)
+        assert code_of(ss.ss_batch_create, [hs[0], h64]) == ss.SS_ERR_ARG  # mixed dtype
+        hgs = ss.ss_create_grid((64, 64), (1, 1), ss.SS_F32)
+        ss.ss_set_model(hgs, 4, (0.16, 0.08, 0.035, 0.065), 1.0)
+        ss.ss_bind_workspace(hgs, fake, ss.ss_workspace_size(hgs))
+        hs.append(hgs)
+        assert code_of(ss.ss_batch_create, [hs[0], hgs]) == ss.SS_ERR_UNSUPPORTED  # two fields
+        h3 = ss.ss_create_grid((64, 64, 64), (1, 1, 1), ss.SS_F32)
+        ss.ss_set_model(h3, 2, (1, 1, 1, 1), 0.1)
+        hs.append(h3)
+        assert code_of(ss.ss_batch_create, [hs[0], h3]) == ss.SS_ERR_UNSUPPORTED  # 3D
+    finally:
+        for h in hs:
+            ss.ss_destroy_grid(h)

@@ -1,0 +1,129 @@
+"""Batched step: many uneven Cahn-Hilliard grids in grouped launches.
+
+Each member must match the plain single-grid path bit for bit (both run
+the same per-line code, and multiply-adds are contracted per source
+expression, not per inlining context), match the FP64 oracle to the
+parity bar, and a captured HIP graph replayed several times (with eager
+work and synchronisations in between) must give exactly what eager
+stepping gives.
+"""
+
+
+def same_as_plain(got, want, dtype):
+    return np.array_equal(got, want)
+import numpy as np
+import pytest
+
+from oracle import spectral
+from paper_2109_02598_amd import inputs
+from tests._common import TOL, as_input, need_gpu, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def make_members(sizes, dtype, seed0=4000):
+    ws = []
+    for i, (nx, ny) in enumerate(sizes):
+        m = 0.5 + 1.5 * inputs.uniform(77, 2 * len(sizes))[2 * i]
+        k = 0.5 + 1.5 * inputs.uniform(77, 2 * len(sizes))[2 * i + 1]
+        f = inputs.uniform_field(seed0 + i, (ny, nx), -0.05, 0.05)
+        ws.append(inputs.Workload("m%d" % i, "cahn_hilliard", (nx, ny), (1.0, 1.0), 0.1,
+                                  (m, k, 1.0, 1.0), 0, as_input([f], dtype)))
+    return ws
+
+
+def grids_for(specstep, ws, dtype, stream):
+    gs = []
+    for w in ws:
+        g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=w.dt, stream=stream)
+        g.set_field(0, w.fields[0].astype(np.float32) if dtype == "f32" else w.fields[0])
+        gs.append(g)
+    return gs
+
+
+SIZES = [(64, 64), (128, 64), (64, 256), (256, 256), (512, 128), (128, 128), (1024, 64), (64, 512)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_matches_plain_and_oracle(dtype):
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = make_members(SIZES, dtype)
+    steps = 20
+    plain = grids_for(specstep, ws, dtype, stream.cuda_stream)
+    for g in plain:
+        g.step(steps)
+    want_plain = [g.get_field(0).cpu().numpy() for g in plain]
+    gs = grids_for(specstep, ws, dtype, stream.cuda_stream)
+    b = specstep.Batch(gs, autotune=True, reps=2)
+    say("batch info (threads, x tiles, k tiles):", b.info())
+    b.step(steps)
+    torch.cuda.synchronize()
+    for i, (g, w) in enumerate(zip(gs, ws)):
+        got = g.get_field(0).cpu().numpy()
+        say("member", i, w.n, "vs plain rel %.3e" % rel_l2(got, want_plain[i]))
+        assert same_as_plain(got, want_plain[i], dtype), (i, w.n)
+        ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, steps)[0]
+        err = rel_l2(got, ref)
+        say("member", i, w.n, "rel_l2 %.3e" % err)
+        assert err <= TOL[dtype]
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_graph_replay_equals_eager(dtype):
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = make_members(SIZES[:5], dtype, seed0=4100)
+    eager = grids_for(specstep, ws, dtype, stream.cuda_stream)
+    be = specstep.Batch(eager, autotune=False)
+    graph = grids_for(specstep, ws, dtype, stream.cuda_stream)
+    bg = specstep.Batch(graph, autotune=False)
+    bg.capture(4)
+    for rep in range(3):
+        bg.launch()
+        be.step(4)
+        torch.cuda.synchronize()
+        # eager work on the side between replays
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        for a, c in zip(graph, eager):
+            assert np.array_equal(a.get_field(0).cpu().numpy(), c.get_field(0).cpu().numpy()), rep
+    be.close()
+    bg.close()
+
+
+def test_batch_64_uneven_members():
+    """The 64-member workload (sizes from {128, 256, 512, 1024}^2, M and kappa
+    in [0.5, 2)), FP32, autotuned, run through a captured graph: every
+    member equals the plain path; the smaller members also match the
+    oracle after 20 steps."""
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = inputs.cahn_hilliard_batch(count=64)
+    for w in ws:
+        w.fields = as_input(w.fields, "f32")
+    steps = 20
+    gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    b = specstep.Batch(gs, autotune=True, reps=2)
+    say("64-member batch info:", b.info(), "cells", sum(w.cells for w in ws))
+    b.capture(steps)
+    b.launch()
+    torch.cuda.synchronize()
+    checked = 0
+    for i, w in enumerate(ws):
+        got = gs[i].get_field(0).cpu().numpy()
+        if i % 8 == 0:
+            p = specstep.Grid(w.n, w.dx, dtype="f32", model=w.model, coef=w.coef, dt=w.dt,
+                              stream=stream.cuda_stream)
+            p.set_field(0, w.fields[0].astype(np.float32))
+            p.step(steps)
+            assert np.array_equal(got, p.get_field(0).cpu().numpy()), i
+            p.close()
+        if w.n[0] <= 256:
+            ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, steps)[0]
+            err = rel_l2(got, ref)
+            assert err <= TOL["f32"], (i, w.n, err)
+            checked += 1
+    say("oracle-checked members:", checked)
+    assert checked >= 8
+    b.close()
