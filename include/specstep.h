@@ -145,6 +145,31 @@ ss_status ss_autotune(ss_grid g, int reps);
 ss_status ss_get_tiles(ss_grid g, int tiles[4]);
 ss_status ss_set_tiles(ss_grid g, const int tiles[4]);
 
+/* ---- Reverse mode (adjoint) of ss_step_n ---------------------------------
+ *
+ * Gradients of a scalar J(q^T) of the fields after nsteps steps with
+ * respect to the initial fields and the model coefficients, by the exact
+ * transpose of the discrete step (the paper has no adjoint; the forward
+ * map is the scheme of Sec. 2.4.2, Eqs. 3-4 and 8).  Implemented for 2D
+ * Gray-Scott grids with axes up to 1024.  Memory: the fields are stored
+ * every K steps during the forward run; the backward sweep recomputes one
+ * segment of K steps at a time from its checkpoint.
+ *
+ * Sequence: ss_bind_adjoint_workspace(nsteps, K) -> set fields ->
+ * ss_step_n_checkpointed (the fields advance to q^T) -> ss_adjoint_n. */
+ss_status ss_adjoint_workspace_size(ss_grid g, int64_t nsteps, int K, size_t* bytes);
+ss_status ss_bind_adjoint_workspace(ss_grid g, void* device_ptr, size_t bytes, int64_t nsteps, int K);
+
+/* Advance nsteps (as ss_step_n) storing checkpoints every K steps. */
+ss_status ss_step_n_checkpointed(ss_grid g);
+
+/* Backward sweep.  dJ_dqT[f]: device (ny, nx) arrays of dJ/dq_f at the
+ * final step (grid dtype).  dJ_dq0[f]: device outputs, dJ/dq_f at step 0.
+ * dJ_dcoef: host double[4] receiving dJ/d(Du, Dv, F, k).  Synchronises
+ * the stream.  Errors: SS_ERR_STATE (no checkpointed forward run, or the
+ * coefficients or dt changed since), SS_ERR_ARG, SS_ERR_DEVICE. */
+ss_status ss_adjoint_n(ss_grid g, const void* const dJ_dqT[], void* const dJ_dq0[], double* dJ_dcoef);
+
 /* ---- Batched step: many independent grids in grouped launches ----------
  *
  * A batch advances several independent simulations together, the way the

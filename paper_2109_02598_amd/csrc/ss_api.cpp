@@ -83,6 +83,15 @@ struct ss_grid_s {
   // tiling of each pass (rows or lines per workgroup); 0 = not chosen yet
   int tile_x_step = 0, tile_x_io = 0, tile_y = 0, tile_k = 0;
 
+  // reverse mode: caller-owned workspace with checkpoints and segment
+  void* adj_ws = nullptr;
+  size_t adj_bytes = 0;
+  int64_t adj_nsteps = 0;
+  int adj_K = 0;
+  bool adj_forward_done = false;
+  double adj_coef[8] = {0};
+  double adj_dt = 0;
+
   int64_t cells() const { return n[0] * n[1] * n[2]; }
   size_t esz() const { return (size_t)dtype; }
   size_t field_bytes() const { return (size_t)cells() * esz(); }
@@ -624,6 +633,172 @@ ss_status batch_step_once(ss_batch b) {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// Reverse mode (Gray-Scott, 2D)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct AdjLayout {
+  size_t fb;            // one field array
+  int64_t nck;          // checkpoints
+  size_t ckpt, segT, segG, lam, la, mu, acc, dc, total;
+};
+
+AdjLayout adj_layout(ss_grid g, int64_t nsteps, int K) {
+  AdjLayout L;
+  L.fb = align_up(g->field_bytes());
+  L.nck = (nsteps + K - 1) / K;
+  size_t o = 0;
+  L.ckpt = o; o += (size_t)L.nck * 2 * L.fb;
+  L.segT = o; o += (size_t)K * 2 * L.fb;
+  L.segG = o; o += (size_t)K * 2 * L.fb;
+  L.lam = o; o += 2 * L.fb;
+  L.la = o; o += 2 * L.fb;
+  L.mu = o; o += 2 * L.fb;
+  L.acc = o; o += align_up(sizeof(double) * 2 * 2 * (size_t)(g->n[0] / 2));
+  L.dc = o; o += align_up(sizeof(double));
+  L.total = o;
+  return L;
+}
+
+char* adj_ptr(ss_grid g, size_t off) { return (char*)g->adj_ws + off; }
+void* ck_field(ss_grid g, const AdjLayout& L, int64_t i, int f) { return adj_ptr(g, L.ckpt + ((size_t)i * 2 + f) * L.fb); }
+void* seg_T(ss_grid g, const AdjLayout& L, int64_t j, int f) { return adj_ptr(g, L.segT + ((size_t)j * 2 + f) * L.fb); }
+void* seg_G(ss_grid g, const AdjLayout& L, int64_t j, int f) { return adj_ptr(g, L.segG + ((size_t)j * 2 + f) * L.fb); }
+
+template <typename T>
+ss_status kpass_to(ss_grid g, const void* st0, const void* st1, const void* g0, const void* g1, void* o0, void* o1) {
+  ss::KArgs a;
+  memset(&a, 0, sizeof(a));
+  const void* st[2] = {st0, st1};
+  const void* gn[2] = {g0, g1};
+  void* out[2] = {o0, o1};
+  for (int f = 0; f < 2; ++f) {
+    a.fld[f] = g->kf[f];
+    a.fld[f].state = const_cast<void*>(st[f]);
+    a.fld[f].nonlin = gn[f];
+    a.fld[f].out = out[f];
+  }
+  a.J = 1;
+  a.nlines = (int)(g->n[0] / 2);
+  a.nx = (int)g->n[0];
+  const double two_pi = 6.283185307179586476925286766559;
+  a.sx = two_pi / ((double)g->n[0] * g->dx[0]);
+  a.sy = two_pi / ((double)g->n[1] * g->dx[1]);
+  a.dt = g->dt;
+  a.a_scale = 1.0 / (double)g->n[1];
+  a.b_scale = 1.0 / (double)g->cells();
+  a.nf = 2;
+  ensure_tiles(g);
+  a.lines_per_block = g->tile_k;
+  return hip_check(ss::run_kpass<T>((int)g->n[1], a, g->stream, ss::LaunchEvents()), "k-space pass launch");
+}
+
+template <typename T>
+ss_status adjoint_t(ss_grid g, const void* const dqT[], void* const dq0[], double* dcoef) {
+  const AdjLayout L = adj_layout(g, g->adj_nsteps, g->adj_K);
+  const int64_t nsteps = g->adj_nsteps;
+  const int K = g->adj_K;
+  const int esz = esz_of(g);
+  const int nx = (int)g->n[0], ny = (int)g->n[1];
+  void* lam[2] = {adj_ptr(g, L.lam), adj_ptr(g, L.lam + L.fb)};
+  void* la[2] = {adj_ptr(g, L.la), adj_ptr(g, L.la + L.fb)};
+  void* mu[2] = {adj_ptr(g, L.mu), adj_ptr(g, L.mu + L.fb)};
+  double* acc = (double*)adj_ptr(g, L.acc);
+  double* dc = (double*)adj_ptr(g, L.dc);
+  const int kl = ss::kadj_tile(ny, nx / 2);
+  const int kblocks = (nx / 2) / kl;
+  SS_TRY(hip_check(hipMemsetAsync(acc, 0, sizeof(double) * 2 * 2 * kblocks, g->stream), "hipMemsetAsync"));
+  SS_TRY(hip_check(hipMemsetAsync(dc, 0, sizeof(double), g->stream), "hipMemsetAsync"));
+  // lambda^T = dJ/dq^T, in the spectral state layout
+  for (int f = 0; f < 2; ++f)
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_FWD, 1, nullptr, nullptr, lam[f], nullptr, dqT[f], nullptr,
+                           1.0 / (double)nx));
+  ss::KAdjArgs ka;
+  memset(&ka, 0, sizeof(ka));
+  for (int f = 0; f < 2; ++f) {
+    ka.fld[f].lam = lam[f];
+    ka.fld[f].out_a = la[f];
+    ka.fld[f].out_m = mu[f];
+    ka.fld[f].l[0] = g->kf[f].l[0];
+    ka.fld[f].l[1] = g->kf[f].l[1];
+  }
+  ka.nlines = nx / 2;
+  ka.lines_per_block = kl;
+  ka.nx = nx;
+  const double two_pi = 6.283185307179586476925286766559;
+  ka.sx = two_pi / ((double)nx * g->dx[0]);
+  ka.sy = two_pi / ((double)ny * g->dx[1]);
+  ka.dt = g->dt;
+  ka.a_scale = 1.0 / (double)ny;
+  ka.nxd = (double)nx;
+  ka.acc = acc;
+  ka.dc = dc;
+  ss::XAdjArgs xa;
+  memset(&xa, 0, sizeof(xa));
+  for (int f = 0; f < 2; ++f) {
+    xa.m[f] = mu[f];
+    xa.la[f] = la[f];
+    xa.out[f] = lam[f];
+  }
+  xa.rows = ny;
+  xa.rows_per_block = ss::xadj_tile(esz, nx, ny);
+  if (!xa.rows_per_block) return fail(SS_ERR_UNSUPPORTED, "ss_adjoint_n: grid too large for the adjoint x pass");
+  const int64_t nseg = L.nck;
+  for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int64_t s0 = sgi * K;
+    const int64_t s1 = (s0 + K < nsteps) ? s0 + K : nsteps;
+    // recompute the segment: states q^n and nonlinear terms g^n, n in [s0, s1)
+    for (int f = 0; f < 2; ++f)
+      SS_TRY(hip_check(hipMemcpyAsync(seg_T(g, L, 0, f), ck_field(g, L, sgi, f), g->field_bytes(),
+                                      hipMemcpyDeviceToDevice, g->stream), "checkpoint copy"));
+    for (int64_t n = s0; n < s1; ++n) {
+      const int64_t j = n - s0;
+      SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, 2, seg_T(g, L, j, 0), seg_T(g, L, j, 1), seg_G(g, L, j, 0),
+                             seg_G(g, L, j, 1), nullptr, nullptr, 1.0));
+      if (n + 1 < s1)
+        SS_TRY(kpass_to<T>(g, seg_T(g, L, j, 0), seg_T(g, L, j, 1), seg_G(g, L, j, 0), seg_G(g, L, j, 1),
+                           seg_T(g, L, j + 1, 0), seg_T(g, L, j + 1, 1)));
+    }
+    // sweep the segment backwards
+    for (int64_t n = s1 - 1; n >= s0; --n) {
+      const int64_t j = n - s0;
+      for (int f = 0; f < 2; ++f) {
+        ka.fld[f].q = seg_T(g, L, j, f);
+        ka.fld[f].g = seg_G(g, L, j, f);
+        xa.q[f] = seg_T(g, L, j, f);
+      }
+      SS_TRY(hip_check(ss::run_kadj<T>(ny, ka, g->stream), "adjoint k-space launch"));
+      SS_TRY(hip_check(ss::run_xadj<T>(nx, xa, g->stream), "adjoint x launch"));
+    }
+  }
+  for (int f = 0; f < 2; ++f)
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_INV, 1, lam[f], nullptr, nullptr, nullptr, nullptr, dq0[f], 1.0));
+  std::vector<double> hacc((size_t)2 * 2 * kblocks);
+  double hdc = 0;
+  SS_TRY(hip_check(hipMemcpyAsync(hacc.data(), acc, sizeof(double) * hacc.size(), hipMemcpyDeviceToHost, g->stream),
+                   "gradient copy"));
+  SS_TRY(hip_check(hipMemcpyAsync(&hdc, dc, sizeof(double), hipMemcpyDeviceToHost, g->stream), "gradient copy"));
+  SS_TRY(hip_check(hipStreamSynchronize(g->stream), "ss_adjoint_n: synchronise"));
+  double S0[2] = {0, 0}, S1[2] = {0, 0};
+  for (int f = 0; f < 2; ++f)
+    for (int b = 0; b < kblocks; ++b) {
+      S0[f] += hacc[2 * ((size_t)f * kblocks + b)];
+      S1[f] += hacc[2 * ((size_t)f * kblocks + b) + 1];
+    }
+  // S_j = Nx * acc_j (the kernel sums w (Nx dA P' + dB Q') with P' and Q'
+  // built from the /Nx-scaled spectra); inner products carry 1/N.
+  const double scale = (double)nx / (double)g->cells();
+  dcoef[0] = -S1[0] * scale;                              // Du: dL_u/dDu = -k^2
+  dcoef[1] = -S1[1] * scale;                              // Dv: dL_v/dDv = -k^2
+  dcoef[2] = -(S0[0] + S0[1]) * scale + hdc;              // F: dL/dF = -1 (both), dg_u/dF = 1
+  dcoef[3] = -S0[1] * scale;                              // k: dL_v/dk = -1
+  return SS_OK;
+}
+
+}  // namespace
+
 namespace {
 
 bool finite_all(const double* v, int n) {
@@ -1018,6 +1193,62 @@ ss_status ss_batch_destroy(ss_batch b) {
   if (b->graph) hipGraphDestroy(b->graph);
   delete b;
   return SS_OK;
+}
+
+ss_status ss_adjoint_workspace_size(ss_grid g, int64_t nsteps, int K, size_t* bytes) {
+  if (!g || !bytes) return fail(SS_ERR_ARG, "ss_adjoint_workspace_size: null argument");
+  if (!g->has_model) return fail(SS_ERR_STATE, "ss_adjoint_workspace_size: call ss_set_model first");
+  if (g->model != SS_GRAY_SCOTT || g->ndim != 2)
+    return fail(SS_ERR_UNSUPPORTED, "ss_adjoint_workspace_size: reverse mode is implemented for 2D Gray-Scott");
+  if (g->n[0] > 1024 || g->n[1] > 1024) return fail(SS_ERR_UNSUPPORTED, "ss_adjoint_workspace_size: axes up to 1024");
+  if (nsteps < 1 || K < 1) return fail(SS_ERR_ARG, "ss_adjoint_workspace_size: nsteps and K must be >= 1");
+  *bytes = adj_layout(g, nsteps, K).total;
+  return SS_OK;
+}
+
+ss_status ss_bind_adjoint_workspace(ss_grid g, void* device_ptr, size_t bytes, int64_t nsteps, int K) {
+  size_t need = 0;
+  SS_TRY(ss_adjoint_workspace_size(g, nsteps, K, &need));
+  if (!device_ptr) return fail(SS_ERR_ARG, "ss_bind_adjoint_workspace: null pointer");
+  if (((uintptr_t)device_ptr) % kAlign) return fail(SS_ERR_ARG, "ss_bind_adjoint_workspace: pointer not 256-byte aligned");
+  if (bytes < need) return fail(SS_ERR_ARG, "ss_bind_adjoint_workspace: %zu bytes given, %zu needed", bytes, need);
+  g->adj_ws = device_ptr;
+  g->adj_bytes = bytes;
+  g->adj_nsteps = nsteps;
+  g->adj_K = K;
+  g->adj_forward_done = false;
+  return SS_OK;
+}
+
+ss_status ss_step_n_checkpointed(ss_grid g) {
+  if (!g) return fail(SS_ERR_ARG, "ss_step_n_checkpointed: null grid");
+  if (!g->adj_ws) return fail(SS_ERR_STATE, "ss_step_n_checkpointed: bind the adjoint workspace first");
+  if (!g->ws || !g->field_set[0] || !g->field_set[1])
+    return fail(SS_ERR_STATE, "ss_step_n_checkpointed: workspace and both fields must be set");
+  const AdjLayout L = adj_layout(g, g->adj_nsteps, g->adj_K);
+  for (int64_t i = 0; i < g->adj_nsteps; ++i) {
+    if (i % g->adj_K == 0)
+      for (int f = 0; f < 2; ++f)
+        SS_TRY(hip_check(hipMemcpyAsync(ck_field(g, L, i / g->adj_K, f), g->state[f], g->field_bytes(),
+                                        hipMemcpyDeviceToDevice, g->stream), "checkpoint copy"));
+    SS_TRY(g->dtype == SS_F64 ? step_once<double>(g, nullptr) : step_once<float>(g, nullptr));
+  }
+  for (int i = 0; i < g->ncoef; ++i) g->adj_coef[i] = g->coef[i];
+  g->adj_dt = g->dt;
+  g->adj_forward_done = true;
+  return SS_OK;
+}
+
+ss_status ss_adjoint_n(ss_grid g, const void* const dJ_dqT[], void* const dJ_dq0[], double* dJ_dcoef) {
+  if (!g || !dJ_dqT || !dJ_dq0 || !dJ_dcoef) return fail(SS_ERR_ARG, "ss_adjoint_n: null argument");
+  if (!dJ_dqT[0] || !dJ_dqT[1] || !dJ_dq0[0] || !dJ_dq0[1]) return fail(SS_ERR_ARG, "ss_adjoint_n: null field pointer");
+  if (!g->adj_ws || !g->adj_forward_done)
+    return fail(SS_ERR_STATE, "ss_adjoint_n: run ss_step_n_checkpointed first");
+  for (int i = 0; i < g->ncoef; ++i)
+    if (g->adj_coef[i] != g->coef[i]) return fail(SS_ERR_STATE, "ss_adjoint_n: coefficients changed since the forward run");
+  if (g->adj_dt != g->dt) return fail(SS_ERR_STATE, "ss_adjoint_n: dt changed since the forward run");
+  return g->dtype == SS_F64 ? adjoint_t<double>(g, dJ_dqT, dJ_dq0, dJ_dcoef)
+                            : adjoint_t<float>(g, dJ_dqT, dJ_dq0, dJ_dcoef);
 }
 
 ss_status ss_destroy_grid(ss_grid g) {

@@ -9,6 +9,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "ss_adjoint.hpp"
 #include "ss_batch.hpp"
 #include "ss_kernels.hpp"
 
@@ -93,6 +94,28 @@ template <typename T>
 hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev);
 template <typename T>
 hipError_t run_batch_k(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev);
+
+// adjoint (Gray-Scott, 2D): sizes 8 .. 1024
+inline int xadj_tile(int esz, int nx, int64_t rows) {
+  int best = 0;
+  for (int r = 2; r <= 64; r *= 2) {
+    if (r > rows || rows % r) break;
+    if (xadj_lds(esz, nx, r) > (int64_t)LDS_BUDGET * 7 / 10) break;
+    if ((r / 2) * (nx / 8) > 512) break;
+    best = r;
+  }
+  if (!best && xadj_lds(esz, nx, 2) <= LDS_BUDGET) best = 2;
+  return best;
+}
+inline int kadj_tile(int nl, int64_t nlines) {
+  int l = 256 / (nl / 8) > 1 ? 256 / (nl / 8) : 1;
+  while (l > nlines) l /= 2;
+  return l;
+}
+template <typename T>
+hipError_t run_kadj(int nl, KAdjArgs a, hipStream_t s);
+template <typename T>
+hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s);
 
 template <typename T>
 hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s, LaunchEvents ev);
@@ -201,7 +224,51 @@ hipError_t run_batch_k(BatchArgs b, int threads, int blocks, uint32_t lds, hipSt
   return launch_with(kpass_grouped<T>, dim3(blocks), dim3(threads), lds, s, ev, b);
 }
 
+#define SS_ADJ_CASES(M) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024)
+
+template <typename T>
+hipError_t run_kadj(int nl, KAdjArgs a, hipStream_t s) {
+  constexpr int ESZ = (int)sizeof(C<T>);
+  const int L = a.lines_per_block;
+  const int threads = L * (nl / 8);
+  if (L < 1 || a.nlines % L || threads > 512) return hipErrorInvalidConfiguration;
+  const int64_t lds = kadj_lds(ESZ, nl, L, threads);
+  if (lds > LDS_BUDGET) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(a.nlines / L), 2), block((unsigned)threads);
+  switch (nl) {
+#define SS_CASE(n) \
+  case n:          \
+    return launch_with(kadj_kernel<T, n>, grid, block, (uint32_t)lds, s, LaunchEvents(), a);
+    SS_ADJ_CASES(SS_CASE)
+#undef SS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
+  constexpr int ESZ = (int)sizeof(C<T>);
+  const int R = a.rows_per_block;
+  if (R < 2 || a.rows % R) return hipErrorInvalidConfiguration;
+  const int64_t lds = xadj_lds(ESZ, nx, R);
+  if (lds > LDS_BUDGET) return hipErrorInvalidConfiguration;
+  int G = 512 / (nx / 8);
+  if (G > R / 2) G = R / 2;
+  if (G < 1) G = 1;
+  dim3 grid((unsigned)(a.rows / R)), block((unsigned)(G * (nx / 8)));
+  switch (nx) {
+#define SS_CASE(n) \
+  case n:          \
+    return launch_with(xadj_kernel<T, n>, grid, block, (uint32_t)lds, s, LaunchEvents(), a);
+    SS_ADJ_CASES(SS_CASE)
+#undef SS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
 #define SS_INSTANTIATE(T)                                                                  \
+  template hipError_t run_kadj<T>(int, KAdjArgs, hipStream_t);                          \
+  template hipError_t run_xadj<T>(int, XAdjArgs, hipStream_t);                          \
   template hipError_t run_batch_x<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_batch_k<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t, LaunchEvents); \

@@ -351,8 +351,9 @@ __global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
 // k-space pass: lines along the last axis (length NL), ETD1 update.
 // ---------------------------------------------------------------------------
 struct KField {
-  void* state;              // T, updated in place
+  void* state;              // T (read; written too unless `out` is set)
   const void* nonlin;       // G
+  void* out;                // where the new T goes (null: in place)
   double l[4];              // L(k^2) = l0 + l1 k^2 + l2 k^4 + l3 k^6
   double n[2];              // N(k^2) = n0 + n1 k^2
 };
@@ -428,8 +429,9 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     kyi = slot - kxi * a.J;
   }
   const int64_t lbase = ((int64_t)kxi * a.J + kyi) * NL;
-  C<T>* st = (C<T>*)F.state + lbase;
+  const C<T>* st = (const C<T>*)F.state + lbase;
   const C<T>* gn = (const C<T>*)F.nonlin + lbase;
+  C<T>* so = (C<T>*)(F.out ? F.out : F.state) + lbase;
 
   C<T> ct[1][8], cg[1][8];
 #pragma unroll
@@ -525,7 +527,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
 
   fft_lines<T, NL, +1, 1>(ct, x, t, tw);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) st[t + e * S] = ct[0][e];
+  for (int e = 0; e < 8; ++e) so[t + e * S] = ct[0][e];
 }
 
 template <typename T, int NL>

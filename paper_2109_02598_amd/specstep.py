@@ -64,6 +64,10 @@ def lib():
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
         "ss_set_stream": [vp, vp],
         "ss_destroy_grid": [vp],
+        "ss_adjoint_workspace_size": [vp, i64, cint, ctypes.POINTER(ctypes.c_size_t)],
+        "ss_bind_adjoint_workspace": [vp, vp, ctypes.c_size_t, i64, cint],
+        "ss_step_n_checkpointed": [vp],
+        "ss_adjoint_n": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(dbl)],
         "ss_batch_create": [ctypes.POINTER(vp), cint, ctypes.POINTER(vp)],
         "ss_batch_workspace_size": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "ss_batch_bind_workspace": [vp, vp, ctypes.c_size_t],
@@ -186,6 +190,29 @@ def ss_destroy_grid(h):
     _check(lib().ss_destroy_grid(h))
 
 
+def ss_adjoint_workspace_size(h, nsteps, K):
+    n = ctypes.c_size_t()
+    _check(lib().ss_adjoint_workspace_size(h, int(nsteps), int(K), ctypes.byref(n)))
+    return n.value
+
+
+def ss_bind_adjoint_workspace(h, ptr, nbytes, nsteps, K):
+    _check(lib().ss_bind_adjoint_workspace(h, ptr, nbytes, int(nsteps), int(K)))
+
+
+def ss_step_n_checkpointed(h):
+    _check(lib().ss_step_n_checkpointed(h))
+
+
+def ss_adjoint_n(h, dqT_ptrs, dq0_ptrs):
+    """Returns dJ/d(coefficients) as a list; writes dJ/dq0 to dq0_ptrs."""
+    a = (ctypes.c_void_p * 2)(*dqT_ptrs)
+    b = (ctypes.c_void_p * 2)(*dq0_ptrs)
+    c = (ctypes.c_double * 4)()
+    _check(lib().ss_adjoint_n(h, a, b, c))
+    return list(c)
+
+
 def ss_batch_create(handles):
     arr = (ctypes.c_void_p * len(handles))(*handles)
     b = ctypes.c_void_p()
@@ -260,6 +287,7 @@ class Grid:
         self.h = ss_create_grid(self.n, self.dx, self.ss_dtype, stream)
         self.model_id = MODELS[model] if isinstance(model, str) else int(model)
         self.nfields = NFIELDS[self.model_id]
+        self.dt = float(dt)
         ss_set_model(self.h, self.model_id, coef, dt)
         nbytes = ss_workspace_size(self.h)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -273,6 +301,7 @@ class Grid:
     def set_model(self, model, coef, dt):
         mid = MODELS[model] if isinstance(model, str) else int(model)
         ss_set_model(self.h, mid, coef, dt)
+        self.dt = float(dt)
         if mid != self.model_id:
             self.model_id = mid
             self.nfields = NFIELDS[mid]
@@ -324,6 +353,25 @@ class Grid:
 
     def step_profiled(self, nsteps):
         return ss_step_n_profiled(self.h, nsteps)
+
+    def bind_adjoint(self, nsteps, K):
+        """Allocate (torch) and bind the reverse-mode workspace."""
+        nbytes = ss_adjoint_workspace_size(self.h, nsteps, K)
+        self.adj_workspace = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        ss_bind_adjoint_workspace(self.h, self.adj_workspace.data_ptr(), nbytes, nsteps, K)
+        self.adj_cfg = (int(nsteps), int(K))
+
+    def step_checkpointed(self):
+        ss_step_n_checkpointed(self.h)
+
+    def adjoint(self, dqT):
+        """dqT: list of device tensors (dJ/dq at the final step).
+        Returns ([dJ/dq0 tensors], [dJ/dcoef])."""
+        torch = self.torch
+        dqT = [t.to(device=self.device, dtype=self.tdtype).contiguous() for t in dqT]
+        out = [torch.empty(self.shape, dtype=self.tdtype, device=self.device) for _ in dqT]
+        dc = ss_adjoint_n(self.h, [t.data_ptr() for t in dqT], [t.data_ptr() for t in out])
+        return out, dc
 
     def enable_mass_log(self, capacity):
         self.mass_buf = self.torch.zeros(capacity * self.nfields, dtype=self.torch.float64,
