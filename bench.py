@@ -46,9 +46,10 @@ def workloads():
 
 
 def kernel_source_hash():
+    """Hash of the device code of the single-grid step kernels."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2109_02598_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("ss_fft.hpp", "ss_kernels.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -92,6 +93,9 @@ def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     prof = g.step_profiled(profile_steps)
+    # mean launch time of each pass from back-to-back launches between two
+    # events (per-launch events add a completion fence to every launch)
+    prof["mean_b2b"] = {k: g.time_pass(k, 200) for k in prof}
     mass = g.mass_log()
     g.close()
     prof["tiles"] = tiles
@@ -150,20 +154,67 @@ def run_batch(steps=500, reps=3):
             "threads_per_block": info[0], "x_tiles": info[1], "k_tiles": info[2]}
 
 
+def run_adjoint(steps=200, K=20, dtype="f32"):
+    """Gray-Scott 512x512: checkpointed forward + reverse sweep, against the
+    plain forward of the same steps."""
+    import torch
+    from paper_2109_02598_amd import inputs, specstep
+    w = inputs.gray_scott_2d(n=512, steps=steps)
+    vstar = torch.from_numpy(inputs.gray_scott_target(n=512)).to("cuda")
+    g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=w.dt)
+    g.autotune(3)
+    g.bind_adjoint(steps, K)
+
+    def reset():
+        for i, f in enumerate(w.fields):
+            g.set_field(i, torch.from_numpy(f).to("cuda"))
+
+    reset()
+    g.step(steps)                       # warm-up
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    reset()
+    g.step_checkpointed()
+    (du0, dv0), dc = g.adjoint([torch.zeros(g.shape, device="cuda", dtype=g.tdtype),
+                                (g.get_field(1) - vstar.to(g.tdtype))])   # warm-up
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step_checkpointed()
+    vT = g.get_field(1)
+    (du0, dv0), dc = g.adjoint([torch.zeros(g.shape, device="cuda", dtype=g.tdtype),
+                                (vT - vstar.to(g.tdtype))])
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    g.close()
+    return {"workload": "gray_scott 512x512, %s, %d steps, checkpoint every %d" % (dtype, steps, K),
+            "ms_plain_forward": round(t_plain * 1e3, 3),
+            "ms_forward_plus_adjoint": round(t_adj * 1e3, 3),
+            "ratio_to_plain": round(t_adj / t_plain, 2),
+            "dJ_dcoef": [float(x) for x in dc]}
+
+
 def roofline(w, dtype, prof, traffic_rec):
     esz = 8 if dtype == "f64" else 4
     tiles = prof.pop("tiles", None)
-    per = {k: (v[0] / v[1]) for k, v in prof.items()}
+    b2b = prof.pop("mean_b2b")
+    evt = {k: (v[0] / v[1]) for k, v in prof.items()}
+    per = dict(b2b)
     dom = max(per, key=per.get)
     algo = algorithmic_bytes(dom, w, esz)
     achieved = algo / (per[dom] * 1e-3) / 1e9
     traffic = None
-    if traffic_rec and traffic_rec.get("kernel") == dom:
-        traffic = traffic_rec.get("bytes_per_launch")
+    if traffic_rec:
+        traffic = traffic_rec.get("bytes_per_launch", {}).get(dom)
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": algo,
             "mean_launch_us": {k: round(v * 1e3, 2) for k, v in per.items()},
+            "mean_launch_us_per_launch_events": {k: round(v * 1e3, 2) for k, v in evt.items()},
             "tiles": tiles}
 
 
@@ -204,6 +255,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiles")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-grid run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (for scaling "
@@ -248,6 +300,10 @@ def main():
                                not args.no_autotune)
     roof2 = roofline(w, other, prof2, load_traffic(args.workload, other))
     drift = float(abs(mass[-1][0] - mass[0][0])) if len(mass) else None
+    adj = None
+    if not args.no_adjoint:
+        print("bench: adjoint workload", file=sys.stderr, flush=True)
+        adj = run_adjoint()
     batch = None
     if not args.no_batch:
         print("bench: batched 64-grid workload", file=sys.stderr, flush=True)
@@ -272,6 +328,7 @@ def main():
                         "ms_per_step": round(ms2 / args.steps, 5), "roofline": roof2},
         "mass_drift_over_run": drift,
         "batched": batch,
+        "adjoint": adj,
         "wall_s_timed_region": round(wall, 4),
     }
     if not args.no_cpu:

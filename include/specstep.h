@@ -126,6 +126,14 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps);
 ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t* pass_count,
                              int npass);
 
+/* Mean duration in milliseconds of one launch of pass kind `pass` (as in
+ * ss_step_n_profiled) with the current tiling, from `nlaunch` back-to-back
+ * launches between two events on the grid's stream (after one warm-up
+ * launch).  The launches leave the fields untouched: the x pass reads the
+ * state and writes the scratch arrays, the k-space and y passes run on
+ * the scratch and staging arrays.  For measurement.  Synchronises. */
+ss_status ss_time_pass(ss_grid g, int pass, int nlaunch, double* mean_ms);
+
 /* Choose the work decomposition of every kernel of the step for this
  * grid by timing each valid tiling (rows or lines per workgroup) `reps`
  * times on the grid's stream and keeping the fastest.  The tilings do not

@@ -809,6 +809,73 @@ bool finite_all(const double* v, int n) {
 
 }  // namespace
 
+namespace {
+
+// Launch one pass of the current tiling in the autotuner's harmless form:
+// the x pass reads the state and writes the scratch arrays; the k-space
+// pass runs on the scratch arrays with the staging array as nonlinear term;
+// the y pass runs in place on scratch 0.
+template <typename T>
+ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
+  const int nx = (int)g->n[0];
+  const int64_t rows = g->n[1] * g->n[2];
+  if (pass == PASS_X) {
+    ss::XArgs a;
+    memset(&a, 0, sizeof(a));
+    a.spec_in[0] = g->state[0];
+    a.spec_in[1] = g->state[1];
+    a.spec_out[0] = g->scratch[0];
+    a.spec_out[1] = g->scratch[1];
+    a.rows = rows;
+    a.nz = (int)g->n[2];
+    a.ny = (int)g->n[1];
+    a.xcd_remap = 1;
+    a.scale = 1.0;
+    a.rows_per_block = g->tile_x_step;
+    for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+    return hip_check(ss::run_xpass<T>(nx, g->nf, ss::XMODE_STEP, g->nlm, a, g->stream, ev), "timed x pass");
+  }
+  if (pass == PASS_K) {
+    const int nl = nlast(g);
+    ss::KArgs a;
+    memset(&a, 0, sizeof(a));
+    for (int f = 0; f < g->nf; ++f) {
+      a.fld[f] = g->kf[f];
+      a.fld[f].state = g->scratch[f];
+      a.fld[f].nonlin = g->staging;
+    }
+    a.J = g->ndim == 3 ? (int)g->n[1] : 1;
+    a.nlines = (int)nlines_k(g);
+    a.nx = nx;
+    const double two_pi = 6.283185307179586476925286766559;
+    a.sx = two_pi / ((double)g->n[0] * g->dx[0]);
+    a.sy = two_pi / ((double)g->n[1] * g->dx[1]);
+    a.sz = g->ndim == 3 ? two_pi / ((double)g->n[2] * g->dx[2]) : 0.0;
+    a.dt = g->dt;
+    a.a_scale = 1.0 / nl;
+    a.b_scale = 1.0 / (double)g->cells();
+    a.nf = g->nf;
+    a.three_d = g->ndim == 3;
+    a.lines_per_block = g->tile_k;
+    return hip_check(ss::run_kpass<T>(nl, a, g->stream, ev), "timed k pass");
+  }
+  if (g->ndim == 3 && (pass == PASS_YINV || pass == PASS_YFWD)) {
+    ss::YArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = g->scratch[0];
+    a.out = g->scratch[0];
+    a.ny = (int)g->n[1];
+    a.nz = (int)g->n[2];
+    a.scale = 1.0;
+    a.lines_per_block = g->tile_y;
+    return hip_check(ss::run_ypass<T>((int)g->n[1], pass == PASS_YFWD ? -1 : +1, a, g->n[0] / 2, g->stream, ev),
+                     "timed y pass");
+  }
+  return fail(SS_ERR_ARG, "ss_time_pass: pass %d does not exist for this grid", pass);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ss_last_error(void) { return g_err.c_str(); }
@@ -988,6 +1055,35 @@ ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t
   }
   for (int e = 0; e < created; ++e) hipEventDestroy(pt->ev[e]);
   delete pt;
+  return st;
+}
+
+ss_status ss_time_pass(ss_grid g, int pass, int nlaunch, double* mean_ms) {
+  if (!g || !mean_ms) return fail(SS_ERR_ARG, "ss_time_pass: null argument");
+  if (nlaunch < 1 || nlaunch > 100000) return fail(SS_ERR_ARG, "ss_time_pass: nlaunch must be in [1, 100000]");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_time_pass: model and workspace must be set first");
+  ensure_tiles(g);
+  hipEvent_t e0, e1;
+  SS_TRY(hip_check(hipEventCreate(&e0), "hipEventCreate"));
+  ss_status st = hip_check(hipEventCreate(&e1), "hipEventCreate");
+  if (st != SS_OK) {
+    hipEventDestroy(e0);
+    return st;
+  }
+  auto one = [&]() {
+    return g->dtype == SS_F64 ? launch_timed_pass<double>(g, pass, ss::LaunchEvents())
+                              : launch_timed_pass<float>(g, pass, ss::LaunchEvents());
+  };
+  st = one();  // warm-up
+  if (st == SS_OK) st = hip_check(hipEventRecord(e0, g->stream), "hipEventRecord");
+  for (int i = 0; st == SS_OK && i < nlaunch; ++i) st = one();
+  if (st == SS_OK) st = hip_check(hipEventRecord(e1, g->stream), "hipEventRecord");
+  if (st == SS_OK) st = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+  float ms = 0.f;
+  if (st == SS_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  if (st == SS_OK) *mean_ms = (double)ms / nlaunch;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
   return st;
 }
 

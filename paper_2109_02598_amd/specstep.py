@@ -59,6 +59,7 @@ def lib():
         "ss_step_n_profiled": [vp, i64, ctypes.POINTER(dbl), ctypes.POINTER(i64), cint],
         "ss_bind_mass_log": [vp, vp, i64],
         "ss_autotune": [vp, cint],
+        "ss_time_pass": [vp, cint, cint, ctypes.POINTER(dbl)],
         "ss_get_tiles": [vp, ctypes.POINTER(cint)],
         "ss_set_tiles": [vp, ctypes.POINTER(cint)],
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
@@ -155,6 +156,13 @@ def ss_step_n_profiled(h, nsteps):
     cnt = (ctypes.c_int64 * SS_NPASS)()
     _check(lib().ss_step_n_profiled(h, int(nsteps), ms, cnt, SS_NPASS))
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(SS_NPASS) if cnt[i]}
+
+
+def ss_time_pass(h, pass_name, nlaunch=100):
+    """Mean ms of one launch of a pass ('xpass', 'kpass', 'ypass_inv', 'ypass_fwd')."""
+    ms = ctypes.c_double()
+    _check(lib().ss_time_pass(h, PASS_NAMES.index(pass_name), int(nlaunch), ctypes.byref(ms)))
+    return ms.value
 
 
 def ss_autotune(h, reps=5):
@@ -350,6 +358,9 @@ class Grid:
 
     def set_tiles(self, tiles):
         ss_set_tiles(self.h, tiles)
+
+    def time_pass(self, pass_name, nlaunch=100):
+        return ss_time_pass(self.h, pass_name, nlaunch)
 
     def step_profiled(self, nsteps):
         return ss_step_n_profiled(self.h, nsteps)
