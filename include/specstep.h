@@ -147,11 +147,17 @@ ss_status ss_autotune(ss_grid g, int reps);
 
 /* Read / override the tiling: tiles[0] = rows per x-pass workgroup (step),
  * tiles[1] = lines per k-space workgroup, tiles[2] = lines per y-pass
- * workgroup (3D), tiles[3] = rows per x-pass workgroup for set/get field.
- * In ss_set_tiles a 0 entry keeps the default; an invalid entry is
- * SS_ERR_ARG. */
-ss_status ss_get_tiles(ss_grid g, int tiles[4]);
-ss_status ss_set_tiles(ss_grid g, const int tiles[4]);
+ * workgroup (3D), tiles[3] = rows per x-pass workgroup for set/get field,
+ * tiles[4] = x-pass tiles per workgroup (0 or 1: one tile each; > 1: a
+ * persistent x pass whose workgroups prefetch their next tile while
+ * transforming the current one), tiles[5] = row block B of the spectral
+ * layout (power of two; B consecutive rows of every kx are stored together,
+ * B = ny*nz being the plain transposed layout).  In ss_set_tiles a 0 entry
+ * keeps the current value; an invalid entry is SS_ERR_ARG; changing B
+ * after a field was set is SS_ERR_STATE.  ss_autotune also chooses B when
+ * no field is set yet. */
+ss_status ss_get_tiles(ss_grid g, int tiles[6]);
+ss_status ss_set_tiles(ss_grid g, const int tiles[6]);
 
 /* ---- Reverse mode (adjoint) of ss_step_n ---------------------------------
  *

@@ -45,6 +45,7 @@ struct KAdjArgs {
   double nxd;          // Nx
   double* acc;         // [gridDim.y][gridDim.x][2]: sums of w (Nx dA P + dB Q) and k^2 times it
   double* dc;          // [1]: sum of mu_u over the grid (F-derivative of g_u)
+  int lb;              // log2 of the row block of the spectral layout
 };
 
 // dphi1(z) = (z e^z - expm1(z)) / z^2 = 1/2 + z/3 + z^2/8 + z^3/30 + z^4/144 + ...
@@ -87,10 +88,10 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
   const int ls = tid / S, t = tid - ls * S;
   const KAdjField F = fi == 0 ? a.fld[0] : a.fld[1];
   const int kxi = bx * a.lines_per_block + ls;
-  const int64_t lbase = (int64_t)kxi * NL;
-  const C<T>* pl = (const C<T>*)F.lam + lbase;
-  const C<T>* pq = (const C<T>*)F.q + lbase;
-  const C<T>* pg = (const C<T>*)F.g + lbase;
+  const int64_t hx = a.nx / 2;
+  const C<T>* pl = (const C<T>*)F.lam;
+  const C<T>* pq = (const C<T>*)F.q;
+  const C<T>* pg = (const C<T>*)F.g;
   const int L = a.lines_per_block;
   // three regions per block: lambda^, q^, g^ (each L lines)
   C<T>* xl = lds + (0 * L + ls) * REG;
@@ -101,9 +102,10 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
   C<T> cl[1][8], cq[1][8], cg[1][8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    cl[0][e] = pl[t + e * S];
-    cq[0][e] = pq[t + e * S];
-    cg[0][e] = pg[t + e * S];
+    const int64_t ix = sidx(kxi, t + e * S, hx, a.lb);
+    cl[0][e] = pl[ix];
+    cq[0][e] = pq[ix];
+    cg[0][e] = pg[ix];
   }
   {
     C<T>* x1[1] = {xl};
@@ -171,12 +173,13 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
     fft_lines<T, NL, +1, 1>(oa, x1, t, tw);
     fft_lines<T, NL, +1, 1>(om, x1, t, tw);
   }
-  C<T>* pa = (C<T>*)F.out_a + lbase;
-  C<T>* pm = (C<T>*)F.out_m + lbase;
+  C<T>* pa = (C<T>*)F.out_a;
+  C<T>* pm = (C<T>*)F.out_m;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    pa[t + e * S] = oa[0][e];
-    pm[t + e * S] = om[0][e];
+    const int64_t ix = sidx(kxi, t + e * S, hx, a.lb);
+    pa[ix] = oa[0][e];
+    pm[ix] = om[0][e];
   }
   // deterministic block reduction of (s0, s1)
   red[2 * tid] = s0;
@@ -218,6 +221,7 @@ struct XAdjArgs {
   void* out[2];        // lambda at the input level
   int64_t rows;
   int rows_per_block;
+  int lb;              // log2 of the row block of the spectral layout
 };
 
 // six staged arrays per row pair: mu_u, mu_v, q_u, q_v, la_u, la_v
@@ -244,7 +248,7 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
     const int kx = (i / R) % H;
     const int f = i / (R * H);
     const void* base = f == 0 ? a.m[0] : f == 1 ? a.m[1] : f == 2 ? a.q[0] : f == 3 ? a.q[1] : f == 4 ? a.la[0] : a.la[1];
-    lds[((r >> 1) * NA + f) * REG + (r & 1) * HB + kx] = ((const C<T>*)base)[(int64_t)kx * rows + s0 + r];
+    lds[((r >> 1) * NA + f) * REG + (r & 1) * HB + kx] = ((const C<T>*)base)[sidx(kx, s0 + r, H, a.lb)];
   }
   __syncthreads();
   for (int it = 0; it < P / G; ++it) {
@@ -340,7 +344,7 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
     const int kx = (i / R) % H;
     const int f = i / (R * H);
     C<T>* dst = (C<T>*)(f == 0 ? a.out[0] : a.out[1]);
-    dst[(int64_t)kx * rows + s0 + r] = lds[((r >> 1) * NA + 4 + f) * REG + (r & 1) * HB + kx];
+    dst[sidx(kx, s0 + r, H, a.lb)] = lds[((r >> 1) * NA + 4 + f) * REG + (r & 1) * HB + kx];
   }
 }
 

@@ -82,6 +82,8 @@ struct ss_grid_s {
 
   // tiling of each pass (rows or lines per workgroup); 0 = not chosen yet
   int tile_x_step = 0, tile_x_io = 0, tile_y = 0, tile_k = 0;
+  int tile_x_ppb = 0;   // x pass tiles per block (> 1: persistent, prefetching)
+  int lb = -1;          // log2 of the row block B of the spectral layout (-1: not chosen)
 
   // reverse mode: caller-owned workspace with checkpoints and segment
   void* adj_ws = nullptr;
@@ -226,7 +228,7 @@ ss::LaunchEvents take_events(PassTimer* pt, int kind) {
 // Tiles chosen by ss_autotune, shared by every grid of the same shape.
 typedef std::tuple<int, int, int64_t, int64_t, int64_t, int> TileKey;  // ndim, esz, nx, ny, nz, nf
 struct Tiles {
-  int x_step, y, k;
+  int x_step, y, k, x_ppb, lb;
 };
 std::mutex g_tile_mu;
 std::map<TileKey, Tiles> g_tile_cache;
@@ -239,18 +241,41 @@ int esz_of(ss_grid g) { return (int)(2 * g->esz()); }
 int64_t nlines_k(ss_grid g) { return (g->n[0] / 2) * (g->ndim == 3 ? g->n[1] : 1); }
 int nlast(ss_grid g) { return (int)(g->ndim == 3 ? g->n[2] : g->n[1]); }
 
+int ilog2i(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << (l + 1)) <= v) ++l;
+  return l;
+}
+
+// Row block of the spectral layout: B rows of every kx stored together.
+bool blk_ok(ss_grid g, int64_t B) {
+  const int64_t rows = g->n[1] * g->n[2];
+  if (!ss::is_pow2(B) || B > rows) return false;
+  if (g->ndim == 3 && B > g->n[2]) return false;
+  return true;
+}
+int64_t blk_default(ss_grid g) {
+  // 64-byte chunks along the k-space lines
+  int64_t B = 64 / esz_of(g);
+  while (!blk_ok(g, B)) B /= 2;
+  return B;
+}
+
 void ensure_tiles(ss_grid g) {
   const int esz = esz_of(g);
   if (!g->tile_x_io) g->tile_x_io = ss::x_tile_default(esz, (int)g->n[0], 1, g->n[1] * g->n[2]);
-  if (g->tile_x_step && g->tile_k && (g->ndim == 2 || g->tile_y)) return;
-  Tiles t = {0, 0, 0};
+  if (g->lb >= 0 && g->tile_x_step && g->tile_k && (g->ndim == 2 || g->tile_y)) return;
+  Tiles t = {0, 0, 0, 0, -1};
   {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     auto it = g_tile_cache.find(tile_key(g));
     if (it != g_tile_cache.end()) t = it->second;
   }
-  if (!g->tile_x_step)
+  if (g->lb < 0) g->lb = (t.lb >= 0 && !g->field_set[0]) ? t.lb : ilog2i(blk_default(g));
+  if (!g->tile_x_step) {
     g->tile_x_step = t.x_step ? t.x_step : ss::x_tile_default(esz, (int)g->n[0], g->nf, g->n[1] * g->n[2]);
+    g->tile_x_ppb = t.x_step ? t.x_ppb : 0;
+  }
   if (!g->tile_k) g->tile_k = t.k ? t.k : ss::k_tile_default(esz, nlast(g), nlines_k(g), g->ndim == 3);
   if (g->ndim == 3 && !g->tile_y) g->tile_y = t.y ? t.y : ss::y_tile_default(esz, (int)g->n[1], g->n[2]);
 }
@@ -274,6 +299,8 @@ ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void*
   a.scale = scale;
   ensure_tiles(g);
   a.rows_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_step : g->tile_x_io;
+  a.tiles_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_ppb : 0;
+  a.lb = g->lb;
   for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
   return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, g->nlm, a, g->stream, take_events(pt, PASS_X)),
                    "x pass launch");
@@ -291,6 +318,8 @@ ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double sca
   a.scale = scale;
   ensure_tiles(g);
   a.lines_per_block = g->tile_y;
+  a.hx = (int)(g->n[0] / 2);
+  a.lb = g->lb;
   return hip_check(ss::run_ypass<T>((int)g->n[1], dir, a, g->n[0] / 2, g->stream,
                                     take_events(pt, dir < 0 ? PASS_YFWD : PASS_YINV)),
                    "y pass launch");
@@ -324,6 +353,7 @@ ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr) {
   a.three_d = three ? 1 : 0;
   ensure_tiles(g);
   a.lines_per_block = g->tile_k;
+  a.lb = g->lb;
   const int nl = (int)nlast;
   return hip_check(ss::run_kpass<T>(nl, a, g->stream, take_events(pt, PASS_K)), "k-space pass launch");
 }
@@ -394,41 +424,52 @@ ss_status time_launch(ss_grid g, F launch, int reps, float* best_ms) {
   return st;
 }
 
+// Tune the tiles of every pass for the current row block (g->lb); *total
+// receives the summed best times of one step's launches.
 template <typename T>
-ss_status autotune_t(ss_grid g, int reps) {
+ss_status autotune_tiles(ss_grid g, int reps, float* total) {
   const int esz = esz_of(g);
   const int nx = (int)g->n[0];
   const int64_t rows = g->n[1] * g->n[2];
+  float sum = 0.f;
   // x pass (STEP): reads the state, writes the scratch arrays only
   {
-    int best_r = 0;
+    int best_r = 0, best_ppb = 0;
     float best = 1e30f;
-    for (int r = 2; r <= 64; r *= 2) {
-      if (!ss::x_tile_ok(esz, nx, g->nf, rows, r)) continue;
-      auto launch = [&](ss::LaunchEvents ev) {
-        ss::XArgs a;
-        memset(&a, 0, sizeof(a));
-        a.spec_in[0] = g->state[0];
-        a.spec_in[1] = g->state[1];
-        a.spec_out[0] = g->scratch[0];
-        a.spec_out[1] = g->scratch[1];
-        a.rows = rows;
-        a.nz = (int)g->n[2];
-        a.ny = (int)g->n[1];
-        a.xcd_remap = 1;
-        a.scale = 1.0;
-        a.rows_per_block = r;
-        for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
-        return hip_check(ss::run_xpass<T>(nx, g->nf, ss::XMODE_STEP, g->nlm, a, g->stream, ev), "autotune x");
-      };
-      float ms;
-      SS_TRY(time_launch(g, launch, reps, &ms));
-      if (ms < best) {
-        best = ms;
-        best_r = r;
+    for (int r = 2; r <= 64; r *= 2)
+      for (int ppb : {0, 2, 4, 8}) {
+        if (!ss::x_tile_ok(esz, nx, g->nf, rows, r)) continue;
+        if (ppb && !ss::x_pp_ok(esz, nx, g->nf, rows, r)) continue;
+        if (ppb && rows / r < 2 * ppb) continue;
+        auto launch = [&](ss::LaunchEvents ev) {
+          ss::XArgs a;
+          memset(&a, 0, sizeof(a));
+          a.spec_in[0] = g->state[0];
+          a.spec_in[1] = g->state[1];
+          a.spec_out[0] = g->scratch[0];
+          a.spec_out[1] = g->scratch[1];
+          a.rows = rows;
+          a.nz = (int)g->n[2];
+          a.ny = (int)g->n[1];
+          a.xcd_remap = 1;
+          a.scale = 1.0;
+          a.rows_per_block = r;
+          a.tiles_per_block = ppb;
+          a.lb = g->lb;
+          for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+          return hip_check(ss::run_xpass<T>(nx, g->nf, ss::XMODE_STEP, g->nlm, a, g->stream, ev), "autotune x");
+        };
+        float ms;
+        SS_TRY(time_launch(g, launch, reps, &ms));
+        if (ms < best) {
+          best = ms;
+          best_r = r;
+          best_ppb = ppb;
+        }
       }
-    }
     g->tile_x_step = best_r;
+    g->tile_x_ppb = best_ppb;
+    sum += best;
   }
   // k-space pass: run on the scratch arrays as "state" and the staging
   // array as nonlinear term, so the fields are untouched
@@ -457,6 +498,7 @@ ss_status autotune_t(ss_grid g, int reps) {
         a.nf = g->nf;
         a.three_d = g->ndim == 3;
         a.lines_per_block = l;
+        a.lb = g->lb;
         return hip_check(ss::run_kpass<T>(nl, a, g->stream, ev), "autotune k");
       };
       float ms;
@@ -467,6 +509,7 @@ ss_status autotune_t(ss_grid g, int reps) {
       }
     }
     g->tile_k = best_l;
+    sum += best;
   }
   if (g->ndim == 3) {
     int best_y = 0;
@@ -480,6 +523,8 @@ ss_status autotune_t(ss_grid g, int reps) {
         a.out = g->scratch[0];
         a.ny = (int)g->n[1];
         a.nz = (int)g->n[2];
+        a.hx = nx / 2;
+        a.lb = g->lb;
         a.scale = 1.0;
         a.lines_per_block = l;
         return hip_check(ss::run_ypass<T>((int)g->n[1], -1, a, g->n[0] / 2, g->stream, ev), "autotune y");
@@ -492,9 +537,50 @@ ss_status autotune_t(ss_grid g, int reps) {
       }
     }
     g->tile_y = best_y;
+    sum += 2 * g->nf * best;   // one inverse and one forward y pass per field
   }
+  *total = sum;
+  return SS_OK;
+}
+
+template <typename T>
+ss_status autotune_t(ss_grid g, int reps) {
+  // The row block of the layout can change only while no field is stored.
+  const bool free_layout = !g->field_set[0] && !g->field_set[1];
+  std::vector<int> lbs;
+  if (free_layout) {
+    const int64_t rows = g->n[1] * g->n[2];
+    for (int64_t B : {blk_default(g), rows, (int64_t)16, (int64_t)8, (int64_t)4, (int64_t)2}) {
+      if (!blk_ok(g, B)) continue;
+      const int lb = ilog2i(B);
+      if (std::find(lbs.begin(), lbs.end(), lb) == lbs.end()) lbs.push_back(lb);
+    }
+  } else {
+    lbs.push_back(g->lb);
+  }
+  int best_lb = g->lb;
+  int bx = 0, bppb = 0, bk = 0, by = 0;
+  float best = 1e30f;
+  for (int lb : lbs) {
+    g->lb = lb;
+    float tot;
+    SS_TRY(autotune_tiles<T>(g, reps, &tot));
+    if (tot < best) {
+      best = tot;
+      best_lb = lb;
+      bx = g->tile_x_step;
+      bppb = g->tile_x_ppb;
+      bk = g->tile_k;
+      by = g->tile_y;
+    }
+  }
+  g->lb = best_lb;
+  g->tile_x_step = bx;
+  g->tile_x_ppb = bppb;
+  g->tile_k = bk;
+  g->tile_y = by;
   std::lock_guard<std::mutex> lk(g_tile_mu);
-  g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k};
+  g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k, g->tile_x_ppb, g->lb};
   return SS_OK;
 }
 
@@ -552,6 +638,8 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     m.x.rows_per_block = R;
     m.x.xcd_remap = 0;
     m.x.scale = 1.0;
+    ensure_tiles(g);
+    m.x.lb = g->lb;
     for (int i = 0; i < 5; ++i) m.x.p[i] = g->p[i];
     m.k.fld[0] = g->kf[0];
     m.k.fld[0].state = g->state[0];
@@ -567,6 +655,7 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     m.k.a_scale = 1.0 / (double)ny;
     m.k.b_scale = 1.0 / (double)g->cells();
     m.k.nf = 1;
+    m.k.lb = g->lb;
     m.nx = nx;
     m.ny = ny;
     m.x_first = x_total;
@@ -692,6 +781,7 @@ ss_status kpass_to(ss_grid g, const void* st0, const void* st1, const void* g0, 
   a.nf = 2;
   ensure_tiles(g);
   a.lines_per_block = g->tile_k;
+  a.lb = g->lb;
   return hip_check(ss::run_kpass<T>((int)g->n[1], a, g->stream, ss::LaunchEvents()), "k-space pass launch");
 }
 
@@ -735,6 +825,8 @@ ss_status adjoint_t(ss_grid g, const void* const dqT[], void* const dq0[], doubl
   ka.nxd = (double)nx;
   ka.acc = acc;
   ka.dc = dc;
+  ensure_tiles(g);
+  ka.lb = g->lb;
   ss::XAdjArgs xa;
   memset(&xa, 0, sizeof(xa));
   for (int f = 0; f < 2; ++f) {
@@ -743,6 +835,7 @@ ss_status adjoint_t(ss_grid g, const void* const dqT[], void* const dq0[], doubl
     xa.out[f] = lam[f];
   }
   xa.rows = ny;
+  xa.lb = g->lb;
   xa.rows_per_block = ss::xadj_tile(esz, nx, ny);
   if (!xa.rows_per_block) return fail(SS_ERR_UNSUPPORTED, "ss_adjoint_n: grid too large for the adjoint x pass");
   const int64_t nseg = L.nck;
@@ -832,6 +925,8 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     a.xcd_remap = 1;
     a.scale = 1.0;
     a.rows_per_block = g->tile_x_step;
+    a.tiles_per_block = g->tile_x_ppb;
+    a.lb = g->lb;
     for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
     return hip_check(ss::run_xpass<T>(nx, g->nf, ss::XMODE_STEP, g->nlm, a, g->stream, ev), "timed x pass");
   }
@@ -857,6 +952,7 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     a.nf = g->nf;
     a.three_d = g->ndim == 3;
     a.lines_per_block = g->tile_k;
+    a.lb = g->lb;
     return hip_check(ss::run_kpass<T>(nl, a, g->stream, ev), "timed k pass");
   }
   if (g->ndim == 3 && (pass == PASS_YINV || pass == PASS_YFWD)) {
@@ -868,6 +964,8 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     a.nz = (int)g->n[2];
     a.scale = 1.0;
     a.lines_per_block = g->tile_y;
+    a.hx = (int)(g->n[0] / 2);
+    a.lb = g->lb;
     return hip_check(ss::run_ypass<T>((int)g->n[1], pass == PASS_YFWD ? -1 : +1, a, g->n[0] / 2, g->stream, ev),
                      "timed y pass");
   }
@@ -926,6 +1024,7 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
     g->field_set[0] = g->field_set[1] = false;
   }
   if (!g->has_model || nf != g->nf) g->tile_x_step = g->tile_y = g->tile_k = 0;
+  if (g->has_model && model != g->model) g->lb = -1;
   g->model = model;
   g->nf = nf;
   g->ncoef = ncoef;
@@ -1095,7 +1194,7 @@ ss_status ss_autotune(ss_grid g, int reps) {
   return g->dtype == SS_F64 ? autotune_t<double>(g, reps) : autotune_t<float>(g, reps);
 }
 
-ss_status ss_get_tiles(ss_grid g, int tiles[4]) {
+ss_status ss_get_tiles(ss_grid g, int tiles[6]) {
   if (!g || !tiles) return fail(SS_ERR_ARG, "ss_get_tiles: null argument");
   if (!g->has_model) return fail(SS_ERR_STATE, "ss_get_tiles: call ss_set_model first");
   ensure_tiles(g);
@@ -1103,10 +1202,12 @@ ss_status ss_get_tiles(ss_grid g, int tiles[4]) {
   tiles[1] = g->tile_k;
   tiles[2] = g->tile_y;
   tiles[3] = g->tile_x_io;
+  tiles[4] = g->tile_x_ppb;
+  tiles[5] = 1 << g->lb;
   return SS_OK;
 }
 
-ss_status ss_set_tiles(ss_grid g, const int tiles[4]) {
+ss_status ss_set_tiles(ss_grid g, const int tiles[6]) {
   if (!g || !tiles) return fail(SS_ERR_ARG, "ss_set_tiles: null argument");
   if (!g->has_model) return fail(SS_ERR_STATE, "ss_set_tiles: call ss_set_model first");
   const int esz = esz_of(g);
@@ -1119,10 +1220,22 @@ ss_status ss_set_tiles(ss_grid g, const int tiles[4]) {
     return fail(SS_ERR_ARG, "ss_set_tiles: y tile %d not valid for this grid", tiles[2]);
   if (tiles[3] && !ss::x_tile_ok(esz, (int)g->n[0], 1, rows, tiles[3]))
     return fail(SS_ERR_ARG, "ss_set_tiles: x io tile %d not valid for this grid", tiles[3]);
+  if (tiles[4] < 0 || tiles[4] > 64) return fail(SS_ERR_ARG, "ss_set_tiles: tiles per block must be in [0, 64]");
+  ensure_tiles(g);
+  if (tiles[5] && !blk_ok(g, tiles[5])) return fail(SS_ERR_ARG, "ss_set_tiles: row block %d not valid for this grid", tiles[5]);
+  if (tiles[5] && ilog2i(tiles[5]) != g->lb && (g->field_set[0] || g->field_set[1]))
+    return fail(SS_ERR_STATE, "ss_set_tiles: the row block can change only before any field is set");
+  if (tiles[4] > 1) {
+    const int r = tiles[0] ? tiles[0] : ss::x_tile_default(esz, (int)g->n[0], g->nf, rows);
+    if (!ss::x_pp_ok(esz, (int)g->n[0], g->nf, rows, r))
+      return fail(SS_ERR_ARG, "ss_set_tiles: x tile %d cannot run persistent", r);
+  }
   g->tile_x_step = tiles[0];
   g->tile_k = tiles[1];
   g->tile_y = g->ndim == 3 ? tiles[2] : 0;
   g->tile_x_io = tiles[3];
+  g->tile_x_ppb = tiles[4];
+  if (tiles[5]) g->lb = ilog2i(tiles[5]);
   ensure_tiles(g);
   return SS_OK;
 }

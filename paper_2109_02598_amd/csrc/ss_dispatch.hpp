@@ -40,6 +40,11 @@ inline int x_threads(int esz, int nx, int rows) {
   if (G < 1) G = 1;
   return G * S;
 }
+// persistent x pass: needs every pair of the tile in flight at once
+inline bool x_pp_ok(int esz, int nx, int nf, int64_t nrows, int rows) {
+  return x_tile_ok(esz, nx, nf, nrows, rows) && (rows / 2) * (nx / 8) <= 512 &&
+         (rows / 2) * (nx / 8) >= 64;
+}
 inline int x_tile_default(int esz, int nx, int nf, int64_t nrows) {
   // at most 128 contiguous bytes per staged chunk, at most half the LDS
   // (two blocks per CU), and enough blocks to cover the CUs twice
@@ -126,17 +131,17 @@ hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev);
 
 #ifdef SS_DISPATCH_IMPL
 
-template <typename K, typename A>
+template <typename K, typename... A>
 hipError_t launch_with(K kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, LaunchEvents ev,
-                       const A& a) {
+                       const A&... a) {
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   if (ev.start || ev.stop)
-    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ev.start, ev.stop, 0, a);
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ev.start, ev.stop, 0, a...);
   else
-    hipLaunchKernelGGL(kernel, grid, block, lds, s, a);
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, a...);
   return hipGetLastError();
 }
 
@@ -145,9 +150,16 @@ hipError_t launch_x(XArgs a, hipStream_t s, LaunchEvents ev) {
   constexpr int ESZ = (int)sizeof(C<T>);
   const int R = a.rows_per_block;
   if (!x_tile_ok(ESZ, NX, NF, a.rows, R)) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)(a.rows / R)), block((unsigned)x_threads(ESZ, NX, R));
-  return launch_with(xpass_kernel<T, NX, NF, MODE, NLM>, grid, block, (uint32_t)x_lds(ESZ, NX, NF, R), s,
-                     ev, a);
+  const int ntiles = (int)(a.rows / R);
+  const int threads = x_threads(ESZ, NX, R);
+  const uint32_t lds = (uint32_t)x_lds(ESZ, NX, NF, R);
+  if constexpr (MODE == XMODE_STEP) {
+    if (a.tiles_per_block > 1 && x_pp_ok(ESZ, NX, NF, a.rows, R)) {
+      const int grid = (ntiles + a.tiles_per_block - 1) / a.tiles_per_block;
+      return launch_with(xpass_pp_kernel<T, NX, NF, NLM>, dim3(grid), dim3(threads), lds, s, ev, a, ntiles);
+    }
+  }
+  return launch_with(xpass_kernel<T, NX, NF, MODE, NLM>, dim3(ntiles), dim3(threads), lds, s, ev, a);
 }
 
 #define SS_POW2_CASES(M) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024) M(2048) M(4096)

@@ -26,6 +26,8 @@
 //          mode (-k) before the update.
 #pragma once
 
+#include <type_traits>
+
 #include "ss_fft.hpp"
 
 namespace ss {
@@ -34,6 +36,27 @@ enum { XMODE_FWD = 0, XMODE_INV = 1, XMODE_STEP = 2 };
 enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2 };
 
 constexpr int LDS_BUDGET = 160 * 1024;
+
+// Index of spectral element (kx, s) (kx < H, s = row).  Rows are grouped in
+// blocks of B = 2^lb consecutive rows; inside a block the layout is
+// [kx][s mod B] and blocks follow each other, so
+//   index = ((s >> lb) * H + kx) * B + (s mod B).
+// The x pass then reads a block of rows as one contiguous region, while
+// the k-space pass reads a line as chunks of B consecutive elements.  With
+// B = rows this is the plain transposed layout [kx][s].
+__device__ __forceinline__ int64_t sidx(int64_t kx, int64_t s, int64_t H, int lb) {
+  return (((s >> lb) * H + kx) << lb) + (s & ((int64_t(1) << lb) - 1));
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E), so
+// register arrays are only ever indexed by constants.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>());
+    static_for<B + 1, E>(f);
+  }
+}
 
 #ifndef SS_KWAVES
 #define SS_KWAVES 2
@@ -73,6 +96,8 @@ struct XArgs {
   int64_t rows;             // Ny*Nz = leading dimension of T
   int nz, ny;               // s = y*nz + z ; real row offset (z*ny + y)*Nx
   int rows_per_block;       // R at run time (even, divides rows)
+  int tiles_per_block;      // STEP: > 1 selects the persistent, prefetching kernel
+  int lb;                   // log2 of the row block of the spectral layout
   int xcd_remap;            // 1: spread consecutive chunks over one XCD
   double scale;             // multiplies the forward output (1/Nx for FWD)
   double p[5];              // nonlinear coefficients
@@ -130,7 +155,9 @@ struct XThreads {
 
 // One x-pass tile: rows blk*R .. blk*R+R-1 of the spectral layout.  The
 // block's threads form G = blockDim/S groups of S threads, G dividing R/2.
-template <typename T, int NX, int NF, int MODE, int NLM>
+// PRELOADED: the caller has already staged the tile's spectral rows in LDS
+// (the persistent kernel below does, from registers it filled earlier).
+template <typename T, int NX, int NF, int MODE, int NLM, bool PRELOADED = false>
 __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* lds) {
   typedef XCfg<T, NX> K;
   constexpr int S = K::S, H = K::H, HB = K::HB;
@@ -145,7 +172,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
   const int64_t rows = a.rows;
   const Twiddles<T, NX> tw = make_twiddles<T, NX>(t);
 
-  if constexpr (MODE != XMODE_FWD) {
+  if constexpr (MODE != XMODE_FWD && !PRELOADED) {
     // staged load: element (f, kx, r) -> region(r/2, f) + (r&1)*HB + kx
     const int total = NF * H * R;
     for (int i = tid; i < total; i += blockDim.x) {
@@ -153,7 +180,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
       const int kx = (i / R) % H;
       const int f = i / (R * H);
       const C<T>* src = (const C<T>*)(f == 0 ? a.spec_in[0] : a.spec_in[1]);
-      lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx] = src[(int64_t)kx * rows + s0 + r];
+      lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx] = src[sidx(kx, s0 + r, H, a.lb)];
     }
     __syncthreads();
   }
@@ -272,7 +299,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
       const int kx = (i / R) % H;
       const int f = i / (R * H);
       C<T>* dst = (C<T>*)(f == 0 ? a.spec_out[0] : a.spec_out[1]);
-      dst[(int64_t)kx * rows + s0 + r] = lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx];
+      dst[sidx(kx, s0 + r, H, a.lb)] = lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx];
     }
   }
 }
@@ -284,6 +311,63 @@ __global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a
                                    reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
 
+// Register prefetch of one x-pass tile (element i = tid + q*nthr of the
+// tile's staged list: r = i mod R, kx = (i / R) mod H, field i / (R H)).
+template <typename T, int H, int PER>
+__device__ __forceinline__ void xpass_prefetch(T (&pre_re)[PER], T (&pre_im)[PER], const C<T>* in0,
+                                               const C<T>* in1, int tid, int nthr, int R, int lb,
+                                               int64_t s0) {
+  static_for<0, PER>([&](auto qc) __attribute__((always_inline)) {
+    constexpr int q = decltype(qc)::value;
+    const int i = tid + q * nthr;
+    const int r = i % R, kx = (i / R) % H, f = i / (R * H);
+    const C<T>* src = f == 0 ? in0 : in1;
+    const C<T> v = src[sidx(kx, s0 + r, H, lb)];
+    pre_re[q] = v.x;
+    pre_im[q] = v.y;
+  });
+}
+
+// Persistent x pass (STEP): block b takes tiles b, b + gridDim, ... and
+// loads the next tile's spectral rows into registers while it transforms
+// the current one, so the loads of one tile overlap the transforms of the
+// previous.  Requires blockDim = (R/2)*S (every pair in flight at once):
+// then each thread stages exactly 8*NF elements.
+template <typename T, int NX, int NF, int NLM>
+__global__ void __launch_bounds__(512) xpass_pp_kernel(XArgs a, int ntiles) {
+  typedef XCfg<T, NX> K;
+  constexpr int H = K::H, HB = K::HB;
+  constexpr int REG = K::reg_for(NF);
+  constexpr int PER = 8 * NF;
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
+  const int R = a.rows_per_block;
+  const int tid = threadIdx.x;
+  const int nthr = (int)blockDim.x;
+  const int64_t rows = a.rows;
+  T pre_re[PER], pre_im[PER];   // scalar arrays: kept in registers
+  int tile = blockIdx.x;
+  const C<T>* in0 = (const C<T>*)a.spec_in[0];
+  const C<T>* in1 = (const C<T>*)a.spec_in[1];
+  const int remap = a.xcd_remap;
+  if (tile < ntiles)
+    xpass_prefetch<T, H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(tile, ntiles, remap) * R);
+  for (; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();
+    static_for<0, PER>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      const int i = tid + q * nthr;
+      const int r = i % R, kx = (i / R) % H, f = i / (R * H);
+      lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx] = mk<T>(pre_re[q], pre_im[q]);
+    });
+    __syncthreads();
+    const int next = tile + gridDim.x;
+    if (next < ntiles)
+      xpass_prefetch<T, H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(next, ntiles, remap) * R);
+    xpass_body<T, NX, NF, XMODE_STEP, NLM, true>(a, xcd_block(tile, ntiles, a.xcd_remap), lds);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // y pass (3D): complex FFT along y of T[kx][y][z] on chunks of R
 // consecutive z; block = (kx, z chunk).  In place is allowed.
@@ -292,6 +376,8 @@ struct YArgs {
   const void* in;
   void* out;
   int ny, nz;
+  int hx;                  // Nx/2 (kx count of the spectral layout)
+  int lb;                  // log2 of the row block of the spectral layout
   int lines_per_block;     // R (divides nz)
   double scale;
 };
@@ -316,14 +402,14 @@ __global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
   const int64_t chunks_per_kx = a.nz / R;
   const int64_t kx = blockIdx.x / chunks_per_kx;
   const int64_t z0 = (blockIdx.x - kx * chunks_per_kx) * R;
-  const int64_t base = kx * (int64_t)a.ny * a.nz + z0;
+
   const C<T>* src = (const C<T>*)a.in;
   C<T>* dst = (C<T>*)a.out;
   const Twiddles<T, NY> tw = make_twiddles<T, NY>(t);
 
   for (int i = tid; i < NY * R; i += blockDim.x) {
     const int r = i % R, y = i / R;
-    lds[r * REG + y] = src[base + (int64_t)y * a.nz + r];
+    lds[r * REG + y] = src[sidx(kx, (int64_t)y * a.nz + z0 + r, a.hx, a.lb)];
   }
   __syncthreads();
   const T sc = (T)a.scale;
@@ -343,7 +429,7 @@ __global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
   __syncthreads();
   for (int i = tid; i < NY * R; i += blockDim.x) {
     const int r = i % R, y = i / R;
-    dst[base + (int64_t)y * a.nz + r] = lds[r * REG + y];
+    dst[sidx(kx, (int64_t)y * a.nz + z0 + r, a.hx, a.lb)] = lds[r * REG + y];
   }
 }
 
@@ -372,6 +458,7 @@ struct KArgs {
   int64_t log_capacity;
   int nf;
   int three_d;
+  int lb;                   // log2 of the row block of the spectral layout
 };
 
 template <typename T>
@@ -428,20 +515,23 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     kxi = slot / a.J;
     kyi = slot - kxi * a.J;
   }
-  const int64_t lbase = ((int64_t)kxi * a.J + kyi) * NL;
-  const C<T>* st = (const C<T>*)F.state + lbase;
-  const C<T>* gn = (const C<T>*)F.nonlin + lbase;
-  C<T>* so = (C<T>*)(F.out ? F.out : F.state) + lbase;
+  // element p of this line is row s = kyi*NL + p of plane kxi
+  const int64_t srow = (int64_t)kyi * NL;
+  const int64_t hx = a.nx / 2;
+  const int lb = a.lb;
+  const C<T>* st = (const C<T>*)F.state;
+  const C<T>* gn = (const C<T>*)F.nonlin;
+  C<T>* so = (C<T>*)(F.out ? F.out : F.state);
 
   C<T> ct[1][8], cg[1][8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) ct[0][e] = st[t + e * S];
+  for (int e = 0; e < 8; ++e) ct[0][e] = st[sidx(kxi, srow + t + e * S, hx, lb)];
   // one LDS region per line serves all three transforms in turn
   C<T>* x[1] = {lds + ls * REG};
   const Twiddles<T, NL> tw = make_twiddles<T, NL>(t);
   fft_lines<T, NL, -1, 1>(ct, x, t, tw);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) cg[0][e] = gn[t + e * S];
+  for (int e = 0; e < 8; ++e) cg[0][e] = gn[sidx(kxi, srow + t + e * S, hx, lb)];
   fft_lines<T, NL, -1, 1>(cg, x, t, tw);
 
   // wavenumbers: k_last from the position, k_mid from kyi (3D), k_x from kxi
@@ -527,7 +617,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
 
   fft_lines<T, NL, +1, 1>(ct, x, t, tw);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) so[t + e * S] = ct[0][e];
+  for (int e = 0; e < 8; ++e) so[sidx(kxi, srow + t + e * S, hx, lb)] = ct[0][e];
 }
 
 template <typename T, int NL>

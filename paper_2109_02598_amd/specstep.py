@@ -170,13 +170,14 @@ def ss_autotune(h, reps=5):
 
 
 def ss_get_tiles(h):
-    t = (ctypes.c_int * 4)()
+    t = (ctypes.c_int * 6)()
     _check(lib().ss_get_tiles(h, t))
     return list(t)
 
 
 def ss_set_tiles(h, tiles):
-    t = (ctypes.c_int * 4)(*[int(v) for v in tiles])
+    tiles = list(tiles) + [0] * (6 - len(tiles))
+    t = (ctypes.c_int * 6)(*[int(v) for v in tiles])
     _check(lib().ss_set_tiles(h, t))
 
 

@@ -87,12 +87,12 @@ def test_tilings_are_bitwise_identical(n, model, dtype):
     g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model], dt=0.05)
     base = None
     esz = 16 if dtype == "f64" else 8
-    cands = [(r, l, y) for r in (2, 4, 8, 16, 32, 64) for l in (1, 2, 4, 8, 16, 32, 64)
-             for y in ((1, 2, 4, 8, 16) if len(n) == 3 else (0,))]
+    cands = [(r, l, y, pp) for r in (2, 4, 8, 16, 32, 64) for l in (1, 2, 4, 8, 16, 32, 64)
+             for y in ((1, 2, 4, 8, 16) if len(n) == 3 else (0,)) for pp in (0, 2, 3)]
     tried = 0
-    for r, l, y in cands:
+    for r, l, y, pp in cands:
         try:
-            g.set_tiles([r, l, y, 0])
+            g.set_tiles([r, l, y, 0, pp])
         except specstep.SpecStepError:
             continue
         for i, f in enumerate(f0):
@@ -103,9 +103,26 @@ def test_tilings_are_bitwise_identical(n, model, dtype):
             base = out
         else:
             for a, b in zip(out, base):
-                assert np.array_equal(a, b), (r, l, y)
+                assert np.array_equal(a, b), (r, l, y, pp)
         tried += 1
     assert tried >= 3
+    # the row block of the layout (chosen before any field is set)
+    for blk in (1, 2, 8, 1 << 30):
+        gb = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model], dt=0.05)
+        rows = int(np.prod(n[1:]))
+        b = min(blk, rows)
+        if len(n) == 3 and b > n[2]:
+            gb.close()
+            continue
+        gb.set_tiles([0, 0, 0, 0, 0, b])
+        for i, f in enumerate(f0):
+            gb.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
+        gb.step(7)
+        for i, ref in enumerate(base):
+            assert np.array_equal(gb.get_field(i).cpu().numpy(), ref), ("row block", b)
+        assert gb.tiles()[5] == b
+        gb.close()
+        tried += 1
     tiles = g.autotune(2)
     for i, f in enumerate(f0):
         g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
