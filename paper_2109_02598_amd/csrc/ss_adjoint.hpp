@@ -243,12 +243,10 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
   const int64_t rows = a.rows;
   const Twiddles<T, NX> tw = make_twiddles<T, NX>(t);
 
-  for (int i = tid; i < NA * H * R; i += blockDim.x) {
-    const int r = i % R;
-    const int kx = (i / R) % H;
-    const int f = i / (R * H);
-    const void* base = f == 0 ? a.m[0] : f == 1 ? a.m[1] : f == 2 ? a.q[0] : f == 3 ? a.q[1] : f == 4 ? a.la[0] : a.la[1];
-    lds[((r >> 1) * NA + f) * REG + (r & 1) * HB + kx] = ((const C<T>*)base)[sidx(kx, s0 + r, H, a.lb)];
+  {
+    const C<T>* src[NA] = {(const C<T>*)a.m[0], (const C<T>*)a.m[1], (const C<T>*)a.q[0],
+                           (const C<T>*)a.q[1], (const C<T>*)a.la[0], (const C<T>*)a.la[1]};
+    xstage_in<T, H, NA, NA, 0, REG, HB>(lds, src, s0, R, a.lb, tid, (int)blockDim.x);
   }
   __syncthreads();
   for (int it = 0; it < P / G; ++it) {
@@ -339,12 +337,9 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
     }
   }
   __syncthreads();
-  for (int i = tid; i < 2 * H * R; i += blockDim.x) {
-    const int r = i % R;
-    const int kx = (i / R) % H;
-    const int f = i / (R * H);
-    C<T>* dst = (C<T>*)(f == 0 ? a.out[0] : a.out[1]);
-    dst[sidx(kx, s0 + r, H, a.lb)] = lds[((r >> 1) * NA + 4 + f) * REG + (r & 1) * HB + kx];
+  {
+    C<T>* dst[2] = {(C<T>*)a.out[0], (C<T>*)a.out[1]};
+    xstage_out<T, H, 2, NA, 4, REG, HB>(dst, lds, s0, R, a.lb, tid, (int)blockDim.x);
   }
 }
 

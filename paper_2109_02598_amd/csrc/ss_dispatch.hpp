@@ -40,10 +40,12 @@ inline int x_threads(int esz, int nx, int rows) {
   if (G < 1) G = 1;
   return G * S;
 }
-// persistent x pass: needs every pair of the tile in flight at once
+// persistent x pass: needs every pair of the tile in flight at once; its
+// two-field FP64 form would hold 16 prefetched complex values per thread
+// on top of the transform and is not built
 inline bool x_pp_ok(int esz, int nx, int nf, int64_t nrows, int rows) {
   return x_tile_ok(esz, nx, nf, nrows, rows) && (rows / 2) * (nx / 8) <= 512 &&
-         (rows / 2) * (nx / 8) >= 64;
+         (rows / 2) * (nx / 8) >= 64 && !(esz == 16 && nf == 2);
 }
 inline int x_tile_default(int esz, int nx, int nf, int64_t nrows) {
   // at most 128 contiguous bytes per staged chunk, at most half the LDS
@@ -153,7 +155,7 @@ hipError_t launch_x(XArgs a, hipStream_t s, LaunchEvents ev) {
   const int ntiles = (int)(a.rows / R);
   const int threads = x_threads(ESZ, NX, R);
   const uint32_t lds = (uint32_t)x_lds(ESZ, NX, NF, R);
-  if constexpr (MODE == XMODE_STEP) {
+  if constexpr (MODE == XMODE_STEP && !(sizeof(T) == 8 && NF == 2)) {
     if (a.tiles_per_block > 1 && x_pp_ok(ESZ, NX, NF, a.rows, R)) {
       const int grid = (ntiles + a.tiles_per_block - 1) / a.tiles_per_block;
       return launch_with(xpass_pp_kernel<T, NX, NF, NLM>, dim3(grid), dim3(threads), lds, s, ev, a, ntiles);
@@ -261,7 +263,7 @@ template <typename T>
 hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
   constexpr int ESZ = (int)sizeof(C<T>);
   const int R = a.rows_per_block;
-  if (R < 2 || a.rows % R) return hipErrorInvalidConfiguration;
+  if (R < 2 || !is_pow2(R) || a.rows % R) return hipErrorInvalidConfiguration;
   const int64_t lds = xadj_lds(ESZ, nx, R);
   if (lds > LDS_BUDGET) return hipErrorInvalidConfiguration;
   int G = 512 / (nx / 8);

@@ -120,6 +120,97 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// ---- staged copies between the spectral layout and x-pass LDS regions ----
+// A tile is the R rows s0 .. s0+R-1 (R a power of two) of NS arrays.  Row r
+// of array f sits in LDS at region((r/2)*NR + F0 + f) + (r&1)*HB + kx
+// (region stride REG, NR regions per row pair).  Per array the tile's
+// elements are ordered (kx, r) with r fastest and thread tid moves the
+// elements tid + q*nthr, so a wave reads R consecutive rows of consecutive
+// kx.  When nthr >= R the thread's row r = tid mod R is fixed: its global
+// index is one row offset plus kx*B (B = 2^lb row block) and kx advances by
+// nthr/R per element.  Eight loads are issued before their LDS writes; the
+// arrays are walked one after the other so that each pointer is chosen at
+// compile time.  Elements per thread and array: H*R/nthr, a multiple of 8
+// for the x-pass launch shapes (nthr = G*NX/8 with G dividing R/2).
+template <int H>
+__device__ __forceinline__ int64_t xstage_row(int64_t s, int lb) {
+  return (((s >> lb) * H) << lb) + (s & ((int64_t(1) << lb) - 1));
+}
+
+template <typename T, int H, int NS, int NR, int F0, int REG, int HB>
+__device__ __forceinline__ void xstage_in(C<T>* lds, const C<T>* const (&src)[NS], int64_t s0,
+                                          int R, int lb, int tid, int nthr) {
+  const int lr = __builtin_ctz((unsigned)R);
+  if (nthr >= R) {
+    const int r = tid & (R - 1);
+    const int64_t row = xstage_row<H>(s0 + r, lb);
+    const int kstep = nthr >> lr;
+    const int per = (H * R) / nthr;
+#pragma unroll
+    for (int f = 0; f < NS; ++f) {
+      const C<T>* g = src[f] + row;
+      C<T>* lrow = lds + ((r >> 1) * NR + F0 + f) * REG + (r & 1) * HB;
+      for (int c = 0, k0 = tid >> lr; c < per; c += 8, k0 += 8 * kstep) {
+        T vr[8], vi[8];   // scalar arrays: promoted to registers
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const C<T> v = g[(int64_t)(k0 + q * kstep) << lb];
+          vr[q] = v.x;
+          vi[q] = v.y;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lrow[k0 + q * kstep] = mk<T>(vr[q], vi[q]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < NS; ++f) {
+      for (int i = tid; i < H * R; i += nthr) {
+        const int r = i & (R - 1), kx = i >> lr;
+        lds[((r >> 1) * NR + F0 + f) * REG + (r & 1) * HB + kx] =
+            src[f][xstage_row<H>(s0 + r, lb) + ((int64_t)kx << lb)];
+      }
+    }
+  }
+}
+
+template <typename T, int H, int NS, int NR, int F0, int REG, int HB>
+__device__ __forceinline__ void xstage_out(C<T>* const (&dst)[NS], const C<T>* lds, int64_t s0,
+                                           int R, int lb, int tid, int nthr) {
+  const int lr = __builtin_ctz((unsigned)R);
+  if (nthr >= R) {
+    const int r = tid & (R - 1);
+    const int64_t row = xstage_row<H>(s0 + r, lb);
+    const int kstep = nthr >> lr;
+    const int per = (H * R) / nthr;
+#pragma unroll
+    for (int f = 0; f < NS; ++f) {
+      C<T>* g = dst[f] + row;
+      const C<T>* lrow = lds + ((r >> 1) * NR + F0 + f) * REG + (r & 1) * HB;
+      for (int c = 0, k0 = tid >> lr; c < per; c += 8, k0 += 8 * kstep) {
+        T vr[8], vi[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const C<T> v = lrow[k0 + q * kstep];
+          vr[q] = v.x;
+          vi[q] = v.y;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) g[(int64_t)(k0 + q * kstep) << lb] = mk<T>(vr[q], vi[q]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < NS; ++f) {
+      for (int i = tid; i < H * R; i += nthr) {
+        const int r = i & (R - 1), kx = i >> lr;
+        dst[f][xstage_row<H>(s0 + r, lb) + ((int64_t)kx << lb)] =
+            lds[((r >> 1) * NR + F0 + f) * REG + (r & 1) * HB + kx];
+      }
+    }
+  }
+}
+
 template <typename T, int NLM>
 __device__ __forceinline__ void nonlinear(C<T>* c0, C<T>* c1, T p0, T p1, T p2) {
   if constexpr (NLM == NLIN_POLY) {
@@ -173,15 +264,10 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
   const Twiddles<T, NX> tw = make_twiddles<T, NX>(t);
 
   if constexpr (MODE != XMODE_FWD && !PRELOADED) {
-    // staged load: element (f, kx, r) -> region(r/2, f) + (r&1)*HB + kx
-    const int total = NF * H * R;
-    for (int i = tid; i < total; i += blockDim.x) {
-      const int r = i % R;
-      const int kx = (i / R) % H;
-      const int f = i / (R * H);
-      const C<T>* src = (const C<T>*)(f == 0 ? a.spec_in[0] : a.spec_in[1]);
-      lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx] = src[sidx(kx, s0 + r, H, a.lb)];
-    }
+    const C<T>* src[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) src[f] = (const C<T>*)a.spec_in[f];
+    xstage_in<T, H, NF, NF, 0, REG, HB>(lds, src, s0, R, a.lb, tid, (int)blockDim.x);
     __syncthreads();
   }
 
@@ -293,14 +379,10 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
 
   if constexpr (MODE != XMODE_INV) {
     __syncthreads();
-    const int total = NF * H * R;
-    for (int i = tid; i < total; i += blockDim.x) {
-      const int r = i % R;
-      const int kx = (i / R) % H;
-      const int f = i / (R * H);
-      C<T>* dst = (C<T>*)(f == 0 ? a.spec_out[0] : a.spec_out[1]);
-      dst[sidx(kx, s0 + r, H, a.lb)] = lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx];
-    }
+    C<T>* dst[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) dst[f] = (C<T>*)a.spec_out[f];
+    xstage_out<T, H, NF, NF, 0, REG, HB>(dst, lds, s0, R, a.lb, tid, (int)blockDim.x);
   }
 }
 
@@ -311,18 +393,21 @@ __global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a
                                    reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
 
-// Register prefetch of one x-pass tile (element i = tid + q*nthr of the
-// tile's staged list: r = i mod R, kx = (i / R) mod H, field i / (R H)).
+// Register prefetch of one x-pass tile for the persistent kernel: the
+// element order and thread mapping of xstage_in (fast path, nthr >= R),
+// exactly 8 elements per thread and field.
 template <typename T, int H, int PER>
 __device__ __forceinline__ void xpass_prefetch(T (&pre_re)[PER], T (&pre_im)[PER], const C<T>* in0,
                                                const C<T>* in1, int tid, int nthr, int R, int lb,
                                                int64_t s0) {
+  const int lr = __builtin_ctz((unsigned)R);
+  const int64_t row = xstage_row<H>(s0 + (tid & (R - 1)), lb);
+  const int kstep = nthr >> lr;
+  const int k0 = tid >> lr;
   static_for<0, PER>([&](auto qc) __attribute__((always_inline)) {
     constexpr int q = decltype(qc)::value;
-    const int i = tid + q * nthr;
-    const int r = i % R, kx = (i / R) % H, f = i / (R * H);
-    const C<T>* src = f == 0 ? in0 : in1;
-    const C<T> v = src[sidx(kx, s0 + r, H, lb)];
+    const C<T>* src = (q < 8 ? in0 : in1) + row;
+    const C<T> v = src[(int64_t)(k0 + (q & 7) * kstep) << lb];
     pre_re[q] = v.x;
     pre_im[q] = v.y;
   });
@@ -332,11 +417,11 @@ __device__ __forceinline__ void xpass_prefetch(T (&pre_re)[PER], T (&pre_im)[PER
 // loads the next tile's spectral rows into registers while it transforms
 // the current one, so the loads of one tile overlap the transforms of the
 // previous.  Requires blockDim = (R/2)*S (every pair in flight at once):
-// then each thread stages exactly 8*NF elements.
+// then each thread stages exactly 8 elements per field.
 template <typename T, int NX, int NF, int NLM>
 __global__ void __launch_bounds__(512) xpass_pp_kernel(XArgs a, int ntiles) {
   typedef XCfg<T, NX> K;
-  constexpr int H = K::H, HB = K::HB;
+  constexpr int HB = K::HB;
   constexpr int REG = K::reg_for(NF);
   constexpr int PER = 8 * NF;
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
@@ -344,26 +429,28 @@ __global__ void __launch_bounds__(512) xpass_pp_kernel(XArgs a, int ntiles) {
   const int R = a.rows_per_block;
   const int tid = threadIdx.x;
   const int nthr = (int)blockDim.x;
-  const int64_t rows = a.rows;
+  const int lr = __builtin_ctz((unsigned)R);
+  const int r = tid & (R - 1);
+  C<T>* lrow = lds + (r >> 1) * NF * REG + (r & 1) * HB;
+  const int kstep = nthr >> lr;
+  const int k0 = tid >> lr;
   T pre_re[PER], pre_im[PER];   // scalar arrays: kept in registers
   int tile = blockIdx.x;
   const C<T>* in0 = (const C<T>*)a.spec_in[0];
   const C<T>* in1 = (const C<T>*)a.spec_in[1];
   const int remap = a.xcd_remap;
   if (tile < ntiles)
-    xpass_prefetch<T, H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(tile, ntiles, remap) * R);
+    xpass_prefetch<T, K::H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(tile, ntiles, remap) * R);
   for (; tile < ntiles; tile += gridDim.x) {
     __syncthreads();
     static_for<0, PER>([&](auto qc) __attribute__((always_inline)) {
       constexpr int q = decltype(qc)::value;
-      const int i = tid + q * nthr;
-      const int r = i % R, kx = (i / R) % H, f = i / (R * H);
-      lds[((r >> 1) * NF + f) * REG + (r & 1) * HB + kx] = mk<T>(pre_re[q], pre_im[q]);
+      lrow[(q >> 3) * REG + k0 + (q & 7) * kstep] = mk<T>(pre_re[q], pre_im[q]);
     });
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < ntiles)
-      xpass_prefetch<T, H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(next, ntiles, remap) * R);
+      xpass_prefetch<T, K::H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(next, ntiles, remap) * R);
     xpass_body<T, NX, NF, XMODE_STEP, NLM, true>(a, xcd_block(tile, ntiles, a.xcd_remap), lds);
   }
 }
@@ -407,9 +494,27 @@ __global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
   C<T>* dst = (C<T>*)a.out;
   const Twiddles<T, NY> tw = make_twiddles<T, NY>(t);
 
-  for (int i = tid; i < NY * R; i += blockDim.x) {
-    const int r = i % R, y = i / R;
-    lds[r * REG + y] = src[sidx(kx, (int64_t)y * a.nz + z0 + r, a.hx, a.lb)];
+  // staged copies: element (y, r) with r fastest; thread tid keeps line
+  // r = tid mod R (nthr = G*S is a multiple of R) and y advances by nthr/R.
+  // The row block B divides nz, so sidx(kx, y*nz + z) = y*nz*hx + sidx(kx, z).
+  const int nthr = (int)blockDim.x;
+  const int lr = __builtin_ctz((unsigned)R);
+  const int r = tid & (R - 1);
+  const int64_t ystride = (int64_t)a.nz * a.hx;
+  const int64_t zoff = sidx(kx, z0 + r, a.hx, a.lb);
+  const int ystep = nthr >> lr;
+  const int per = (NY * R) / nthr;          // a multiple of 8
+  C<T>* lline = lds + r * REG;
+  for (int c = 0, y0 = tid >> lr; c < per; c += 8, y0 += 8 * ystep) {
+    T vr[8], vi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const C<T> v = src[zoff + (int64_t)(y0 + q * ystep) * ystride];
+      vr[q] = v.x;
+      vi[q] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lline[y0 + q * ystep] = mk<T>(vr[q], vi[q]);
   }
   __syncthreads();
   const T sc = (T)a.scale;
@@ -427,9 +532,16 @@ __global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
     for (int e = 0; e < 8; ++e) x[0][t + e * S] = cscale<T>(c[0][e], sc);
   }
   __syncthreads();
-  for (int i = tid; i < NY * R; i += blockDim.x) {
-    const int r = i % R, y = i / R;
-    dst[sidx(kx, (int64_t)y * a.nz + z0 + r, a.hx, a.lb)] = lds[r * REG + y];
+  for (int c = 0, y0 = tid >> lr; c < per; c += 8, y0 += 8 * ystep) {
+    T vr[8], vi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const C<T> v = lline[y0 + q * ystep];
+      vr[q] = v.x;
+      vi[q] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[zoff + (int64_t)(y0 + q * ystep) * ystride] = mk<T>(vr[q], vi[q]);
   }
 }
 
