@@ -68,10 +68,11 @@ template <typename T>
 __device__ __forceinline__ AdjCoef<T> adj_coeffs(const KAdjField& f, double k2, double dt) {
   AdjCoef<T> r;
   const T z = (T)((f.l[0] + f.l[1] * k2) * dt);
-  const T em = sizeof(T) == 8 ? (T)expm1((double)z) : (T)expm1f((float)z);
+  T A, phi, em;
+  etd1_aphi<T>(z, A, phi, em);   // the forward step's own factors
   const T dtt = (T)dt;
-  r.a = (T)1 + em;
-  r.b = (z != (T)0) ? dtt * (em / z) : dtt;
+  r.a = A;
+  r.b = dtt * phi;
   r.da = dtt * r.a;
   r.db = dtt * dtt * dphi1_of<T>(z, em);
   return r;

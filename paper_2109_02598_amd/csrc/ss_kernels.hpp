@@ -573,27 +573,70 @@ struct KArgs {
   int lb;                   // log2 of the row block of the spectral layout
 };
 
+// A = exp(z) and phi1(z) = (e^z - 1)/z of one mode (Eq. 4; phi1(0) = 1).
+// FP64: one expm1 serves both.  FP32: the library exponential for A;
+// phi1 from its Taylor series where |z| < 1/2 (degree 7: truncation below
+// 2e-8 relative) and from A and the hardware reciprocal elsewhere, where
+// e^z - 1 has no cancellation; both are evaluated and one is selected, so
+// z = 0 needs no special case.  The forward step and its adjoint share
+// this; em is e^z - 1 as the adjoint uses it.
 template <typename T>
-__device__ __forceinline__ void etd1_coeffs(const KField& f, double k2, double dt, double as,
-                                            double bs, T& ao, T& bo) {
+__device__ __forceinline__ void etd1_aphi(T z, T& A, T& phi, T& em) {
   if constexpr (sizeof(T) == 8) {
-    const double L = f.l[0] + k2 * (f.l[1] + k2 * (f.l[2] + k2 * f.l[3]));
-    const double z = L * dt;
-    // one expm1 serves both factors: A = 1 + expm1(z), B = dt expm1(z)/z
-    // (B = dt where z = 0, the limit of Eq. 4)
-    const double em = expm1(z);
-    const double phi = (z != 0.0) ? em / z : 1.0;
-    ao = (1.0 + em) * as;
-    bo = dt * phi * (f.n[0] + f.n[1] * k2) * bs;
+    em = expm1(z);
+    A = 1.0 + em;
+    phi = (z != 0.0) ? em / z : 1.0;
   } else {
-    const float k2f = (float)k2;
-    const float L = (float)f.l[0] + k2f * ((float)f.l[1] + k2f * ((float)f.l[2] + k2f * (float)f.l[3]));
-    const float z = L * (float)dt;
-    const float A = expf(z);
-    const float phi = (z != 0.0f) ? expm1f(z) / z : 1.0f;
-    ao = A * (float)as;
-    bo = (float)dt * phi * ((float)f.n[0] + (float)f.n[1] * k2f) * (float)bs;
+    A = expf(z);
+    float ps = 1.0f / 40320.0f;
+    ps = fmaf(ps, z, 1.0f / 5040.0f);
+    ps = fmaf(ps, z, 1.0f / 720.0f);
+    ps = fmaf(ps, z, 1.0f / 120.0f);
+    ps = fmaf(ps, z, 1.0f / 24.0f);
+    ps = fmaf(ps, z, 1.0f / 6.0f);
+    ps = fmaf(ps, z, 0.5f);
+    ps = fmaf(ps, z, 1.0f);
+    const float pl = (A - 1.0f) * __builtin_amdgcn_rcpf(z);
+    phi = __builtin_fabsf(z) < 0.5f ? ps : pl;
+    em = A - 1.0f;
   }
+}
+
+// ETD1 factors of one mode (Eq. 4): A = exp(L dt) and B = dt phi1(L dt) N,
+// with the k-space pass scalings folded in.
+template <typename T>
+__device__ __forceinline__ void etd1_coeffs(const KField& f, T k2, double dt, double as, double bs,
+                                            T& ao, T& bo) {
+  const T L = (T)f.l[0] + k2 * ((T)f.l[1] + k2 * ((T)f.l[2] + k2 * (T)f.l[3]));
+  const T z = L * (T)dt;
+  T A, phi, em;
+  etd1_aphi<T>(z, A, phi, em);
+  ao = A * (T)as;
+  bo = (T)dt * phi * ((T)f.n[0] + (T)f.n[1] * k2) * (T)bs;
+}
+
+// Offset of element u (0 <= u < N_last) of a k-space line from the line's
+// first element: g(u) = ((u >> lb) * hx << lb) + (u mod B).  For t < S and
+// S, B powers of two (B at most the line length, the line start a multiple
+// of B): g(t + e S) = g(t) + g(e S), a per-thread part plus a part that is
+// the same for every thread of the line.
+__device__ __forceinline__ int64_t kline_off(int64_t u, int64_t hx, int lb) {
+  return (((u >> lb) * hx) << lb) + (u & ((int64_t(1) << lb) - 1));
+}
+
+// Uniform 64-bit value across the wave (the line of a k-space thread is the
+// same for all 64 lanes when the line has at least 64 threads).
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// base + uo (elements, wave uniform) + tb (bytes, per thread, < 4 GiB)
+template <typename P>
+__device__ __forceinline__ P* kline_at(P* base, int64_t uo, uint32_t tb) {
+  typedef typename std::conditional<std::is_const<P>::value, const char, char>::type B;
+  return reinterpret_cast<P*>(reinterpret_cast<B*>(base + uo) + tb);
 }
 
 template <typename T, int NL>
@@ -627,33 +670,36 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     kxi = slot / a.J;
     kyi = slot - kxi * a.J;
   }
-  // element p of this line is row s = kyi*NL + p of plane kxi
-  const int64_t srow = (int64_t)kyi * NL;
+  // element p of this line is row s = kyi*NL + p of plane kxi; the line
+  // start is a multiple of NL, and the row block B is at most NL
   const int64_t hx = a.nx / 2;
   const int lb = a.lb;
-  const C<T>* st = (const C<T>*)F.state;
-  const C<T>* gn = (const C<T>*)F.nonlin;
-  C<T>* so = (C<T>*)(F.out ? F.out : F.state);
+  int64_t lbase = sidx(kxi, (int64_t)kyi * NL, hx, lb);
+  if constexpr (S >= 64) lbase = wave_uniform(lbase);
+  const uint32_t tb = (uint32_t)(kline_off(t, hx, lb) * (int64_t)sizeof(C<T>));
+  const C<T>* st = (const C<T>*)F.state + lbase;
+  const C<T>* gn = (const C<T>*)F.nonlin + lbase;
+  C<T>* so = (C<T>*)(F.out ? F.out : F.state) + lbase;
 
   C<T> ct[1][8], cg[1][8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) ct[0][e] = st[sidx(kxi, srow + t + e * S, hx, lb)];
+  for (int e = 0; e < 8; ++e) ct[0][e] = *kline_at(st, kline_off(e * S, hx, lb), tb);
   // one LDS region per line serves all three transforms in turn
   C<T>* x[1] = {lds + ls * REG};
   const Twiddles<T, NL> tw = make_twiddles<T, NL>(t);
   fft_lines<T, NL, -1, 1>(ct, x, t, tw);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) cg[0][e] = gn[sidx(kxi, srow + t + e * S, hx, lb)];
+  for (int e = 0; e < 8; ++e) cg[0][e] = *kline_at(gn, kline_off(e * S, hx, lb), tb);
   fft_lines<T, NL, -1, 1>(cg, x, t, tw);
 
   // wavenumbers: k_last from the position, k_mid from kyi (3D), k_x from kxi
-  const double kxv = (double)kxi * a.sx;
-  double kmid2 = 0.0;
+  const T kxv = (T)kxi * (T)a.sx;
+  T kmid2 = (T)0;
   if (a.three_d) {
     const int m = kyi <= a.J / 2 ? kyi : kyi - a.J;
-    kmid2 = ((double)m * a.sy) * ((double)m * a.sy);
+    kmid2 = ((T)m * (T)a.sy) * ((T)m * (T)a.sy);
   }
-  const double klast_s = a.three_d ? a.sz : a.sy;
+  const T klast_s = (T)(a.three_d ? a.sz : a.sy);
 
   if (packed_block) {
     // The kx = 0 lines hold S(0) + i S(Nx/2).  With the mirror mode m(-k):
@@ -664,7 +710,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     int mls = ls;
     if (a.three_d && (slot >> 1) != 0) mls = ls ^ 1;
     const C<T>* xm = lds + mls * REG;
-    const double kny = (double)(a.nx / 2) * a.sx;
+    const T kny = (T)(a.nx / 2) * (T)a.sx;
 #pragma unroll
     for (int e = 0; e < 8; ++e) x[0][pidx<T>(t + e * S)] = ct[0][e];
     __syncthreads();
@@ -674,8 +720,8 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
         __builtin_amdgcn_sched_barrier(0);
         const int p = t + e * S;
         const int m = p <= NL / 2 ? p : p - NL;
-        const double kl = (double)m * klast_s;
-        const double k2_0 = kmid2 + kl * kl;
+        const T kl = (T)m * klast_s;
+        const T k2_0 = kmid2 + kl * kl;
         T a0, b0, an, bn;
         etd1_coeffs<T>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
         etd1_coeffs<T>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
@@ -693,9 +739,9 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
       __builtin_amdgcn_sched_barrier(0);
       const int p = t + e * S;
       const int m = p <= NL / 2 ? p : p - NL;
-      const double kl = (double)m * klast_s;
+      const T kl = (T)m * klast_s;
       if (packed) {
-        const double k2_0 = kmid2 + kl * kl;
+        const T k2_0 = kmid2 + kl * kl;
         T a0, b0, an, bn;
         etd1_coeffs<T>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
         etd1_coeffs<T>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
@@ -704,7 +750,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
         ct[0][e] = mk<T>(ct[0][e].x + bp * cg[0][e].x + bmn * dm.x,
                          ct[0][e].y + bp * cg[0][e].y + bmn * dm.y);
       } else {
-        const double k2 = kxv * kxv + kmid2 + kl * kl;
+        const T k2 = kxv * kxv + kmid2 + kl * kl;
         T av, bv;
         etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
         ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
@@ -719,8 +765,8 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
       __builtin_amdgcn_sched_barrier(0);
       const int p = t + e * S;
       const int m = p <= NL / 2 ? p : p - NL;
-      const double kl = (double)m * klast_s;
-      const double k2 = kxv * kxv + kmid2 + kl * kl;
+      const T kl = (T)m * klast_s;
+      const T k2 = kxv * kxv + kmid2 + kl * kl;
       T av, bv;
       etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
       ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
@@ -729,7 +775,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
 
   fft_lines<T, NL, +1, 1>(ct, x, t, tw);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) so[sidx(kxi, srow + t + e * S, hx, lb)] = ct[0][e];
+  for (int e = 0; e < 8; ++e) *kline_at(so, kline_off(e * S, hx, lb), tb) = ct[0][e];
 }
 
 template <typename T, int NL>
