@@ -83,7 +83,14 @@ constexpr int y_reg(int esz, int ny) {
 }
 constexpr int64_t y_lds(int esz, int ny, int lines) { return (int64_t)lines * y_reg(esz, ny) * esz; }
 constexpr int k_reg(int esz, int nl) { return padded_len_e(esz, nl); }
-constexpr int64_t k_lds(int esz, int nl, int lines) { return (int64_t)lines * k_reg(esz, nl) * esz; }
+// twiddle bases per thread of an nl-point transform (Twiddles<T, nl>::NW)
+constexpr int k_nw(int nl) {
+  return ((ilog2c(nl) + 2) / 3) > 1 ? ((ilog2c(nl) + 2) / 3) - 1 : 1;
+}
+// FP64 k-space blocks keep the twiddle bases in LDS after the line regions
+constexpr int64_t k_lds(int esz, int nl, int lines) {
+  return (int64_t)lines * (k_reg(esz, nl) + (esz == 16 ? (nl / 8) * k_nw(nl) : 0)) * esz;
+}
 
 // ---------------------------------------------------------------------------
 // x pass
@@ -639,6 +646,20 @@ __device__ __forceinline__ P* kline_at(P* base, int64_t uo, uint32_t tb) {
   return reinterpret_cast<P*>(reinterpret_cast<B*>(base + uo) + tb);
 }
 
+// Twiddle bases of a k-space thread: from registers (FP32) or from its LDS
+// entries (FP64).
+template <typename T, int NL>
+__device__ __forceinline__ Twiddles<T, NL> ktw(const Twiddles<T, NL>& tw, const C<T>* twl, int stride) {
+  if constexpr (sizeof(T) == 8) {
+    Twiddles<T, NL> r;
+#pragma unroll
+    for (int i = 0; i < Twiddles<T, NL>::NW; ++i) r.w[i] = twl[i * stride];
+    return r;
+  } else {
+    return tw;
+  }
+}
+
 template <typename T, int NL>
 struct KCfg {
   static constexpr int S = NL / 8;
@@ -686,11 +707,21 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   for (int e = 0; e < 8; ++e) ct[0][e] = *kline_at(st, kline_off(e * S, hx, lb), tb);
   // one LDS region per line serves all three transforms in turn
   C<T>* x[1] = {lds + ls * REG};
+  // FP64 parks the twiddle bases in LDS between the transforms (entry i of
+  // thread j at i * L*S + j): the registers they free let three waves share
+  // a SIMD.  Each thread reads back only what it wrote.
+  C<T>* const twl = lds + a.lines_per_block * REG + ls * S + t;
+  const int twstride = a.lines_per_block * S;
+  static_assert(Twiddles<T, NL>::NW == k_nw(NL), "LDS twiddle table size");
   const Twiddles<T, NL> tw = make_twiddles<T, NL>(t);
-  fft_lines<T, NL, -1, 1>(ct, x, t, tw);
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int i = 0; i < Twiddles<T, NL>::NW; ++i) twl[i * twstride] = tw.w[i];
+  }
+  fft_lines<T, NL, -1, 1>(ct, x, t, ktw<T, NL>(tw, twl, twstride));
 #pragma unroll
   for (int e = 0; e < 8; ++e) cg[0][e] = *kline_at(gn, kline_off(e * S, hx, lb), tb);
-  fft_lines<T, NL, -1, 1>(cg, x, t, tw);
+  fft_lines<T, NL, -1, 1>(cg, x, t, ktw<T, NL>(tw, twl, twstride));
 
   // wavenumbers: k_last from the position, k_mid from kyi (3D), k_x from kxi
   const T kxv = (T)kxi * (T)a.sx;
@@ -773,13 +804,14 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     }
   }
 
-  fft_lines<T, NL, +1, 1>(ct, x, t, tw);
+  fft_lines<T, NL, +1, 1>(ct, x, t, ktw<T, NL>(tw, twl, twstride));
 #pragma unroll
   for (int e = 0; e < 8; ++e) *kline_at(so, kline_off(e * S, hx, lb), tb) = ct[0][e];
 }
 
 template <typename T, int NL>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SS_KWAVES))) kpass_kernel(KArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : SS_KWAVES)))
+kpass_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
   kpass_body<T, NL>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
