@@ -97,6 +97,19 @@ def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
     # events (per-launch events add a completion fence to every launch)
     prof["mean_b2b"] = {k: g.time_pass(k, 200) for k in prof}
     mass = g.mass_log()
+    # one radially averaged structure factor of the evolved field (x pass with
+    # the occupancy threshold, line transforms, binning), back to back
+    L = [n * d for n, d in zip(w.n, w.dx)]
+    if max(L) - min(L) <= 1e-12 * max(L):
+        s_k, n_k = g.structure_factor(0)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(20):
+            g.structure_factor(0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prof["structure_factor"] = {"ms_per_call": round(e0.elapsed_time(e1) / 20, 4),
+                                    "nbins": int(s_k.numel())}
     g.close()
     prof["tiles"] = tiles
     return ms, wall, prof, mass
@@ -292,12 +305,14 @@ def main():
     ms, wall, prof, mass = run_gpu(w, args.dtype, args.steps, args.warmup, args.profile_steps,
                                    not args.no_autotune)
     value = w.cells * args.steps / (ms * 1e-3)
+    sf1 = prof.pop("structure_factor", None)
     roof = roofline(w, args.dtype, prof, load_traffic(args.workload, args.dtype))
     other = "f32" if args.dtype == "f64" else "f64"
     print("bench: %s done, %.3f ms/step; running %s" % (args.dtype, ms / args.steps, other),
           file=sys.stderr, flush=True)
     ms2, _, prof2, _ = run_gpu(w, other, args.steps, args.warmup, args.profile_steps,
                                not args.no_autotune)
+    sf2 = prof2.pop("structure_factor", None)
     roof2 = roofline(w, other, prof2, load_traffic(args.workload, other))
     drift = float(abs(mass[-1][0] - mass[0][0])) if len(mass) else None
     adj = None
@@ -327,6 +342,9 @@ def main():
         "other_dtype": {"dtype": other, "value": round(w.cells * args.steps / (ms2 * 1e-3), 1),
                         "ms_per_step": round(ms2 / args.steps, 5), "roofline": roof2},
         "mass_drift_over_run": drift,
+        "structure_factor": {
+            "what": "radially averaged S(k) of [psi > 0] of the evolved field, one call",
+            args.dtype: sf1, other: sf2},
         "batched": batch,
         "adjoint": adj,
         "wall_s_timed_region": round(wall, 4),

@@ -245,6 +245,33 @@ ss_status ss_bind_mass_log(ss_grid g, double* device_ptr, int64_t capacity);
 /* Number of steps taken since the mass log was bound. */
 ss_status ss_mass_log_count(ss_grid g, int64_t* count);
 
+/* ---- Structure factor (Sec. 3, coarsening check against Porod's law) ----
+ *
+ * The radially averaged static structure factor of one field: the
+ * occupancy rho = 1 where psi > 0 and 0 elsewhere (the positive phase
+ * stands for the solid), its unnormalised DFT rho_hat over every axis,
+ * S(k) = |rho_hat_k|^2 / N (N = cells, so that S summed over all modes is
+ * the number of occupied cells), and the mean of S over the modes of each
+ * radial bin b = round(|m|), m the integer mode vector (m_j in
+ * -N_j/2 .. N_j/2 - 1).  Porod's law (Eq. 14) predicts S ~ k^-(d+1) in the
+ * scaling regime; the paper averages S over 10 independent runs.
+ *
+ * ss_structure_factor_nbins: *nbins = number of bins of this grid,
+ *   round(|m|max) + 1 with |m|max^2 = sum_j (N_j/2)^2.
+ * ss_structure_factor: s_out[b] = mean S over bin b (0 for an empty bin),
+ *   n_out[b] = number of modes in bin b; both device pointers of exactly
+ *   nbins elements, written on the grid's stream (no synchronisation).
+ *   The field's state is not modified; the grid's nonlinear-term scratch
+ *   and staging arrays are overwritten (calls on one grid are ordered on
+ *   its stream).  Per-bin sums are added in a fixed order across
+ *   workgroups; within a workgroup LDS atomics make the last bits of a sum
+ *   depend on scheduling.  Errors: SS_ERR_ARG (null pointer, field out of
+ *   range, nbins not the grid's), SS_ERR_STATE (no model, workspace or
+ *   field), SS_ERR_UNSUPPORTED (box lengths N_j dx_j not all equal, or no
+ *   tiling fits). */
+ss_status ss_structure_factor_nbins(ss_grid g, int* nbins);
+ss_status ss_structure_factor(ss_grid g, int field, double* s_out, int64_t* n_out, int nbins);
+
 /* Change the stream later calls enqueue on. */
 ss_status ss_set_stream(ss_grid g, void* stream);
 

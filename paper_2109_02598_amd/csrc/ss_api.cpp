@@ -283,7 +283,7 @@ void ensure_tiles(ss_grid g) {
 template <typename T>
 ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void* in1, void* out0,
                        void* out1, const void* real_in, void* real_out, double scale,
-                       PassTimer* pt = nullptr) {
+                       PassTimer* pt = nullptr, int nlm = -1) {
   ss::XArgs a;
   memset(&a, 0, sizeof(a));
   a.spec_in[0] = in0;
@@ -302,7 +302,8 @@ ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void*
   a.tiles_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_ppb : 0;
   a.lb = g->lb;
   for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
-  return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, g->nlm, a, g->stream, take_events(pt, PASS_X)),
+  return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, nlm >= 0 ? nlm : g->nlm, a, g->stream,
+                                    take_events(pt, PASS_X)),
                    "x pass launch");
 }
 
@@ -393,6 +394,76 @@ ss_status get_field_t(ss_grid g, int field, void* ddst) {
     spec = g->scratch[field];
   }
   return launch_xpass<T>(g, ss::XMODE_INV, 1, spec, nullptr, nullptr, nullptr, nullptr, ddst, 1.0);
+}
+
+// ---- structure factor (Sec. 3) ---------------------------------------------
+// Number of radial bins: b = round(|m|) over the grid's integer mode vectors.
+int sf_nbins(ss_grid g) {
+  int64_t m2 = 0;
+  for (int d = 0; d < g->ndim; ++d) m2 += (g->n[d] / 2) * (g->n[d] / 2);
+  int64_t b = (int64_t)std::sqrt((double)m2);
+  while (b * b + b < m2) ++b;
+  while (b > 0 && b * b - b >= m2) --b;
+  return (int)b + 1;
+}
+
+// |k| = 2 pi |m| / L needs the same box length along every axis
+bool sf_isotropic(ss_grid g) {
+  const double l0 = (double)g->n[0] * g->dx[0];
+  for (int d = 1; d < g->ndim; ++d) {
+    const double l = (double)g->n[d] * g->dx[d];
+    if (std::fabs(l - l0) > 1e-12 * std::fabs(l0)) return false;
+  }
+  return true;
+}
+
+template <typename T>
+ss_status sf_run(ss_grid g, int field, double* s_out, int64_t* n_out, int nbins) {
+  const bool three = g->ndim == 3;
+  void* rho = g->scratch[0];
+  // occupancy spectrum: 3D inverse y first, then the x pass with the
+  // threshold in place of f, then (3D) the forward y transform
+  if (three) {
+    SS_TRY(launch_ypass<T>(g, +1, g->state[field], rho, 1.0));
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, 1, rho, nullptr, rho, nullptr, nullptr, nullptr, 1.0, nullptr,
+                           ss::NLIN_THRESH));
+    SS_TRY(launch_ypass<T>(g, -1, rho, rho, 1.0));
+  } else {
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, 1, g->state[field], nullptr, rho, nullptr, nullptr, nullptr, 1.0,
+                           nullptr, ss::NLIN_THRESH));
+  }
+  ss::SFArgs a;
+  memset(&a, 0, sizeof(a));
+  a.spec = rho;
+  a.nbins = nbins;
+  a.J = three ? (int)g->n[1] : 1;
+  a.nlines = (int)(g->n[0] / 2) * a.J;
+  a.nx = (int)g->n[0];
+  a.three_d = three ? 1 : 0;
+  a.lb = g->lb;
+  a.inv_n = 1.0 / (double)g->cells();
+  const int nl = (int)(three ? g->n[2] : g->n[1]);
+  const int esz = esz_of(g);
+  ensure_tiles(g);
+  int L = g->tile_k;
+  while (L > (three ? 2 : 1) && !ss::sf_tile_ok(esz, nl, a.nlines, three, L, nbins)) L /= 2;
+  if (!ss::sf_tile_ok(esz, nl, a.nlines, three, L, nbins))
+    return fail(SS_ERR_UNSUPPORTED, "ss_structure_factor: no line tiling fits this grid");
+  a.lines_per_block = L;
+  // per-block partial histograms in the staging array
+  const int64_t per_block = (int64_t)nbins * (int64_t)(sizeof(double) + sizeof(uint32_t));
+  const int64_t cap = (int64_t)g->field_bytes() / per_block;
+  int64_t nblk = a.nlines / L;
+  if (nblk > 512) nblk = 512;
+  if (nblk > cap) nblk = cap;
+  if (nblk < 1) return fail(SS_ERR_UNSUPPORTED, "ss_structure_factor: grid too small for %d bins", nbins);
+  a.nblocks = (int)nblk;
+  a.part_sum = (double*)g->staging;
+  a.part_cnt = (uint32_t*)((char*)g->staging + (size_t)nblk * nbins * sizeof(double));
+  a.s_out = s_out;
+  a.n_out = n_out;
+  SS_TRY(hip_check(ss::run_sfpass<T>(nl, a, g->stream), "structure factor pass launch"));
+  return hip_check(ss::run_sfreduce<T>(a, g->stream), "structure factor reduce launch");
 }
 
 // Time one launch configuration: one warm-up launch, then `reps` launches
@@ -1110,6 +1181,25 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps) {
     if (st != SS_OK) return st;
   }
   return SS_OK;
+}
+
+ss_status ss_structure_factor_nbins(ss_grid g, int* nbins) {
+  if (!g || !nbins) return fail(SS_ERR_ARG, "ss_structure_factor_nbins: null argument");
+  *nbins = sf_nbins(g);
+  return SS_OK;
+}
+
+ss_status ss_structure_factor(ss_grid g, int field, double* s_out, int64_t* n_out, int nbins) {
+  if (!g || !s_out || !n_out) return fail(SS_ERR_ARG, "ss_structure_factor: null argument");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_structure_factor: model and workspace must be set first");
+  if (field < 0 || field >= g->nf) return fail(SS_ERR_ARG, "ss_structure_factor: field %d out of range", field);
+  if (!g->field_set[field]) return fail(SS_ERR_STATE, "ss_structure_factor: field %d was never set", field);
+  if (nbins != sf_nbins(g))
+    return fail(SS_ERR_ARG, "ss_structure_factor: nbins must be %d for this grid", sf_nbins(g));
+  if (!sf_isotropic(g))
+    return fail(SS_ERR_UNSUPPORTED, "ss_structure_factor: the box must have the same length along every axis");
+  return g->dtype == SS_F64 ? sf_run<double>(g, field, s_out, n_out, nbins)
+                            : sf_run<float>(g, field, s_out, n_out, nbins);
 }
 
 ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t* pass_count,

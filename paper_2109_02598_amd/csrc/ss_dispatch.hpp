@@ -96,6 +96,13 @@ inline int k_tile_default(int esz, int nl, int64_t nlines, bool three_d) {
   return l;
 }
 
+// structure-factor pass: the k-space line tiling plus the LDS histogram
+inline bool sf_tile_ok(int esz, int nl, int64_t nlines, bool three_d, int lines, int nbins) {
+  const int S = nl / 8;
+  return is_pow2(lines) && lines <= nlines && nlines % lines == 0 && lines * S <= k_max_threads() &&
+         (!three_d || lines >= 2) && sf_lds(esz, nl, lines, nbins) <= LDS_BUDGET;
+}
+
 // batched (grouped) launches: `threads` per block, `blocks` blocks
 template <typename T>
 hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev);
@@ -130,6 +137,10 @@ template <typename T>
 hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s, LaunchEvents ev);
 template <typename T>
 hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev);
+template <typename T>
+hipError_t run_sfpass(int nl, SFArgs a, hipStream_t s);
+template <typename T>
+hipError_t run_sfreduce(SFArgs a, hipStream_t s);
 
 #ifdef SS_DISPATCH_IMPL
 
@@ -182,6 +193,7 @@ template <typename T>
 hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s, LaunchEvents ev) {
   if (mode == XMODE_FWD) return xdisp<T, 1, XMODE_FWD, NLIN_POLY>(nx, a, s, ev);
   if (mode == XMODE_INV) return xdisp<T, 1, XMODE_INV, NLIN_POLY>(nx, a, s, ev);
+  if (nf == 1 && nlm == NLIN_THRESH) return xdisp<T, 1, XMODE_STEP, NLIN_THRESH>(nx, a, s, ev);
   if (nf == 1) return xdisp<T, 1, XMODE_STEP, NLIN_POLY>(nx, a, s, ev);
   if (nlm == NLIN_GS) return xdisp<T, 2, XMODE_STEP, NLIN_GS>(nx, a, s, ev);
   return xdisp<T, 2, XMODE_STEP, NLIN_MODELC>(nx, a, s, ev);
@@ -227,6 +239,34 @@ hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev) {
 #undef SS_CASE
   }
   return hipErrorInvalidValue;
+}
+
+template <typename T, int NL>
+hipError_t launch_sf(SFArgs a, hipStream_t s) {
+  constexpr int ESZ = (int)sizeof(C<T>);
+  const int L = a.lines_per_block;
+  if (!sf_tile_ok(ESZ, NL, a.nlines, a.three_d != 0, L, a.nbins) || a.nblocks < 1)
+    return hipErrorInvalidConfiguration;
+  return launch_with(sfpass_kernel<T, NL>, dim3((unsigned)a.nblocks), dim3((unsigned)(L * (NL / 8))),
+                     (uint32_t)sf_lds(ESZ, NL, L, a.nbins), s, LaunchEvents(), a);
+}
+
+template <typename T>
+hipError_t run_sfpass(int nl, SFArgs a, hipStream_t s) {
+  switch (nl) {
+#define SS_CASE(n) \
+  case n:          \
+    return launch_sf<T, n>(a, s);
+    SS_POW2_CASES(SS_CASE)
+#undef SS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t run_sfreduce(SFArgs a, hipStream_t s) {
+  return launch_with(sf_reduce_kernel<T>, dim3((unsigned)((a.nbins + 7) / 8)), dim3(256), 0, s,
+                     LaunchEvents(), a);
 }
 
 template <typename T>
@@ -287,7 +327,9 @@ hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
   template hipError_t run_batch_k<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t, LaunchEvents); \
   template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t, LaunchEvents);  \
-  template hipError_t run_kpass<T>(int, KArgs, hipStream_t, LaunchEvents);
+  template hipError_t run_kpass<T>(int, KArgs, hipStream_t, LaunchEvents);                \
+  template hipError_t run_sfpass<T>(int, SFArgs, hipStream_t);                            \
+  template hipError_t run_sfreduce<T>(SFArgs, hipStream_t);
 
 #endif  // SS_DISPATCH_IMPL
 

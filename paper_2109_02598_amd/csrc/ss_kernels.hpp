@@ -33,7 +33,9 @@
 namespace ss {
 
 enum { XMODE_FWD = 0, XMODE_INV = 1, XMODE_STEP = 2 };
-enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2 };
+// NLIN_THRESH is no equation of motion: it maps psi to the occupancy
+// [psi > 0] of the structure factor (Sec. 3).
+enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2, NLIN_THRESH = 3 };
 
 constexpr int LDS_BUDGET = 160 * 1024;
 
@@ -233,6 +235,10 @@ __device__ __forceinline__ void nonlinear(C<T>* c0, C<T>* c1, T p0, T p1, T p2) 
     T wx = ux * vx * vx, wy = uy * vy * vy;
     c0->x = F - wx; c0->y = F - wy;
     c1->x = wx;     c1->y = wy;
+  } else if constexpr (NLM == NLIN_THRESH) {
+    // occupancy rho = 1 where psi > 0, else 0, on both packed rows
+    c0->x = c0->x > (T)0 ? (T)1 : (T)0;
+    c0->y = c0->y > (T)0 ? (T)1 : (T)0;
   } else {
     // model C: f_psi = -c2 psi^3 + 2 c5 psi m ; f_m = -c4 m^3 + c5 psi^2
     const T c2 = p0, c4 = p1, c5 = p2;
@@ -660,6 +666,24 @@ __device__ __forceinline__ Twiddles<T, NL> ktw(const Twiddles<T, NL>& tw, const 
   }
 }
 
+// Line slot -> (kx index, mid-axis index).  Slots 0 .. J-1 are the packed
+// kx = 0 plane; in 3D they are ordered so that each line sits next to its
+// mirror (-k_mid): pairs (0, J/2), then (j, J - j).
+__device__ __forceinline__ void kline_slot(int slot, int J, int three_d, int& kxi, int& kyi) {
+  if (slot < J) {
+    kxi = 0;
+    if (!three_d) {
+      kyi = 0;
+    } else {
+      const int pi = slot >> 1, mem = slot & 1;
+      kyi = (pi == 0) ? (mem ? J / 2 : 0) : (mem ? J - pi : pi);
+    }
+  } else {
+    kxi = slot / J;
+    kyi = slot - kxi * J;
+  }
+}
+
 template <typename T, int NL>
 struct KCfg {
   static constexpr int S = NL / 8;
@@ -678,19 +702,8 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   const int line0 = bx * a.lines_per_block;
   const int slot = line0 + ls;               // global line slot
   const bool packed_block = line0 < a.J;     // block holds kx = 0 lines
-  // plane-0 slots are ordered so that each line sits next to its mirror
   int kxi, kyi;
-  if (slot < a.J) {
-    kxi = 0;
-    if (!a.three_d) kyi = 0;
-    else {
-      const int pi = slot >> 1, mem = slot & 1;
-      kyi = (pi == 0) ? (mem ? a.J / 2 : 0) : (mem ? a.J - pi : pi);
-    }
-  } else {
-    kxi = slot / a.J;
-    kyi = slot - kxi * a.J;
-  }
+  kline_slot(slot, a.J, a.three_d, kxi, kyi);
   // element p of this line is row s = kyi*NL + p of plane kxi; the line
   // start is a multiple of NL, and the row block B is at most NL
   const int64_t hx = a.nx / 2;
@@ -814,6 +827,172 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 kpass_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
   kpass_body<T, NL>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
+}
+
+// ---------------------------------------------------------------------------
+// Structure factor (Sec. 3): radial average of S(k) = |rho_hat_k|^2 / N for
+// the occupancy rho = [psi > 0].  The x pass (NLIN_THRESH) has already
+// formed the x-spectrum of rho (3D: also transformed along y) in the layout
+// of the state; this pass transforms each line along the last axis and
+// bins every mode by b = round(|m|), m the integer mode vector (the box has
+// the same length along every axis, so |k| = 2 pi |m| / L).  Each block
+// accumulates a histogram in LDS over its lines (several, persistently) and
+// writes it to its own row of a partials array; sf_reduce adds the rows in
+// block order.
+// ---------------------------------------------------------------------------
+struct SFArgs {
+  const void* spec;        // transformed occupancy, layout of the state
+  double* part_sum;        // [gridDim.x][nbins] per-block sums of |rho_hat|^2 / N
+  uint32_t* part_cnt;      // [gridDim.x][nbins] per-block mode counts
+  double* s_out;           // [nbins] radial average (sf_reduce)
+  int64_t* n_out;          // [nbins] modes per bin (sf_reduce)
+  int nbins;
+  int nblocks;             // rows of the partials
+  int nlines, J, lines_per_block, nx, three_d, lb;
+  double inv_n;            // 1/N
+};
+
+constexpr int64_t sf_lds(int esz, int nl, int lines, int nbins) {
+  return (int64_t)lines * k_reg(esz, nl) * esz + (int64_t)nbins * (8 + 4);
+}
+
+// b = round(sqrt(m2)) for an integer m2 >= 0: the b with b^2 - b < m2 <= b^2 + b
+__device__ __forceinline__ int sf_bin(int64_t m2) {
+  int64_t b = (int64_t)sqrt((double)m2);
+  while (b * b + b < m2) ++b;
+  while (b > 0 && b * b - b >= m2) --b;
+  return (int)b;
+}
+
+template <typename T, int NL>
+__device__ __forceinline__ void sf_tile(const SFArgs& a, int tile, C<T>* lds, double* hs, uint32_t* hc) {
+  typedef KCfg<T, NL> K;
+  constexpr int S = K::S, REG = K::REG;
+  const int tid = threadIdx.x;
+  const int ls = tid / S, t = tid - ls * S;
+  const int line0 = tile * a.lines_per_block;
+  const int slot = line0 + ls;
+  const bool packed_block = line0 < a.J;
+  int kxi, kyi;
+  kline_slot(slot, a.J, a.three_d, kxi, kyi);
+  const int64_t hx = a.nx / 2;
+  const int lb = a.lb;
+  const int64_t lbase = sidx(kxi, (int64_t)kyi * NL, hx, lb);
+  const C<T>* src = (const C<T>*)a.spec + lbase;
+  const uint32_t tb = (uint32_t)(kline_off(t, hx, lb) * (int64_t)sizeof(C<T>));
+  C<T> c[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) c[0][e] = *kline_at(src, kline_off(e * S, hx, lb), tb);
+  C<T>* x[1] = {lds + ls * REG};
+  fft_lines<T, NL, -1, 1>(c, x, t, make_twiddles<T, NL>(t));
+  // integer mode components other than x
+  int64_t mmid2 = 0;
+  if (a.three_d) {
+    const int64_t m = kyi <= a.J / 2 ? kyi : kyi - a.J;
+    mmid2 = m * m;
+  }
+  const double w = a.inv_n;
+  bool done = false;
+  if (packed_block) {
+    // the kx = 0 plane holds C = rho_hat(0, .) + i rho_hat(Nx/2, .); with the
+    // mirror mode C(-k): rho_hat(0, k) = (C + conj C(-k))/2,
+    // rho_hat(Nx/2, k) = (C - conj C(-k))/(2i).  Lines of the block that
+    // are not in that plane fall through to the general case below.
+    const bool packed = slot < a.J;
+    int mls = ls;
+    if (a.three_d && (slot >> 1) != 0) mls = ls ^ 1;
+    const C<T>* xm = lds + mls * REG;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[0][pidx<T>(t + e * S)] = c[0][e];
+    __syncthreads();
+    if (packed) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int p = t + e * S;
+        const int64_t ml = p <= NL / 2 ? p : p - NL;
+        const C<T> cm = xm[pidx<T>((NL - p) & (NL - 1))];
+        const double ar = 0.5 * ((double)c[0][e].x + (double)cm.x), ai = 0.5 * ((double)c[0][e].y - (double)cm.y);
+        const double br = 0.5 * ((double)c[0][e].y + (double)cm.y), bi = 0.5 * ((double)cm.x - (double)c[0][e].x);
+        const int b0 = sf_bin(mmid2 + ml * ml);
+        const int bn = sf_bin(hx * hx + mmid2 + ml * ml);
+        atomicAdd(&hs[b0], (ar * ar + ai * ai) * w);
+        atomicAdd(&hc[b0], 1u);
+        atomicAdd(&hs[bn], (br * br + bi * bi) * w);
+        atomicAdd(&hc[bn], 1u);
+      }
+      done = true;
+    }
+  }
+  if (!done) {
+    // kx and -kx have the same |rho_hat| and |m|: weight 2
+    const int64_t mx2 = (int64_t)kxi * kxi;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int p = t + e * S;
+      const int64_t ml = p <= NL / 2 ? p : p - NL;
+      const double re = (double)c[0][e].x, im = (double)c[0][e].y;
+      const int b = sf_bin(mx2 + mmid2 + ml * ml);
+      atomicAdd(&hs[b], 2.0 * (re * re + im * im) * w);
+      atomicAdd(&hc[b], 2u);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NL>
+__global__ void __launch_bounds__(512) sfpass_kernel(SFArgs a) {
+  typedef KCfg<T, NL> K;
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
+  double* hs = reinterpret_cast<double*>(lds + a.lines_per_block * K::REG);
+  uint32_t* hc = reinterpret_cast<uint32_t*>(hs + a.nbins);
+  for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) {
+    hs[i] = 0.0;
+    hc[i] = 0u;
+  }
+  __syncthreads();
+  const int ntiles = a.nlines / a.lines_per_block;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) sf_tile<T, NL>(a, tile, lds, hs, hc);
+  __syncthreads();
+  double* ps = a.part_sum + (int64_t)blockIdx.x * a.nbins;
+  uint32_t* pc = a.part_cnt + (int64_t)blockIdx.x * a.nbins;
+  for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) {
+    ps[i] = hs[i];
+    pc[i] = hc[i];
+  }
+}
+
+// Reduction of the partials: a block takes 8 bins; thread (slice j, bin i)
+// adds rows j, j + 32, j + 64, ... of bin i in order, then the 32 slice
+// sums of each bin are added in slice order (the same order every call).
+template <typename T>
+__global__ void __launch_bounds__(256) sf_reduce_kernel(SFArgs a) {
+  __shared__ double ps[32][8];
+  __shared__ int64_t pn[32][8];
+  const int i = threadIdx.x & 7, j = threadIdx.x >> 3;
+  const int b = blockIdx.x * 8 + i;
+  double s = 0.0;
+  int64_t n = 0;
+  if (b < a.nbins) {
+    for (int k = j; k < a.nblocks; k += 32) {
+      s += a.part_sum[(int64_t)k * a.nbins + b];
+      n += a.part_cnt[(int64_t)k * a.nbins + b];
+    }
+  }
+  ps[j][i] = s;
+  pn[j][i] = n;
+  __syncthreads();
+  if (j == 0 && b < a.nbins) {
+    double t = 0.0;
+    int64_t m = 0;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      t += ps[q][i];
+      m += pn[q][i];
+    }
+    a.s_out[b] = m ? t / (double)m : 0.0;
+    a.n_out[b] = m;
+  }
 }
 
 }  // namespace ss

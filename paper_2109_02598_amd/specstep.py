@@ -63,6 +63,8 @@ def lib():
         "ss_get_tiles": [vp, ctypes.POINTER(cint)],
         "ss_set_tiles": [vp, ctypes.POINTER(cint)],
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
+        "ss_structure_factor_nbins": [vp, ctypes.POINTER(cint)],
+        "ss_structure_factor": [vp, cint, vp, vp, cint],
         "ss_set_stream": [vp, vp],
         "ss_destroy_grid": [vp],
         "ss_adjoint_workspace_size": [vp, i64, cint, ctypes.POINTER(ctypes.c_size_t)],
@@ -189,6 +191,16 @@ def ss_mass_log_count(h):
     c = ctypes.c_int64()
     _check(lib().ss_mass_log_count(h, ctypes.byref(c)))
     return c.value
+
+
+def ss_structure_factor_nbins(h):
+    n = ctypes.c_int()
+    _check(lib().ss_structure_factor_nbins(h, ctypes.byref(n)))
+    return n.value
+
+
+def ss_structure_factor(h, field, s_ptr, n_ptr, nbins):
+    _check(lib().ss_structure_factor(h, int(field), s_ptr, n_ptr, int(nbins)))
 
 
 def ss_set_stream(h, stream):
@@ -389,6 +401,15 @@ class Grid:
         self.mass_buf = self.torch.zeros(capacity * self.nfields, dtype=self.torch.float64,
                                          device=self.device)
         ss_bind_mass_log(self.h, self.mass_buf.data_ptr(), capacity)
+
+    def structure_factor(self, field=0):
+        """Radially averaged S(k) of the occupancy [psi > 0] of one field:
+        (mean S per bin, modes per bin) as device tensors (float64, int64)."""
+        nb = ss_structure_factor_nbins(self.h)
+        s = self.torch.empty(nb, dtype=self.torch.float64, device=self.device)
+        n = self.torch.empty(nb, dtype=self.torch.int64, device=self.device)
+        ss_structure_factor(self.h, field, s.data_ptr(), n.data_ptr(), nb)
+        return s, n
 
     def mass_log(self):
         cnt = min(ss_mass_log_count(self.h), self.mass_buf.numel() // self.nfields)
