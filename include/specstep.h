@@ -229,8 +229,9 @@ ss_status ss_batch_capture(ss_batch b, int64_t nsteps);
 /* Replay the captured graph once on the batch's stream (nsteps steps). */
 ss_status ss_batch_launch(ss_batch b);
 
-/* Threads per block in use and the number of blocks of the grouped x and
- * k launches: info[0..2]. */
+/* info[0] = threads per block of the grouped k-space launch (the grouped
+ * x launch uses the largest power of two <= info[0] that tiles every
+ * member), info[1], info[2] = blocks of the grouped x and k launches. */
 ss_status ss_batch_info(ss_batch b, int info[3]);
 
 ss_status ss_batch_destroy(ss_batch b);

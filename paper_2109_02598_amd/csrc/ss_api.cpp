@@ -667,7 +667,8 @@ struct ss_batch_s {
   hipStream_t stream = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  int threads = 256;
+  int threads = 256;       // k-space launch; the x launch may use fewer
+  int threads_x = 256;
   bool uploaded = false;
   std::vector<ss::BatchMember> table, table_tune;
   std::vector<void*> state_at_build;
@@ -682,22 +683,41 @@ namespace {
 
 bool batch_size_ok(int64_t n) { return n >= 64 && n <= 2048 && ss::is_pow2(n); }
 
-// Member table for `threads` threads per block; false if a member cannot
-// be tiled with that block size.
+// x-pass tile of one member for `tx` threads per block (0 if none)
+int batch_x_rows(ss_grid g, int tx) {
+  const int esz = esz_of(g);
+  const int nx = (int)g->n[0], ny = (int)g->n[1];
+  const int R = 2 * tx / (nx / ss::x_pts(esz, nx, 1));
+  if (R < 2 || !ss::x_tile_ok(esz, nx, 1, ny, R) || ss::x_threads(esz, nx, 1, R) != tx) return 0;
+  return R;
+}
+
+// Member table for `threads` threads per k-space block; the x launch takes
+// the largest power of two <= threads that tiles every member (16 points
+// per thread make a small grid's rows short of threads).  False if a member
+// cannot be tiled.
 bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& tab,
                        std::vector<ss::BatchMember>& tune, int& x_total, int& k_total, uint32_t& lds_x,
-                       uint32_t& lds_k) {
+                       uint32_t& lds_k, int& threads_x) {
   tab.clear();
   tune.clear();
   x_total = k_total = 0;
   lds_x = lds_k = 0;
+  threads_x = threads;
+  for (;;) {
+    bool ok = true;
+    for (int idx : b->order) ok = ok && batch_x_rows(b->grids[idx], threads_x) > 0;
+    if (ok) break;
+    threads_x /= 2;
+    if (threads_x < 64) return false;
+  }
   for (int idx : b->order) {
     ss_grid g = b->grids[idx];
     const int esz = esz_of(g);
     const int nx = (int)g->n[0], ny = (int)g->n[1];
-    const int R = 2 * threads / (nx / 8);
+    const int R = batch_x_rows(g, threads_x);
     const int L = threads / (ny / 8);
-    if (R < 2 || !ss::x_tile_ok(esz, nx, 1, ny, R) || ss::x_threads(esz, nx, R) != threads) return false;
+    if (R < 2) return false;
     if (L < 1 || !ss::k_tile_ok(esz, ny, nx / 2, false, L)) return false;
     ss::BatchMember m;
     memset(&m, 0, sizeof(m));
@@ -750,7 +770,8 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
 size_t batch_table_bytes(ss_batch b) { return align_up(sizeof(ss::BatchMember) * b->grids.size()); }
 
 ss_status batch_upload(ss_batch b, int threads) {
-  if (!build_batch_table(b, threads, b->table, b->table_tune, b->x_total, b->k_total, b->lds_x, b->lds_k))
+  if (!build_batch_table(b, threads, b->table, b->table_tune, b->x_total, b->k_total, b->lds_x, b->lds_k,
+                         b->threads_x))
     return fail(SS_ERR_UNSUPPORTED, "batch: a member cannot be tiled with %d threads per block", threads);
   const size_t tb = batch_table_bytes(b);
   SS_TRY(hip_check(hipMemcpyAsync(b->ws, b->table.data(), sizeof(ss::BatchMember) * b->table.size(),
@@ -783,7 +804,7 @@ ss_status batch_launch_step(ss_batch b, bool tune_table, ss::LaunchEvents evx, s
   a.count = (int)b->grids.size();
   a.x_total = b->x_total;
   a.k_total = b->k_total;
-  SS_TRY(hip_check(ss::run_batch_x<T>(a, b->threads, b->x_total, b->lds_x, b->stream, evx), "batch x launch"));
+  SS_TRY(hip_check(ss::run_batch_x<T>(a, b->threads_x, b->x_total, b->lds_x, b->stream, evx), "batch x launch"));
   return hip_check(ss::run_batch_k<T>(a, b->threads, b->k_total, b->lds_k, b->stream, evk), "batch k launch");
 }
 
@@ -1404,9 +1425,9 @@ ss_status ss_batch_autotune(ss_batch b, int reps) {
   float best = 1e30f;
   for (int threads : {128, 256, 512}) {
     std::vector<ss::BatchMember> t1, t2;
-    int xt, kt;
+    int xt, kt, tx;
     uint32_t lx, lk;
-    if (!build_batch_table(b, threads, t1, t2, xt, kt, lx, lk)) continue;
+    if (!build_batch_table(b, threads, t1, t2, xt, kt, lx, lk, tx)) continue;
     SS_TRY(batch_upload(b, threads));
     auto launch = [&](ss::LaunchEvents ev) {
       // x launch and k launch (on the tuning table) timed together

@@ -21,7 +21,6 @@ struct LaunchEvents {
 };
 
 // Threads per block limits (register budgets of the kernels).
-constexpr int x_max_threads(int esz) { return esz == 16 ? 512 : 1024; }
 constexpr int k_max_threads() { return 512; }
 constexpr int y_max_threads() { return 1024; }
 
@@ -33,19 +32,20 @@ inline bool x_tile_ok(int esz, int nx, int nf, int64_t nrows, int rows) {
   return is_pow2(rows) && rows >= 2 && rows <= 64 && rows <= nrows && nrows % rows == 0 &&
          x_lds(esz, nx, nf, rows) <= LDS_BUDGET;
 }
-inline int x_threads(int esz, int nx, int rows) {
-  const int S = nx / 8;
-  int G = x_max_threads(esz) / S;
+inline int x_threads(int esz, int nx, int nf, int rows) {
+  const int S = nx / x_pts(esz, nx, nf);
+  int G = x_block_threads(esz, nx, nf) / S;
   if (G > rows / 2) G = rows / 2;
   if (G < 1) G = 1;
   return G * S;
 }
-// persistent x pass: needs every pair of the tile in flight at once; its
-// two-field FP64 form would hold 16 prefetched complex values per thread
-// on top of the transform and is not built
+// persistent x pass: needs every pair of the tile in flight at once; only
+// built with 8 points per thread (with 16, or with two FP64 fields, the
+// prefetched values do not fit in the registers beside the transform)
 inline bool x_pp_ok(int esz, int nx, int nf, int64_t nrows, int rows) {
-  return x_tile_ok(esz, nx, nf, nrows, rows) && (rows / 2) * (nx / 8) <= 512 &&
-         (rows / 2) * (nx / 8) >= 64 && !(esz == 16 && nf == 2);
+  const int S = nx / x_pts(esz, nx, nf);
+  return x_tile_ok(esz, nx, nf, nrows, rows) && (rows / 2) * S <= 512 && (rows / 2) * S >= 64 &&
+         !(esz == 16 && nf == 2) && x_pts(esz, nx, nf) == 8;
 }
 inline int x_tile_default(int esz, int nx, int nf, int64_t nrows) {
   // at most 128 contiguous bytes per staged chunk, at most half the LDS
@@ -164,9 +164,9 @@ hipError_t launch_x(XArgs a, hipStream_t s, LaunchEvents ev) {
   const int R = a.rows_per_block;
   if (!x_tile_ok(ESZ, NX, NF, a.rows, R)) return hipErrorInvalidConfiguration;
   const int ntiles = (int)(a.rows / R);
-  const int threads = x_threads(ESZ, NX, R);
+  const int threads = x_threads(ESZ, NX, NF, R);
   const uint32_t lds = (uint32_t)x_lds(ESZ, NX, NF, R);
-  if constexpr (MODE == XMODE_STEP && !(sizeof(T) == 8 && NF == 2)) {
+  if constexpr (MODE == XMODE_STEP && !(sizeof(T) == 8 && NF == 2) && XCfg<T, NX, NF>::P == 8) {
     if (a.tiles_per_block > 1 && x_pp_ok(ESZ, NX, NF, a.rows, R)) {
       const int grid = (ntiles + a.tiles_per_block - 1) / a.tiles_per_block;
       return launch_with(xpass_pp_kernel<T, NX, NF, NLM>, dim3(grid), dim3(threads), lds, s, ev, a, ntiles);

@@ -94,6 +94,21 @@ constexpr int64_t k_lds(int esz, int nl, int lines) {
   return (int64_t)lines * (k_reg(esz, nl) + (esz == 16 ? (nl / 8) * k_nw(nl) : 0)) * esz;
 }
 
+#ifndef SS_XPTS16
+#define SS_XPTS16 1
+#endif
+// Points per thread of the x pass's transforms (the FFT's P): 16 (one LDS
+// exchange fewer per 2048-point transform than 8) except on 8-point rows
+// and in the two-field FP64 pass, which needs the registers for its second
+// field.  The other passes use 8.
+constexpr int x_pts(int esz, int nx, int nf) {
+  return (SS_XPTS16 && nx >= 16 && !(esz == 16 && nf == 2)) ? 16 : 8;
+}
+// threads per x-pass block: 512, or 1024 for FP32 with 8 points per thread
+constexpr int x_block_threads(int esz, int nx, int nf) {
+  return (esz == 8 && x_pts(esz, nx, nf) == 8) ? 1024 : 512;
+}
+
 // ---------------------------------------------------------------------------
 // x pass
 // ---------------------------------------------------------------------------
@@ -112,9 +127,10 @@ struct XArgs {
   double p[5];              // nonlinear coefficients
 };
 
-template <typename T, int NX>
+template <typename T, int NX, int NF>
 struct XCfg {
-  static constexpr int S = NX / 8;                  // threads per line
+  static constexpr int P = x_pts((int)sizeof(C<T>), NX, NF);   // points per thread
+  static constexpr int S = NX / P;                  // threads per line
   static constexpr int H = NX / 2;                  // stored kx count
   static constexpr int ESZ = (int)sizeof(C<T>);
   // HB = H + 1 is the offset of the second row of a pair in its region
@@ -140,7 +156,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap) {
 // nthr/R per element.  Eight loads are issued before their LDS writes; the
 // arrays are walked one after the other so that each pointer is chosen at
 // compile time.  Elements per thread and array: H*R/nthr, a multiple of 8
-// for the x-pass launch shapes (nthr = G*NX/8 with G dividing R/2).
+// for the x-pass launch shapes (nthr = G*NX/P with G dividing R/2).
 template <int H>
 __device__ __forceinline__ int64_t xstage_row(int64_t s, int lb) {
   return (((s >> lb) * H) << lb) + (s & ((int64_t(1) << lb) - 1));
@@ -250,11 +266,10 @@ __device__ __forceinline__ void nonlinear(C<T>* c0, C<T>* c1, T p0, T p1, T p2) 
   }
 }
 
-// threads per block of the x pass: FP64 needs the registers of 512-thread
-// blocks
-template <typename T, int NF>
+// threads per block of the x pass (launch bound)
+template <typename T, int NX, int NF>
 struct XThreads {
-  static constexpr int value = sizeof(T) == 8 ? 512 : 1024;
+  static constexpr int value = x_block_threads((int)sizeof(C<T>), NX, NF);
 };
 
 // One x-pass tile: rows blk*R .. blk*R+R-1 of the spectral layout.  The
@@ -263,8 +278,8 @@ struct XThreads {
 // (the persistent kernel below does, from registers it filled earlier).
 template <typename T, int NX, int NF, int MODE, int NLM, bool PRELOADED = false>
 __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* lds) {
-  typedef XCfg<T, NX> K;
-  constexpr int S = K::S, H = K::H, HB = K::HB;
+  typedef XCfg<T, NX, NF> K;
+  constexpr int S = K::S, H = K::H, HB = K::HB, PT = K::P;
   constexpr int REG = K::reg_for(NF);
 
   const int R = a.rows_per_block;
@@ -274,7 +289,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
   const int g = tid / S, t = tid - g * S;
   const int64_t s0 = blk * R;
   const int64_t rows = a.rows;
-  const Twiddles<T, NX> tw = make_twiddles<T, NX>(t);
+  const Twiddles<T, NX, PT> tw = make_twiddles<T, NX, PT>(t);
 
   if constexpr (MODE != XMODE_FWD && !PRELOADED) {
     const C<T>* src[NF];
@@ -290,7 +305,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
     C<T>* x[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) x[f] = lds + (pr * NF + f) * REG;
-    C<T> c[NF][8];
+    C<T> c[NF][PT];
     const int64_t sa = s0 + 2 * pr;            // spectral row of the pair's first row
 
     if constexpr (MODE == XMODE_FWD) {
@@ -300,13 +315,13 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
       const T* ra = rin + (za * a.ny + ya) * NX;
       const T* rb = rin + (zb * a.ny + yb) * NX;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) c[0][e] = mk<T>(ra[t + e * S], rb[t + e * S]);
+      for (int e = 0; e < PT; ++e) c[0][e] = mk<T>(ra[t + e * S], rb[t + e * S]);
     } else {
       // Z[k] = X_a[k] + i X_b[k] over the full length from the half spectra
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < PT; ++e) {
           const int k = t + e * S;
           C<T> z;
           if (k == 0) {
@@ -326,7 +341,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
         }
       }
       __syncthreads();
-      fft_lines<T, NX, +1, NF>(c, x, t, tw);
+      fft_lines<T, NX, +1, NF, PT>(c, x, t, tw);
       if constexpr (MODE == XMODE_INV) {
         T* rout = (T*)a.real_out;
         const int64_t za = sa % a.nz, ya = sa / a.nz;
@@ -334,7 +349,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
         T* ra = rout + (za * a.ny + ya) * NX;
         T* rb = rout + (zb * a.ny + yb) * NX;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < PT; ++e) {
           ra[t + e * S] = c[0][e].x;
           rb[t + e * S] = c[0][e].y;
         }
@@ -342,28 +357,28 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
       } else {
         const T p0 = (T)a.p[0], p1 = (T)a.p[1], p2 = (T)a.p[2];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < PT; ++e) {
           if constexpr (NF == 1) nonlinear<T, NLM>(&c[0][e], &c[0][e], p0, p1, p2);
           else nonlinear<T, NLM>(&c[0][e], &c[NF - 1][e], p0, p1, p2);
         }
       }
     }
     if constexpr (MODE != XMODE_INV) {
-      fft_lines<T, NX, -1, NF>(c, x, t, tw);
+      fft_lines<T, NX, -1, NF, PT>(c, x, t, tw);
       // natural-order spectrum to LDS, then split the two rows
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[f][pidx<T>(t + e * S)] = c[f][e];
+        for (int e = 0; e < PT; ++e) x[f][pidx<T>(t + e * S)] = c[f][e];
       }
       __syncthreads();
       const T sc = (T)a.scale;
       const T half = (T)0.5 * sc;
-      C<T> fa[NF][4], fb[NF][4];
+      C<T> fa[NF][PT / 2], fb[NF][PT / 2];
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < PT / 2; ++e) {
           const int k = t + e * S;               // 0 .. H-1
           C<T> w = x[f][pidx<T>(k)];
           if (k == 0) {
@@ -381,7 +396,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < PT / 2; ++e) {
           const int k = t + e * S;
           x[f][k] = fa[f][e];
           x[f][HB + k] = fb[f][e];
@@ -400,7 +415,7 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
 }
 
 template <typename T, int NX, int NF, int MODE, int NLM>
-__global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a) {
+__global__ void __launch_bounds__((XThreads<T, NX, NF>::value)) xpass_kernel(XArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
   xpass_body<T, NX, NF, MODE, NLM>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap),
                                    reinterpret_cast<C<T>*>(ss_dyn_lds));
@@ -408,8 +423,8 @@ __global__ void __launch_bounds__((XThreads<T, NF>::value)) xpass_kernel(XArgs a
 
 // Register prefetch of one x-pass tile for the persistent kernel: the
 // element order and thread mapping of xstage_in (fast path, nthr >= R),
-// exactly 8 elements per thread and field.
-template <typename T, int H, int PER>
+// exactly P elements per thread and field (PER = P * fields).
+template <typename T, int H, int P, int PER>
 __device__ __forceinline__ void xpass_prefetch(T (&pre_re)[PER], T (&pre_im)[PER], const C<T>* in0,
                                                const C<T>* in1, int tid, int nthr, int R, int lb,
                                                int64_t s0) {
@@ -419,8 +434,8 @@ __device__ __forceinline__ void xpass_prefetch(T (&pre_re)[PER], T (&pre_im)[PER
   const int k0 = tid >> lr;
   static_for<0, PER>([&](auto qc) __attribute__((always_inline)) {
     constexpr int q = decltype(qc)::value;
-    const C<T>* src = (q < 8 ? in0 : in1) + row;
-    const C<T> v = src[(int64_t)(k0 + (q & 7) * kstep) << lb];
+    const C<T>* src = (q < P ? in0 : in1) + row;
+    const C<T> v = src[(int64_t)(k0 + (q % P) * kstep) << lb];
     pre_re[q] = v.x;
     pre_im[q] = v.y;
   });
@@ -430,13 +445,13 @@ __device__ __forceinline__ void xpass_prefetch(T (&pre_re)[PER], T (&pre_im)[PER
 // loads the next tile's spectral rows into registers while it transforms
 // the current one, so the loads of one tile overlap the transforms of the
 // previous.  Requires blockDim = (R/2)*S (every pair in flight at once):
-// then each thread stages exactly 8 elements per field.
+// then each thread stages exactly P elements per field.
 template <typename T, int NX, int NF, int NLM>
 __global__ void __launch_bounds__(512) xpass_pp_kernel(XArgs a, int ntiles) {
-  typedef XCfg<T, NX> K;
-  constexpr int HB = K::HB;
+  typedef XCfg<T, NX, NF> K;
+  constexpr int HB = K::HB, P = K::P;
   constexpr int REG = K::reg_for(NF);
-  constexpr int PER = 8 * NF;
+  constexpr int PER = P * NF;
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
   C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
   const int R = a.rows_per_block;
@@ -453,17 +468,19 @@ __global__ void __launch_bounds__(512) xpass_pp_kernel(XArgs a, int ntiles) {
   const C<T>* in1 = (const C<T>*)a.spec_in[1];
   const int remap = a.xcd_remap;
   if (tile < ntiles)
-    xpass_prefetch<T, K::H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(tile, ntiles, remap) * R);
+    xpass_prefetch<T, K::H, P, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb,
+                                    xcd_block(tile, ntiles, remap) * R);
   for (; tile < ntiles; tile += gridDim.x) {
     __syncthreads();
     static_for<0, PER>([&](auto qc) __attribute__((always_inline)) {
       constexpr int q = decltype(qc)::value;
-      lrow[(q >> 3) * REG + k0 + (q & 7) * kstep] = mk<T>(pre_re[q], pre_im[q]);
+      lrow[(q / P) * REG + k0 + (q % P) * kstep] = mk<T>(pre_re[q], pre_im[q]);
     });
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < ntiles)
-      xpass_prefetch<T, K::H, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb, xcd_block(next, ntiles, remap) * R);
+      xpass_prefetch<T, K::H, P, PER>(pre_re, pre_im, in0, in1, tid, nthr, R, a.lb,
+                                      xcd_block(next, ntiles, remap) * R);
     xpass_body<T, NX, NF, XMODE_STEP, NLM, true>(a, xcd_block(tile, ntiles, a.xcd_remap), lds);
   }
 }
