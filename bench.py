@@ -61,13 +61,14 @@ def algorithmic_bytes(pass_name, w, esz):
 
     Every array is cells*esz bytes (half spectrum with the kx=0/Nyquist
     packing).  x pass: reads the state of each field, writes the
-    nonlinear term of each field.  k-space pass: reads state and nonlinear
-    term, writes the state (one launch covers every field).  y passes:
-    read and write one array of one field.
+    nonlinear term of each field.  k-space pass (stepping form): reads the
+    state's spectrum and the nonlinear term, writes the new spectrum and
+    the new state (one launch covers every field).  y passes: read and
+    write one array of one field.
     """
     n = w.cells * esz
     nf = len(w.fields)
-    return {"xpass": 2 * nf * n, "kpass": 3 * nf * n,
+    return {"xpass": 2 * nf * n, "kpass": 4 * nf * n,
             "ypass_inv": 2 * n, "ypass_fwd": 2 * n}[pass_name]
 
 

@@ -87,7 +87,11 @@ ss_status ss_create_grid(int ndim, const int64_t n[], const double dx[], ss_dtyp
  * Errors: SS_ERR_ARG (unknown model, ncoef, non-finite, dt <= 0). */
 ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef, double dt);
 
-/* Bytes of device workspace the grid needs (after ss_set_model). */
+/* Bytes of device workspace the grid needs (after ss_set_model):
+ * (3 nfields + 1) arrays of nx*ny*nz reals -- per field the partly
+ * transformed state, its full spectrum (carried between steps so that a
+ * step transforms the state only once, inversely) and the transformed
+ * nonlinear term, plus one staging array. */
 ss_status ss_workspace_size(ss_grid g, size_t* bytes);
 
 /* Bind caller-owned device memory of at least ss_workspace_size bytes,
@@ -174,7 +178,10 @@ ss_status ss_set_tiles(ss_grid g, const int tiles[6]);
 ss_status ss_adjoint_workspace_size(ss_grid g, int64_t nsteps, int K, size_t* bytes);
 ss_status ss_bind_adjoint_workspace(ss_grid g, void* device_ptr, size_t bytes, int64_t nsteps, int K);
 
-/* Advance nsteps (as ss_step_n) storing checkpoints every K steps. */
+/* Advance nsteps (the scheme of ss_step_n, in the form that re-forms the
+ * state's spectrum from the stored state every step, as the backward
+ * sweep's recomputation does; the results agree with ss_step_n to
+ * rounding) storing checkpoints every K steps. */
 ss_status ss_step_n_checkpointed(ss_grid g);
 
 /* Backward sweep.  dJ_dqT[f]: device (ny, nx) arrays of dJ/dq_f at the

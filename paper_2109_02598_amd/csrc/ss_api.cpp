@@ -74,6 +74,8 @@ struct ss_grid_s {
   void* state[2] = {nullptr, nullptr};
   void* scratch[2] = {nullptr, nullptr};
   void* staging = nullptr;
+  void* shat[2] = {nullptr, nullptr};   // full spectrum of each field (stepping form)
+  bool shat_valid = false;              // shat matches state
   bool field_set[2] = {false, false};
 
   double* mass_log = nullptr;
@@ -195,6 +197,8 @@ void carve_workspace(ss_grid g) {
     g->scratch[f] = f < g->nf ? b + (size_t)(g->nf + f) * fb : nullptr;
   }
   g->staging = b + (size_t)(2 * g->nf) * fb;
+  for (int f = 0; f < 2; ++f) g->shat[f] = f < g->nf ? b + (size_t)(2 * g->nf + 1 + f) * fb : nullptr;
+  g->shat_valid = false;
 }
 
 // Optional per-launch timing: a pair of events is recorded around each
@@ -326,8 +330,11 @@ ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double sca
                    "y pass launch");
 }
 
+// k-space pass of a step.  mode 1 (stepping form): S^ and G in, S^ and T
+// out; mode 0: T and G in, T out (three transforms); mode 2: refresh S^
+// from T.
 template <typename T>
-ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr) {
+ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr, int mode = 1) {
   ss::KArgs a;
   memset(&a, 0, sizeof(a));
   const bool three = g->ndim == 3;
@@ -335,6 +342,7 @@ ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr) {
     a.fld[f] = g->kf[f];
     a.fld[f].state = g->state[f];
     a.fld[f].nonlin = g->scratch[f];
+    a.fld[f].shat = g->shat[f];
   }
   a.J = three ? (int)g->n[1] : 1;
   a.nlines = (int)(g->n[0] / 2) * a.J;
@@ -345,9 +353,9 @@ ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr) {
   a.sz = three ? two_pi / ((double)g->n[2] * g->dx[2]) : 0.0;
   a.dt = g->dt;
   const int64_t nlast = three ? g->n[2] : g->n[1];
-  a.a_scale = 1.0 / (double)nlast;
+  a.a_scale = mode == 1 ? 1.0 : 1.0 / (double)nlast;
   a.b_scale = 1.0 / (double)g->cells();
-  a.mass_log = g->mass_log;
+  a.mass_log = mode == 2 ? nullptr : g->mass_log;
   a.log_index = g->log_count;
   a.log_capacity = g->log_cap;
   a.nf = g->nf;
@@ -356,11 +364,26 @@ ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr) {
   a.lines_per_block = g->tile_k;
   a.lb = g->lb;
   const int nl = (int)nlast;
-  return hip_check(ss::run_kpass<T>(nl, a, g->stream, take_events(pt, PASS_K)), "k-space pass launch");
+  return hip_check(ss::run_kpass<T>(nl, a, mode, g->stream, mode == 2 ? ss::LaunchEvents() : take_events(pt, PASS_K)),
+                   "k-space pass launch");
 }
 
+// Bring S^ up to date with the state (after the fields changed outside a
+// stepping-form step).
 template <typename T>
-ss_status step_once(ss_grid g, PassTimer* pt) {
+ss_status ensure_shat(ss_grid g) {
+  if (g->shat_valid) return SS_OK;
+  SS_TRY(launch_kpass<T>(g, nullptr, 2));
+  g->shat_valid = true;
+  return SS_OK;
+}
+
+// One step.  hat: the stepping form (S^ carried between steps; the caller
+// has made it valid); otherwise the three-transform form, which leaves S^
+// stale (the adjoint's checkpointed forward and its recomputation use it,
+// so both follow the same arithmetic).
+template <typename T>
+ss_status step_once(ss_grid g, PassTimer* pt, bool hat = true) {
   if (g->ndim == 2) {
     SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], g->scratch[0],
                            g->scratch[1], nullptr, nullptr, 1.0, pt));
@@ -370,7 +393,8 @@ ss_status step_once(ss_grid g, PassTimer* pt) {
                            g->scratch[1], nullptr, nullptr, 1.0, pt));
     for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, -1, g->scratch[f], g->scratch[f], 1.0, pt));
   }
-  SS_TRY(launch_kpass<T>(g, pt));
+  SS_TRY(launch_kpass<T>(g, pt, hat ? 1 : 0));
+  if (!hat) g->shat_valid = false;
   g->log_count++;
   return SS_OK;
 }
@@ -554,9 +578,12 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
       auto launch = [&](ss::LaunchEvents ev) {
         ss::KArgs a;
         memset(&a, 0, sizeof(a));
+        // stepping form on the scratch (as S^) and staging (G in, T out,
+        // per thread in place) arrays: the fields are untouched
         for (int f = 0; f < g->nf; ++f) {
           a.fld[f] = g->kf[f];
-          a.fld[f].state = g->scratch[f];
+          a.fld[f].shat = g->scratch[f];
+          a.fld[f].state = g->staging;
           a.fld[f].nonlin = g->staging;
         }
         a.J = g->ndim == 3 ? (int)g->n[1] : 1;
@@ -564,13 +591,13 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
         a.nx = nx;
         a.sx = a.sy = a.sz = 0.1;
         a.dt = g->dt;
-        a.a_scale = 1.0 / nl;
+        a.a_scale = 1.0;
         a.b_scale = 1.0 / (double)g->cells();
         a.nf = g->nf;
         a.three_d = g->ndim == 3;
         a.lines_per_block = l;
         a.lb = g->lb;
-        return hip_check(ss::run_kpass<T>(nl, a, g->stream, ev), "autotune k");
+        return hip_check(ss::run_kpass<T>(nl, a, 1, g->stream, ev), "autotune k");
       };
       float ms;
       SS_TRY(time_launch(g, launch, reps, &ms));
@@ -735,6 +762,7 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     m.k.fld[0] = g->kf[0];
     m.k.fld[0].state = g->state[0];
     m.k.fld[0].nonlin = g->scratch[0];
+    m.k.fld[0].shat = g->shat[0];
     m.k.nlines = nx / 2;
     m.k.J = 1;
     m.k.lines_per_block = L;
@@ -743,7 +771,7 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     m.k.sx = two_pi / ((double)nx * g->dx[0]);
     m.k.sy = two_pi / ((double)ny * g->dx[1]);
     m.k.dt = g->dt;
-    m.k.a_scale = 1.0 / (double)ny;
+    m.k.a_scale = 1.0;   // stepping form
     m.k.b_scale = 1.0 / (double)g->cells();
     m.k.nf = 1;
     m.k.lb = g->lb;
@@ -759,8 +787,10 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     if (lx > lds_x) lds_x = lx;
     if (lk > lds_k) lds_k = lk;
     tab.push_back(m);
-    // tuning copy: the k pass runs on the scratch and staging arrays
-    m.k.fld[0].state = g->scratch[0];
+    // tuning copy: the k pass runs on the scratch (as S^) and staging (G in,
+    // T out) arrays
+    m.k.fld[0].shat = g->scratch[0];
+    m.k.fld[0].state = g->staging;
     m.k.fld[0].nonlin = g->staging;
     tune.push_back(m);
   }
@@ -793,6 +823,19 @@ ss_status batch_check_members(ss_batch b) {
     if (!g->ws || !g->field_set[0]) return fail(SS_ERR_STATE, "batch member %zu: workspace or field not set", i);
     if (b->uploaded && b->state_at_build[i] != g->state[0])
       return fail(SS_ERR_STATE, "batch member %zu: workspace was rebound after the batch table was built", i);
+  }
+  return SS_OK;
+}
+
+// Bring every member's S^ up to date, on the batch's stream.
+ss_status batch_refresh(ss_batch b) {
+  for (ss_grid g : b->grids) {
+    if (g->shat_valid) continue;
+    hipStream_t own = g->stream;
+    g->stream = b->stream;
+    ss_status st = g->dtype == SS_F64 ? ensure_shat<double>(g) : ensure_shat<float>(g);
+    g->stream = own;
+    SS_TRY(st);
   }
   return SS_OK;
 }
@@ -874,7 +917,7 @@ ss_status kpass_to(ss_grid g, const void* st0, const void* st1, const void* g0, 
   ensure_tiles(g);
   a.lines_per_block = g->tile_k;
   a.lb = g->lb;
-  return hip_check(ss::run_kpass<T>((int)g->n[1], a, g->stream, ss::LaunchEvents()), "k-space pass launch");
+  return hip_check(ss::run_kpass<T>((int)g->n[1], a, 0, g->stream, ss::LaunchEvents()), "k-space pass launch");
 }
 
 template <typename T>
@@ -1028,7 +1071,8 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     memset(&a, 0, sizeof(a));
     for (int f = 0; f < g->nf; ++f) {
       a.fld[f] = g->kf[f];
-      a.fld[f].state = g->scratch[f];
+      a.fld[f].shat = g->scratch[f];
+      a.fld[f].state = g->staging;
       a.fld[f].nonlin = g->staging;
     }
     a.J = g->ndim == 3 ? (int)g->n[1] : 1;
@@ -1039,13 +1083,13 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     a.sy = two_pi / ((double)g->n[1] * g->dx[1]);
     a.sz = g->ndim == 3 ? two_pi / ((double)g->n[2] * g->dx[2]) : 0.0;
     a.dt = g->dt;
-    a.a_scale = 1.0 / nl;
+    a.a_scale = 1.0;
     a.b_scale = 1.0 / (double)g->cells();
     a.nf = g->nf;
     a.three_d = g->ndim == 3;
     a.lines_per_block = g->tile_k;
     a.lb = g->lb;
-    return hip_check(ss::run_kpass<T>(nl, a, g->stream, ev), "timed k pass");
+    return hip_check(ss::run_kpass<T>(nl, a, 1, g->stream, ev), "timed k pass");
   }
   if (g->ndim == 3 && (pass == PASS_YINV || pass == PASS_YFWD)) {
     ss::YArgs a;
@@ -1130,7 +1174,7 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
 ss_status ss_workspace_size(ss_grid g, size_t* bytes) {
   if (!g || !bytes) return fail(SS_ERR_ARG, "ss_workspace_size: null argument");
   if (!g->has_model) return fail(SS_ERR_STATE, "ss_workspace_size: call ss_set_model first");
-  *bytes = align_up(g->field_bytes()) * (size_t)(2 * g->nf + 1);
+  *bytes = align_up(g->field_bytes()) * (size_t)(3 * g->nf + 1);
   return SS_OK;
 }
 
@@ -1169,6 +1213,7 @@ ss_status ss_set_field(ss_grid g, int field, const void* src, int src_on_device)
     if (st != SS_OK) return st;
   }
   g->field_set[field] = true;
+  g->shat_valid = false;
   return SS_OK;
 }
 
@@ -1197,6 +1242,7 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps) {
   if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_step_n: model and workspace must be set first");
   for (int f = 0; f < g->nf; ++f)
     if (!g->field_set[f]) return fail(SS_ERR_STATE, "ss_step_n: field %d was never set", f);
+  if (nsteps > 0) SS_TRY(g->dtype == SS_F64 ? ensure_shat<double>(g) : ensure_shat<float>(g));
   for (int64_t i = 0; i < nsteps; ++i) {
     ss_status st = g->dtype == SS_F64 ? step_once<double>(g, nullptr) : step_once<float>(g, nullptr);
     if (st != SS_OK) return st;
@@ -1244,6 +1290,7 @@ ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t
     st = hip_check(hipEventCreate(&pt->ev[created]), "hipEventCreate");
     if (st != SS_OK) break;
   }
+  if (st == SS_OK && nsteps > 0) st = g->dtype == SS_F64 ? ensure_shat<double>(g) : ensure_shat<float>(g);
   for (int64_t i = 0; st == SS_OK && i < nsteps; ++i)
     st = g->dtype == SS_F64 ? step_once<double>(g, pt) : step_once<float>(g, pt);
   if (st == SS_OK) st = hip_check(hipStreamSynchronize(g->stream), "ss_step_n_profiled: synchronise");
@@ -1454,6 +1501,7 @@ ss_status ss_batch_step_n(ss_batch b, int64_t nsteps) {
   if (!b->ws) return fail(SS_ERR_STATE, "ss_batch_step_n: bind the batch workspace first");
   SS_TRY(batch_check_members(b));
   if (!b->uploaded) SS_TRY(batch_upload(b, b->threads));
+  if (nsteps > 0) SS_TRY(batch_refresh(b));
   for (int64_t i = 0; i < nsteps; ++i) SS_TRY(batch_step_once(b));
   for (ss_grid g : b->grids) g->log_count += nsteps;
   return SS_OK;
@@ -1474,6 +1522,7 @@ ss_status ss_batch_capture(ss_batch b, int64_t nsteps) {
     hipGraphDestroy(b->graph);
     b->graph = nullptr;
   }
+  SS_TRY(batch_refresh(b));   // outside the capture
   SS_TRY(hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"));
   ss_status st = SS_OK;
   for (int64_t i = 0; st == SS_OK && i < nsteps; ++i) st = batch_step_once(b);
@@ -1494,6 +1543,7 @@ ss_status ss_batch_launch(ss_batch b) {
   if (!b) return fail(SS_ERR_ARG, "ss_batch_launch: null batch");
   if (!b->exec) return fail(SS_ERR_STATE, "ss_batch_launch: nothing captured");
   SS_TRY(batch_check_members(b));
+  SS_TRY(batch_refresh(b));
   SS_TRY(hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch"));
   for (ss_grid g : b->grids) g->log_count += b->graph_steps;
   return SS_OK;
@@ -1551,7 +1601,7 @@ ss_status ss_step_n_checkpointed(ss_grid g) {
       for (int f = 0; f < 2; ++f)
         SS_TRY(hip_check(hipMemcpyAsync(ck_field(g, L, i / g->adj_K, f), g->state[f], g->field_bytes(),
                                         hipMemcpyDeviceToDevice, g->stream), "checkpoint copy"));
-    SS_TRY(g->dtype == SS_F64 ? step_once<double>(g, nullptr) : step_once<float>(g, nullptr));
+    SS_TRY(g->dtype == SS_F64 ? step_once<double>(g, nullptr, false) : step_once<float>(g, nullptr, false));
   }
   for (int i = 0; i < g->ncoef; ++i) g->adj_coef[i] = g->coef[i];
   g->adj_dt = g->dt;

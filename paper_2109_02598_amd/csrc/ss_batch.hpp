@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SS_KWA
     switch (b.m[i].ny) {
 #define SS_CASE(n)                  \
   case n:                           \
-    kpass_body<T, n>(a, bx, 0, lds); \
+    kpass_body<T, n, true>(a, bx, 0, lds); \
     break;
       SS_BATCH_SIZES(SS_CASE)
 #undef SS_CASE

@@ -136,7 +136,7 @@ hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s, 
 template <typename T>
 hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s, LaunchEvents ev);
 template <typename T>
-hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev);
+hipError_t run_kpass(int nl, KArgs a, int mode, hipStream_t s, LaunchEvents ev);
 template <typename T>
 hipError_t run_sfpass(int nl, SFArgs a, hipStream_t s);
 template <typename T>
@@ -220,21 +220,25 @@ hipError_t run_ypass(int ny, int dir, YArgs a, int64_t nkx, hipStream_t s, Launc
   return hipErrorInvalidValue;
 }
 
+// mode: 0 = three transforms (T in, T out), 1 = stepping form (S^ and G in,
+// S^ and T out), 2 = refresh S^ = FFT(T)/N_last only
 template <typename T, int NL>
-hipError_t launch_k(KArgs a, hipStream_t s, LaunchEvents ev) {
+hipError_t launch_k(KArgs a, int mode, hipStream_t s, LaunchEvents ev) {
   constexpr int ESZ = (int)sizeof(C<T>);
   const int L = a.lines_per_block;
   if (!k_tile_ok(ESZ, NL, a.nlines, a.three_d != 0, L)) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(a.nlines / L), (unsigned)a.nf), block((unsigned)(L * (NL / 8)));
-  return launch_with(kpass_kernel<T, NL>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  if (mode == 2) return launch_with(kfwd_kernel<T, NL>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  if (mode == 1) return launch_with(kpass_kernel<T, NL, true>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  return launch_with(kpass_kernel<T, NL, false>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
 }
 
 template <typename T>
-hipError_t run_kpass(int nl, KArgs a, hipStream_t s, LaunchEvents ev) {
+hipError_t run_kpass(int nl, KArgs a, int mode, hipStream_t s, LaunchEvents ev) {
   switch (nl) {
 #define SS_CASE(n) \
   case n:          \
-    return launch_k<T, n>(a, s, ev);
+    return launch_k<T, n>(a, mode, s, ev);
     SS_POW2_CASES(SS_CASE)
 #undef SS_CASE
   }
@@ -327,7 +331,7 @@ hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
   template hipError_t run_batch_k<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t, LaunchEvents); \
   template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t, LaunchEvents);  \
-  template hipError_t run_kpass<T>(int, KArgs, hipStream_t, LaunchEvents);                \
+  template hipError_t run_kpass<T>(int, KArgs, int, hipStream_t, LaunchEvents);           \
   template hipError_t run_sfpass<T>(int, SFArgs, hipStream_t);                            \
   template hipError_t run_sfreduce<T>(SFArgs, hipStream_t);
 

@@ -582,6 +582,7 @@ struct KField {
   void* state;              // T (read; written too unless `out` is set)
   const void* nonlin;       // G
   void* out;                // where the new T goes (null: in place)
+  void* shat;               // stepping form: the state's full spectrum S^, read and rewritten
   double l[4];              // L(k^2) = l0 + l1 k^2 + l2 k^4 + l3 k^6
   double n[2];              // N(k^2) = n0 + n1 k^2
 };
@@ -709,7 +710,13 @@ struct KCfg {
 };
 
 // One k-space tile: lines bx*L .. bx*L+L-1 of field `fi`.
-template <typename T, int NL>
+// HAT = false: the state's spectrum is formed here (forward FFT of T, three
+// transforms per line).  HAT = true (stepping form): the full spectrum S^ of
+// the state is carried between steps (S^ = FFT(T)/N_last), so only the
+// nonlinear term is transformed; U = A S^ + B N G^ is written back as the
+// new S^ and, inverse transformed, as the new T (two transforms per line;
+// the host passes a_scale = 1).
+template <typename T, int NL, bool HAT = false>
 __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>* lds) {
   typedef KCfg<T, NL> K;
   constexpr int S = K::S, REG = K::REG;
@@ -728,7 +735,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   int64_t lbase = sidx(kxi, (int64_t)kyi * NL, hx, lb);
   if constexpr (S >= 64) lbase = wave_uniform(lbase);
   const uint32_t tb = (uint32_t)(kline_off(t, hx, lb) * (int64_t)sizeof(C<T>));
-  const C<T>* st = (const C<T>*)F.state + lbase;
+  const C<T>* st = (const C<T>*)(HAT ? F.shat : F.state) + lbase;
   const C<T>* gn = (const C<T>*)F.nonlin + lbase;
   C<T>* so = (C<T>*)(F.out ? F.out : F.state) + lbase;
 
@@ -748,7 +755,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
 #pragma unroll
     for (int i = 0; i < Twiddles<T, NL>::NW; ++i) twl[i * twstride] = tw.w[i];
   }
-  fft_lines<T, NL, -1, 1>(ct, x, t, ktw<T, NL>(tw, twl, twstride));
+  if constexpr (!HAT) fft_lines<T, NL, -1, 1>(ct, x, t, ktw<T, NL>(tw, twl, twstride));
 #pragma unroll
   for (int e = 0; e < 8; ++e) cg[0][e] = *kline_at(gn, kline_off(e * S, hx, lb), tb);
   fft_lines<T, NL, -1, 1>(cg, x, t, ktw<T, NL>(tw, twl, twstride));
@@ -834,16 +841,50 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     }
   }
 
+  if constexpr (HAT) {
+    C<T>* sh = (C<T>*)F.shat + lbase;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) *kline_at(sh, kline_off(e * S, hx, lb), tb) = ct[0][e];
+  }
   fft_lines<T, NL, +1, 1>(ct, x, t, ktw<T, NL>(tw, twl, twstride));
 #pragma unroll
   for (int e = 0; e < 8; ++e) *kline_at(so, kline_off(e * S, hx, lb), tb) = ct[0][e];
 }
 
-template <typename T, int NL>
+template <typename T, int NL, bool HAT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : SS_KWAVES)))
 kpass_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
-  kpass_body<T, NL>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
+  kpass_body<T, NL, HAT>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
+}
+
+// S^ = FFT(T) / N_last along every line of field blockIdx.y (the stepping
+// form's spectrum, refreshed after the fields change outside a step).
+template <typename T, int NL>
+__global__ void __launch_bounds__(512) kfwd_kernel(KArgs a) {
+  typedef KCfg<T, NL> K;
+  constexpr int S = K::S, REG = K::REG;
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
+  const int tid = threadIdx.x;
+  const int ls = tid / S, t = tid - ls * S;
+  const KField& F = blockIdx.y == 0 ? a.fld[0] : a.fld[1];
+  int kxi, kyi;
+  kline_slot(blockIdx.x * a.lines_per_block + ls, a.J, a.three_d, kxi, kyi);
+  const int64_t hx = a.nx / 2;
+  const int lb = a.lb;
+  const int64_t lbase = sidx(kxi, (int64_t)kyi * NL, hx, lb);
+  const uint32_t tb = (uint32_t)(kline_off(t, hx, lb) * (int64_t)sizeof(C<T>));
+  const C<T>* st = (const C<T>*)F.state + lbase;
+  C<T>* sh = (C<T>*)F.shat + lbase;
+  C<T> c[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) c[0][e] = *kline_at(st, kline_off(e * S, hx, lb), tb);
+  C<T>* x[1] = {lds + ls * REG};
+  fft_lines<T, NL, -1, 1>(c, x, t, make_twiddles<T, NL>(t));
+  const T sc = (T)1 / (T)NL;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) *kline_at(sh, kline_off(e * S, hx, lb), tb) = cscale<T>(c[0][e], sc);
 }
 
 // ---------------------------------------------------------------------------
