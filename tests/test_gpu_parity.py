@@ -14,8 +14,11 @@ from tests._common import (COEF, TOL, as_input, oracle_run, rel_l2, run_gpu, say
 
 pytestmark = pytest.mark.gpu
 
+# every transform plan: x lengths 8 .. 4096 (16 points per thread: first
+# stage of radix 2, 4, 8 or 16 and one to three radix-16 stages; 8 points for
+# 8-point rows) and line lengths 8 .. 4096 (8 points per thread)
 SHAPES_2D = [(8, 8), (16, 64), (64, 16), (256, 32), (128, 128), (32, 512), (2048, 16),
-             (4096, 8), (8, 1024)]
+             (4096, 8), (8, 1024), (512, 8), (1024, 16), (16, 4096), (16, 2048)]
 SHAPES_3D = [(8, 8, 8), (16, 32, 8), (32, 16, 64), (64, 8, 32)]
 DX = {"pfc": math.pi / 4}
 
