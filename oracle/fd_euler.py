@@ -3,11 +3,16 @@
 TEST INFRASTRUCTURE ONLY.
 
 Sec. 2.4.1 provides forward Euler as the base explicit method; Sec. 2.2.2
-names the second-order central stencils (the 5-point Laplacian in 2D, the
-7-point one in 3D).  Higher powers of the Laplacian are built here by
-composing that stencil, and periodic boundaries wrap the grid.  This is a
-discretisation independent of the spectral scheme (real space, no
-transforms, no exponentials), so the two agree only if the operator
+lists the second-order central Laplacian stencils: 5 and 9 points in 2D,
+7 and 19 (among others) in 3D.  The 5/7-point stencils are the axis-wise
+central differences; the 9- and 19-point ones are the standard
+second-order isotropic stencils (their leading error term depends on |k|
+only), weights over 6 h^2: 2D 4 per edge neighbour, 1 per corner, -20 in
+the centre; 3D 2 per face neighbour, 1 per edge neighbour, -24 in the
+centre (equal spacing on every axis).  Higher powers of the Laplacian are
+built by composing the stencil, and periodic boundaries wrap the grid.
+This is a discretisation independent of the spectral scheme (real space,
+no transforms, no exponentials), so the two agree only if the operator
 split, the signs and the coefficients of the spectral side are right.
 """
 from __future__ import annotations
@@ -15,22 +20,44 @@ from __future__ import annotations
 import numpy as np
 
 
-def laplacian(f, dx):
+def laplacian(f, dx, stencil=0):
     """Second-order central Laplacian with periodic wrap.
 
-    ``f`` is shaped (..., y, x); ``dx`` is (dx, dy[, dz]).  In 2D this is
-    the 5-point stencil, in 3D the 7-point stencil.
+    ``f`` is shaped ([z,] y, x); ``dx`` is (dx, dy[, dz]).  stencil 0, 5
+    or 7: the axis-wise stencil (5 points in 2D, 7 in 3D); 9 (2D) or 19
+    (3D): the isotropic stencil, which needs equal spacings.
     """
-    out = np.zeros_like(f)
-    dxs = tuple(reversed(tuple(dx)))
-    for ax, h in enumerate(dxs):
-        out += (np.roll(f, 1, axis=ax) - 2.0 * f + np.roll(f, -1, axis=ax)) / (h * h)
-    return out
+    f = np.asarray(f, dtype=np.float64)
+    d = f.ndim
+    if stencil in (0, 5, 7):
+        assert stencil in (0, 5 if d == 2 else 7)
+        out = np.zeros_like(f)
+        dxs = tuple(reversed(tuple(dx)))
+        for ax, h in enumerate(dxs):
+            out += (np.roll(f, 1, axis=ax) - 2.0 * f + np.roll(f, -1, axis=ax)) / (h * h)
+        return out
+    h = float(dx[0])
+    assert all(abs(float(v) - h) <= 1e-12 * h for v in dx), "isotropic stencils need equal spacing"
+    if stencil == 9:
+        assert d == 2
+        edge = sum(np.roll(f, s, axis=a) for a in (0, 1) for s in (1, -1))
+        corner = sum(np.roll(np.roll(f, sy, axis=0), sx, axis=1) for sy in (1, -1) for sx in (1, -1))
+        return (4.0 * edge + corner - 20.0 * f) / (6.0 * h * h)
+    if stencil == 19:
+        assert d == 3
+        face = sum(np.roll(f, s, axis=a) for a in (0, 1, 2) for s in (1, -1))
+        edge = 0.0
+        for a, b in ((0, 1), (0, 2), (1, 2)):
+            for sa in (1, -1):
+                for sb in (1, -1):
+                    edge = edge + np.roll(np.roll(f, sa, axis=a), sb, axis=b)
+        return (2.0 * face + edge - 24.0 * f) / (6.0 * h * h)
+    raise ValueError("unknown stencil %r" % (stencil,))
 
 
-def rhs(model, coef, q, dx):
+def rhs(model, coef, q, dx, stencil=0):
     """Right-hand sides of the equations of motion in real space."""
-    lap = lambda f: laplacian(f, dx)
+    lap = lambda f: laplacian(f, dx, stencil)
     c = [float(v) for v in coef]
     if model == "allen_cahn":
         M, kap, c1, c2 = c
@@ -61,10 +88,10 @@ def rhs(model, coef, q, dx):
     raise ValueError("unknown model %r" % (model,))
 
 
-def euler_n(fields, model, coef, dt, dx, nsteps):
+def euler_n(fields, model, coef, dt, dx, nsteps, stencil=0):
     """``nsteps`` forward-Euler steps q <- q + dt * rhs(q)."""
     q = [np.array(f, dtype=np.float64, copy=True) for f in fields]
     for _ in range(int(nsteps)):
-        r = rhs(model, coef, q, dx)
+        r = rhs(model, coef, q, dx, stencil)
         q = [a + dt * b for a, b in zip(q, r)]
     return q
