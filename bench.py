@@ -212,6 +212,39 @@ def run_adjoint(steps=200, K=20, dtype="f32"):
             "dJ_dcoef": [float(x) for x in dc]}
 
 
+def run_euler(w, dtype, steps=500):
+    """The forward-Euler finite-difference solver on the same grid and
+    fields (axis-wise and isotropic Laplacian).  A Cahn-Hilliard step is two
+    launches: mu from psi (one array read, one written), then psi + dt M L mu
+    (two read, one written): 5 arrays of algorithmic traffic per step."""
+    import torch
+    from paper_2109_02598_amd import specstep
+    out = {"workload": "%s, forward Euler, %s, %d steps (dt 0.01)" % (w.name, dtype, steps)}
+    esz = 8 if dtype == "f64" else 4
+    nfa = {"allen_cahn": 2, "cahn_hilliard": 5, "pfc": 8, "gray_scott": 4, "model_c": 6}[w.model]
+    for st in ((0, 9) if len(w.n) == 2 else (0, 19)):
+        g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=0.01,
+                          solver="euler", stencil=st)
+        for i, f in enumerate(w.fields):
+            g.set_field(i, torch.from_numpy(f).to("cuda:0"))
+        g.step(20)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        g.close()
+        name = "axis-wise" if st == 0 else "isotropic %d-point" % st
+        out[name] = {"value": round(w.cells * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
+                     "us_per_step": round(ms * 1e3 / steps, 2),
+                     "achieved_GBs": round(nfa * w.cells * esz * steps / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def roofline(w, dtype, prof, traffic_rec):
     esz = 8 if dtype == "f64" else 4
     tiles = prof.pop("tiles", None)
@@ -320,6 +353,8 @@ def main():
     if not args.no_adjoint:
         print("bench: adjoint workload", file=sys.stderr, flush=True)
         adj = run_adjoint()
+    print("bench: forward-Euler finite differences", file=sys.stderr, flush=True)
+    euler = run_euler(w, args.dtype)
     batch = None
     if not args.no_batch:
         print("bench: batched 64-grid workload", file=sys.stderr, flush=True)
@@ -347,6 +382,7 @@ def main():
             "what": "radially averaged S(k) of [psi > 0] of the evolved field, one call",
             args.dtype: sf1, other: sf2},
         "batched": batch,
+        "euler_fd": euler,
         "adjoint": adj,
         "wall_s_timed_region": round(wall, 4),
     }

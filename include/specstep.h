@@ -87,8 +87,29 @@ ss_status ss_create_grid(int ndim, const int64_t n[], const double dx[], ss_dtyp
  * Errors: SS_ERR_ARG (unknown model, ncoef, non-finite, dt <= 0). */
 ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef, double dt);
 
+/* ---- Solver choice ---------------------------------------------------------
+ * solver 0 (default): the semi-implicit spectral scheme (Sec. 2.4.2).
+ * solver 1: explicit forward Euler with finite differences (Sec. 2.4.1):
+ *   q <- q + dt * rhs(q) on the real-space fields, the right-hand sides of
+ *   the models above with the Laplacian replaced by a second-order stencil
+ *   (Sec. 2.2.2; periodic wrap; higher powers by composition):
+ *   stencil 0 (or 5 in 2D, 7 in 3D): axis-wise central differences,
+ *   sum_a (f[-1] - 2 f + f[+1]) / dx_a^2;  stencil 9 (2D) or 19 (3D): the
+ *   isotropic stencils (4 edge + 1 corner - 20 centre) / (6 h^2) and
+ *   (2 face + 1 edge - 24 centre) / (6 h^2), which need equal spacings.
+ *   Explicit: stable only for dt below the stencil's limit (the caller's
+ *   choice).  The fields live in real space; ss_set_field / ss_get_field /
+ *   ss_step_n work as with the spectral solver; the mass log is not
+ *   written; ss_step_n_profiled, ss_time_pass, ss_autotune,
+ *   ss_structure_factor, the adjoint and batches are SS_ERR_UNSUPPORTED.
+ * Changing the solver drops the bound workspace and fields (its size
+ * differs: (2 nfields + 3) arrays for solver 1).
+ * Errors: SS_ERR_ARG (unknown solver or stencil for the dimension),
+ * SS_ERR_UNSUPPORTED (isotropic stencil with unequal spacings). */
+ss_status ss_set_solver(ss_grid g, int solver, int stencil);
+
 /* Bytes of device workspace the grid needs (after ss_set_model):
- * (3 nfields + 1) arrays of nx*ny*nz reals -- per field the partly
+ * for the spectral solver (3 nfields + 1) arrays of nx*ny*nz reals -- per field the partly
  * transformed state, its full spectrum (carried between steps so that a
  * step transforms the state only once, inversely) and the transformed
  * nonlinear term, plus one staging array. */

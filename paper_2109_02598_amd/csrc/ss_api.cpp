@@ -75,6 +75,12 @@ struct ss_grid_s {
   void* scratch[2] = {nullptr, nullptr};
   void* staging = nullptr;
   void* shat[2] = {nullptr, nullptr};   // full spectrum of each field (stepping form)
+  // forward-Euler finite-difference solver (solver 1): real-space fields in
+  // state[], the next step's in fd_next[], intermediates in fd_tmp[]
+  int solver = 0;
+  int stencil = 0;
+  void* fd_next[2] = {nullptr, nullptr};
+  void* fd_tmp[2] = {nullptr, nullptr};
   bool shat_valid = false;              // shat matches state
   bool field_set[2] = {false, false};
 
@@ -192,6 +198,20 @@ void build_operators(ss_grid g) {
 void carve_workspace(ss_grid g) {
   char* b = (char*)g->ws;
   const size_t fb = align_up(g->field_bytes());
+  if (g->solver == 1) {
+    // state (nf), next (nf), two intermediates, staging
+    for (int f = 0; f < 2; ++f) {
+      g->state[f] = f < g->nf ? b + (size_t)f * fb : nullptr;
+      g->fd_next[f] = f < g->nf ? b + (size_t)(g->nf + f) * fb : nullptr;
+      g->scratch[f] = nullptr;
+      g->shat[f] = nullptr;
+    }
+    g->fd_tmp[0] = b + (size_t)(2 * g->nf) * fb;
+    g->fd_tmp[1] = b + (size_t)(2 * g->nf + 1) * fb;
+    g->staging = b + (size_t)(2 * g->nf + 2) * fb;
+    g->shat_valid = false;
+    return;
+  }
   for (int f = 0; f < 2; ++f) {
     g->state[f] = f < g->nf ? b + (size_t)f * fb : nullptr;
     g->scratch[f] = f < g->nf ? b + (size_t)(g->nf + f) * fb : nullptr;
@@ -399,8 +419,69 @@ ss_status step_once(ss_grid g, PassTimer* pt, bool hat = true) {
   return SS_OK;
 }
 
+// ---- forward-Euler finite-difference step (Sec. 2.4.1, 2.2.2) -------------
+ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* out0, void* out1, double s0) {
+  ss::FDArgs a;
+  memset(&a, 0, sizeof(a));
+  a.in[0] = in0;
+  a.in[1] = in1;
+  a.out[0] = out0;
+  a.out[1] = out1;
+  a.nx = g->n[0];
+  a.ny = g->n[1];
+  a.nz = g->n[2];
+  a.lx = ilog2i(g->n[0]);
+  a.lxy = ilog2i(g->n[0] * g->n[1]);
+  for (int d = 0; d < 3; ++d) a.ih2[d] = d < g->ndim ? 1.0 / (g->dx[d] * g->dx[d]) : 0.0;
+  a.i6h2 = 1.0 / (6.0 * g->dx[0] * g->dx[0]);
+  a.dt = g->dt;
+  a.op = op;
+  if (op == ss::FD_UPD) {
+    a.p[0] = s0;
+  } else {
+    for (int i = 0; i < g->ncoef && i < 6; ++i) a.p[i] = g->coef[i];
+  }
+  const int st = (g->stencil == 9 || g->stencil == 19) ? g->stencil : 0;
+  hipError_t e = g->dtype == SS_F64 ? ss::run_fd<double>(g->ndim, st, a, g->stream)
+                                    : ss::run_fd<float>(g->ndim, st, a, g->stream);
+  return hip_check(e, "finite-difference launch");
+}
+
+ss_status fd_step_once(ss_grid g) {
+  void** S = g->state;
+  void** N = g->fd_next;
+  void** T = g->fd_tmp;
+  const double* c = g->coef;
+  switch (g->model) {
+    case SS_ALLEN_CAHN:
+      SS_TRY(fd_launch(g, ss::FD_AC, S[0], nullptr, N[0], nullptr, 0.0));
+      break;
+    case SS_GRAY_SCOTT:
+      SS_TRY(fd_launch(g, ss::FD_GS, S[0], S[1], N[0], N[1], 0.0));
+      break;
+    case SS_CAHN_HILLIARD:
+      SS_TRY(fd_launch(g, ss::FD_MU_CH, S[0], nullptr, T[0], nullptr, 0.0));
+      SS_TRY(fd_launch(g, ss::FD_UPD, S[0], T[0], N[0], nullptr, c[0]));
+      break;
+    case SS_PFC:
+      SS_TRY(fd_launch(g, ss::FD_LAP, S[0], nullptr, T[0], nullptr, 0.0));
+      SS_TRY(fd_launch(g, ss::FD_MU_PFC, S[0], T[0], T[1], nullptr, 0.0));
+      SS_TRY(fd_launch(g, ss::FD_UPD, S[0], T[1], N[0], nullptr, 1.0));
+      break;
+    default:  // model C
+      SS_TRY(fd_launch(g, ss::FD_MC, S[0], S[1], N[0], T[0], 0.0));
+      SS_TRY(fd_launch(g, ss::FD_UPD, S[1], T[0], N[1], nullptr, 1.0));
+      break;
+  }
+  for (int f = 0; f < g->nf; ++f) std::swap(g->state[f], g->fd_next[f]);
+  return SS_OK;
+}
+
 template <typename T>
 ss_status set_field_t(ss_grid g, int field, const void* dsrc) {
+  if (g->solver == 1)
+    return hip_check(hipMemcpyAsync(g->state[field], dsrc, g->field_bytes(), hipMemcpyDeviceToDevice, g->stream),
+                     "ss_set_field: copy");
   ss_status st = launch_xpass<T>(g, ss::XMODE_FWD, 1, nullptr, nullptr, g->state[field], nullptr,
                                  dsrc, nullptr, 1.0 / (double)g->n[0]);
   if (st != SS_OK) return st;
@@ -411,6 +492,9 @@ ss_status set_field_t(ss_grid g, int field, const void* dsrc) {
 
 template <typename T>
 ss_status get_field_t(ss_grid g, int field, void* ddst) {
+  if (g->solver == 1)
+    return hip_check(hipMemcpyAsync(ddst, g->state[field], g->field_bytes(), hipMemcpyDeviceToDevice, g->stream),
+                     "ss_get_field: copy");
   const void* spec = g->state[field];
   if (g->ndim == 3) {
     ss_status st = launch_ypass<T>(g, +1, g->state[field], g->scratch[field], 1.0);
@@ -1174,7 +1258,30 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
 ss_status ss_workspace_size(ss_grid g, size_t* bytes) {
   if (!g || !bytes) return fail(SS_ERR_ARG, "ss_workspace_size: null argument");
   if (!g->has_model) return fail(SS_ERR_STATE, "ss_workspace_size: call ss_set_model first");
-  *bytes = align_up(g->field_bytes()) * (size_t)(3 * g->nf + 1);
+  *bytes = align_up(g->field_bytes()) * (size_t)(g->solver == 1 ? 2 * g->nf + 3 : 3 * g->nf + 1);
+  return SS_OK;
+}
+
+ss_status ss_set_solver(ss_grid g, int solver, int stencil) {
+  if (!g) return fail(SS_ERR_ARG, "ss_set_solver: null grid");
+  if (solver != 0 && solver != 1) return fail(SS_ERR_ARG, "ss_set_solver: unknown solver %d", solver);
+  if (solver == 1) {
+    const bool ok = stencil == 0 || (g->ndim == 2 ? (stencil == 5 || stencil == 9) : (stencil == 7 || stencil == 19));
+    if (!ok) return fail(SS_ERR_ARG, "ss_set_solver: stencil %d is not available in %dD", stencil, g->ndim);
+    if (stencil == 9 || stencil == 19)
+      for (int d = 1; d < g->ndim; ++d)
+        if (std::fabs(g->dx[d] - g->dx[0]) > 1e-12 * g->dx[0])
+          return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the isotropic stencil needs equal spacings");
+  } else if (stencil != 0) {
+    return fail(SS_ERR_ARG, "ss_set_solver: the spectral solver takes no stencil");
+  }
+  if (solver != g->solver) {
+    g->ws = nullptr;
+    g->ws_bytes = 0;
+    g->field_set[0] = g->field_set[1] = false;
+  }
+  g->solver = solver;
+  g->stencil = stencil;
   return SS_OK;
 }
 
@@ -1242,6 +1349,10 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps) {
   if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_step_n: model and workspace must be set first");
   for (int f = 0; f < g->nf; ++f)
     if (!g->field_set[f]) return fail(SS_ERR_STATE, "ss_step_n: field %d was never set", f);
+  if (g->solver == 1) {
+    for (int64_t i = 0; i < nsteps; ++i) SS_TRY(fd_step_once(g));
+    return SS_OK;
+  }
   if (nsteps > 0) SS_TRY(g->dtype == SS_F64 ? ensure_shat<double>(g) : ensure_shat<float>(g));
   for (int64_t i = 0; i < nsteps; ++i) {
     ss_status st = g->dtype == SS_F64 ? step_once<double>(g, nullptr) : step_once<float>(g, nullptr);
@@ -1258,6 +1369,7 @@ ss_status ss_structure_factor_nbins(ss_grid g, int* nbins) {
 
 ss_status ss_structure_factor(ss_grid g, int field, double* s_out, int64_t* n_out, int nbins) {
   if (!g || !s_out || !n_out) return fail(SS_ERR_ARG, "ss_structure_factor: null argument");
+  if (g->solver == 1) return fail(SS_ERR_UNSUPPORTED, "ss_structure_factor: spectral solver only");
   if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_structure_factor: model and workspace must be set first");
   if (field < 0 || field >= g->nf) return fail(SS_ERR_ARG, "ss_structure_factor: field %d out of range", field);
   if (!g->field_set[field]) return fail(SS_ERR_STATE, "ss_structure_factor: field %d was never set", field);
@@ -1272,6 +1384,7 @@ ss_status ss_structure_factor(ss_grid g, int field, double* s_out, int64_t* n_ou
 ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t* pass_count,
                              int npass) {
   if (!g) return fail(SS_ERR_ARG, "ss_step_n_profiled: null grid");
+  if (g->solver == 1) return fail(SS_ERR_UNSUPPORTED, "ss_step_n_profiled: spectral solver only");
   if (!pass_ms || !pass_count || npass <= 0) return fail(SS_ERR_ARG, "ss_step_n_profiled: null outputs");
   if (nsteps < 0) return fail(SS_ERR_ARG, "ss_step_n_profiled: nsteps must be >= 0");
   if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_step_n_profiled: model and workspace must be set first");
@@ -1316,6 +1429,7 @@ ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t
 }
 
 ss_status ss_time_pass(ss_grid g, int pass, int nlaunch, double* mean_ms) {
+  if (g && g->solver == 1) return fail(SS_ERR_UNSUPPORTED, "ss_time_pass: spectral solver only");
   if (!g || !mean_ms) return fail(SS_ERR_ARG, "ss_time_pass: null argument");
   if (nlaunch < 1 || nlaunch > 100000) return fail(SS_ERR_ARG, "ss_time_pass: nlaunch must be in [1, 100000]");
   if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_time_pass: model and workspace must be set first");
@@ -1345,6 +1459,7 @@ ss_status ss_time_pass(ss_grid g, int pass, int nlaunch, double* mean_ms) {
 }
 
 ss_status ss_autotune(ss_grid g, int reps) {
+  if (g && g->solver == 1) return fail(SS_ERR_UNSUPPORTED, "ss_autotune: spectral solver only");
   if (!g) return fail(SS_ERR_ARG, "ss_autotune: null grid");
   if (reps < 1 || reps > 1000) return fail(SS_ERR_ARG, "ss_autotune: reps must be in [1, 1000]");
   if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_autotune: model and workspace must be set first");
@@ -1428,6 +1543,7 @@ ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out) {
     if (!g) return fail(SS_ERR_ARG, "ss_batch_create: grid %d is null", i);
     if (g->ndim != 2) return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d is not 2D", i);
     if (!g->has_model) return fail(SS_ERR_STATE, "ss_batch_create: grid %d has no model", i);
+    if (g->solver != 0) return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d uses the finite-difference solver", i);
     if (g->nf != 1) return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d has a two-field model", i);
     if (!g->ws) return fail(SS_ERR_STATE, "ss_batch_create: grid %d has no workspace", i);
     if (!batch_size_ok(g->n[0]) || !batch_size_ok(g->n[1]))
@@ -1566,6 +1682,7 @@ ss_status ss_batch_destroy(ss_batch b) {
 }
 
 ss_status ss_adjoint_workspace_size(ss_grid g, int64_t nsteps, int K, size_t* bytes) {
+  if (g && g->solver == 1) return fail(SS_ERR_UNSUPPORTED, "ss_adjoint_workspace_size: spectral solver only");
   if (!g || !bytes) return fail(SS_ERR_ARG, "ss_adjoint_workspace_size: null argument");
   if (!g->has_model) return fail(SS_ERR_STATE, "ss_adjoint_workspace_size: call ss_set_model first");
   if (g->model != SS_GRAY_SCOTT || g->ndim != 2)
@@ -1577,6 +1694,7 @@ ss_status ss_adjoint_workspace_size(ss_grid g, int64_t nsteps, int K, size_t* by
 }
 
 ss_status ss_bind_adjoint_workspace(ss_grid g, void* device_ptr, size_t bytes, int64_t nsteps, int K) {
+  if (g && g->solver == 1) return fail(SS_ERR_UNSUPPORTED, "ss_bind_adjoint_workspace: spectral solver only");
   size_t need = 0;
   SS_TRY(ss_adjoint_workspace_size(g, nsteps, K, &need));
   if (!device_ptr) return fail(SS_ERR_ARG, "ss_bind_adjoint_workspace: null pointer");

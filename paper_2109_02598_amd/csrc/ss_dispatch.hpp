@@ -11,6 +11,7 @@
 
 #include "ss_adjoint.hpp"
 #include "ss_batch.hpp"
+#include "ss_fd.hpp"
 #include "ss_kernels.hpp"
 
 namespace ss {
@@ -141,6 +142,8 @@ template <typename T>
 hipError_t run_sfpass(int nl, SFArgs a, hipStream_t s);
 template <typename T>
 hipError_t run_sfreduce(SFArgs a, hipStream_t s);
+template <typename T>
+hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s);
 
 #ifdef SS_DISPATCH_IMPL
 
@@ -274,6 +277,17 @@ hipError_t run_sfreduce(SFArgs a, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
+  const int64_t n = a.nx * a.ny * a.nz;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (dim == 2 && stencil == 0) return launch_with(fd_kernel<T, 2, 0>, grid, block, 0, s, LaunchEvents(), a);
+  if (dim == 2 && stencil == 9) return launch_with(fd_kernel<T, 2, 9>, grid, block, 0, s, LaunchEvents(), a);
+  if (dim == 3 && stencil == 0) return launch_with(fd_kernel<T, 3, 0>, grid, block, 0, s, LaunchEvents(), a);
+  if (dim == 3 && stencil == 19) return launch_with(fd_kernel<T, 3, 19>, grid, block, 0, s, LaunchEvents(), a);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev) {
   return launch_with(xpass_grouped<T>, dim3(blocks), dim3(threads), lds, s, ev, b);
 }
@@ -333,7 +347,8 @@ hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
   template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t, LaunchEvents);  \
   template hipError_t run_kpass<T>(int, KArgs, int, hipStream_t, LaunchEvents);           \
   template hipError_t run_sfpass<T>(int, SFArgs, hipStream_t);                            \
-  template hipError_t run_sfreduce<T>(SFArgs, hipStream_t);
+  template hipError_t run_sfreduce<T>(SFArgs, hipStream_t);                                \
+  template hipError_t run_fd<T>(int, int, FDArgs, hipStream_t);
 
 #endif  // SS_DISPATCH_IMPL
 

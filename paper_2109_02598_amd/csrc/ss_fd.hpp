@@ -1,0 +1,129 @@
+// Explicit forward-Euler finite-difference solver (Sec. 2.4.1) with the
+// second-order Laplacian stencils of Sec. 2.2.2, on the real-space fields.
+//
+// Stencils (periodic wrap; axes are powers of two, so wrapping is a mask):
+//   ST = 0  axis-wise central differences (5 points in 2D, 7 in 3D),
+//           sum over axes of (f[-1] - 2 f + f[+1]) / h_a^2;
+//   ST = 9  2D isotropic: (4 sum(edge neighbours) + sum(corners) - 20 f) / (6 h^2);
+//   ST = 19 3D isotropic: (2 sum(face neighbours) + sum(edge neighbours)
+//           - 24 f) / (6 h^2)   (equal spacing on every axis).
+// The leading error of the isotropic stencils depends on |k| only.
+//
+// One launch applies one operation at every cell (thread per cell, x
+// fastest).  A step is one to three launches, by model (the forms of the
+// right-hand sides are those of the equations of motion of Sec. 3):
+//   FD_AC     psi' = psi + dt M (kappa L psi + c1 psi - c2 psi^3)
+//   FD_GS     u' = u + dt (Du L u - u v^2 + F (1 - u)),
+//             v' = v + dt (Dv L v + u v^2 - (F + k) v)
+//   FD_MU_CH  mu = c2 psi^3 - c1 psi - kappa L psi
+//   FD_UPD    q' = q + dt s L w                      (conserved update)
+//   FD_LAP    a = L psi
+//   FD_MU_PFC mu = (r + q0^4) psi + 2 q0^2 a + L a + g2 psi^2 + g3 psi^3
+//   FD_MC     psi' = psi + dt (L psi + c1 psi - c2 psi^3 + 2 c5 psi m),
+//             b = -L m - c3 m + c4 m^3 - c5 psi^2     (then m' = m + dt L b)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+enum { FD_AC = 0, FD_GS = 1, FD_MU_CH = 2, FD_UPD = 3, FD_LAP = 4, FD_MU_PFC = 5, FD_MC = 6 };
+
+struct FDArgs {
+  const void* in[2];
+  void* out[2];
+  int64_t nx, ny, nz;        // nz = 1 in 2D
+  int lx, lxy;               // log2(nx), log2(nx * ny)
+  double ih2[3];             // 1 / h_a^2 (x, y, z) for the axis-wise stencil
+  double i6h2;               // 1 / (6 h^2) for the isotropic stencils
+  double dt;
+  double p[6];               // operation coefficients
+  int op;
+};
+
+template <typename T, int DIM, int ST>
+__device__ __forceinline__ T fd_lap(const T* __restrict__ f, int64_t x, int64_t y, int64_t z, const FDArgs& a) {
+  const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
+  auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+    return f[((((z + dz) & mz) * a.ny + ((y + dy) & my)) << a.lx) + ((x + dx) & mx)];
+  };
+  const T c = at(0, 0, 0);
+  if constexpr (ST == 0) {
+    T s = (at(-1, 0, 0) + at(1, 0, 0) - (T)2 * c) * (T)a.ih2[0] +
+          (at(0, -1, 0) + at(0, 1, 0) - (T)2 * c) * (T)a.ih2[1];
+    if constexpr (DIM == 3) s += (at(0, 0, -1) + at(0, 0, 1) - (T)2 * c) * (T)a.ih2[2];
+    return s;
+  } else if constexpr (ST == 9) {
+    const T edge = at(-1, 0, 0) + at(1, 0, 0) + at(0, -1, 0) + at(0, 1, 0);
+    const T corner = at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0);
+    return ((T)4 * edge + corner - (T)20 * c) * (T)a.i6h2;
+  } else {
+    const T face = at(-1, 0, 0) + at(1, 0, 0) + at(0, -1, 0) + at(0, 1, 0) + at(0, 0, -1) + at(0, 0, 1);
+    const T edge = at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0) +
+                   at(-1, 0, -1) + at(1, 0, -1) + at(-1, 0, 1) + at(1, 0, 1) +
+                   at(0, -1, -1) + at(0, 1, -1) + at(0, -1, 1) + at(0, 1, 1);
+    return ((T)2 * face + edge - (T)24 * c) * (T)a.i6h2;
+  }
+}
+
+template <typename T, int DIM, int ST>
+__global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (a.nx * a.ny * a.nz)) return;
+  const int64_t x = i & (a.nx - 1);
+  const int64_t y = (i >> a.lx) & (a.ny - 1);
+  const int64_t z = i >> a.lxy;
+  const T* in0 = (const T*)a.in[0];
+  const T* in1 = (const T*)a.in[1];
+  T* out0 = (T*)a.out[0];
+  T* out1 = (T*)a.out[1];
+  const T dt = (T)a.dt;
+  switch (a.op) {
+    case FD_AC: {
+      const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+      const T q = in0[i];
+      out0[i] = q + dt * (M * (kap * fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q));
+      break;
+    }
+    case FD_GS: {
+      const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
+      const T u = in0[i], v = in1[i];
+      const T uvv = u * v * v;
+      out0[i] = u + dt * (du * fd_lap<T, DIM, ST>(in0, x, y, z, a) - uvv + F * ((T)1 - u));
+      out1[i] = v + dt * (dv * fd_lap<T, DIM, ST>(in1, x, y, z, a) + uvv - (F + kk) * v);
+      break;
+    }
+    case FD_MU_CH: {
+      const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+      const T q = in0[i];
+      out0[i] = c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(in0, x, y, z, a);
+      break;
+    }
+    case FD_UPD: {
+      out0[i] = in0[i] + dt * ((T)a.p[0] * fd_lap<T, DIM, ST>(in1, x, y, z, a));
+      break;
+    }
+    case FD_LAP: {
+      out0[i] = fd_lap<T, DIM, ST>(in0, x, y, z, a);
+      break;
+    }
+    case FD_MU_PFC: {
+      const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
+      const T q = in0[i], lq = in1[i];
+      const T q02 = q0 * q0;
+      out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + fd_lap<T, DIM, ST>(in1, x, y, z, a) + g2 * q * q +
+                g3 * q * q * q;
+      break;
+    }
+    default: {  // FD_MC
+      const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
+      const T q = in0[i], m = in1[i];
+      out0[i] = q + dt * (fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q + (T)2 * c5 * q * m);
+      out1[i] = -fd_lap<T, DIM, ST>(in1, x, y, z, a) - c3 * m + c4 * m * m * m - c5 * q * q;
+      break;
+    }
+  }
+}
+
+}  // namespace ss

@@ -64,6 +64,7 @@ def lib():
         "ss_set_tiles": [vp, ctypes.POINTER(cint)],
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
         "ss_structure_factor_nbins": [vp, ctypes.POINTER(cint)],
+        "ss_set_solver": [vp, cint, cint],
         "ss_structure_factor": [vp, cint, vp, vp, cint],
         "ss_set_stream": [vp, vp],
         "ss_destroy_grid": [vp],
@@ -203,6 +204,13 @@ def ss_structure_factor(h, field, s_ptr, n_ptr, nbins):
     _check(lib().ss_structure_factor(h, int(field), s_ptr, n_ptr, int(nbins)))
 
 
+SOLVERS = {"spectral": 0, "euler": 1}
+
+
+def ss_set_solver(h, solver, stencil=0):
+    _check(lib().ss_set_solver(h, int(solver), int(stencil)))
+
+
 def ss_set_stream(h, stream):
     _check(lib().ss_set_stream(h, stream))
 
@@ -294,7 +302,7 @@ class Grid:
     """
 
     def __init__(self, n, dx, dtype="f64", model="allen_cahn", coef=(1, 1, 1, 1),
-                 dt=0.1, device="cuda:0", stream=None):
+                 dt=0.1, device="cuda:0", stream=None, solver="spectral", stencil=0):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -310,6 +318,7 @@ class Grid:
         self.nfields = NFIELDS[self.model_id]
         self.dt = float(dt)
         ss_set_model(self.h, self.model_id, coef, dt)
+        ss_set_solver(self.h, SOLVERS[solver] if isinstance(solver, str) else int(solver), stencil)
         nbytes = ss_workspace_size(self.h)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         ss_bind_workspace(self.h, self.workspace.data_ptr(), nbytes)

@@ -1,0 +1,77 @@
+"""Forward-Euler finite-difference solver on the GPU (Sec. 2.4.1, stencils of
+Sec. 2.2.2) against the oracle's forward-Euler solver with the same stencil,
+element by element, for every model in 2D and 3D, with the axis-wise and the
+isotropic second-order Laplacians."""
+import numpy as np
+import pytest
+
+from oracle import fd_euler
+from tests._common import COEF, TOL, as_input, need_gpu, rel_l2, say, synth_fields
+
+pytestmark = pytest.mark.gpu
+
+# explicit time steps inside each model's stability limit at dx = 1
+DT = {"allen_cahn": 0.05, "cahn_hilliard": 0.01, "pfc": 0.0005, "gray_scott": 0.1, "model_c": 0.01}
+COEF_FD = dict(COEF)
+COEF_FD["pfc"] = (-0.25, 1.0, 0.3, 1.0)
+
+
+def gpu_euler(model, n, dx, dt, steps, fields, dtype, stencil):
+    torch, specstep = need_gpu()
+    g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF_FD[model], dt=dt,
+                      solver="euler", stencil=stencil)
+    for i, f in enumerate(fields):
+        g.set_field(i, torch.from_numpy(np.ascontiguousarray(f)).to("cuda:0"))
+    g.step(steps)
+    out = [g.get_field(i).double().cpu().numpy() for i in range(len(fields))]
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc", "gray_scott", "model_c"])
+@pytest.mark.parametrize("n,stencil", [((64, 32), 0), ((32, 64), 9), ((16, 8, 32), 0), ((16, 16, 16), 19)])
+def test_euler_vs_oracle(model, n, stencil, dtype):
+    dx = (1.0,) * len(n)
+    steps = 20
+    fields = synth_fields(model, n, dx, 500 + len(n))
+    got = gpu_euler(model, n, dx, DT[model], steps, [f.astype(np.float32) if dtype == "f32" else f for f in fields],
+                    dtype, stencil)
+    ref = fd_euler.euler_n(as_input(fields, dtype), model, COEF_FD[model], DT[model], dx, steps, stencil)
+    for a, b in zip(got, ref):
+        e = rel_l2(a, b)
+        say(model, n, stencil, dtype, "rel_l2 %.3e" % e)
+        assert e <= TOL[dtype]
+
+
+@pytest.mark.parametrize("stencil,n", [(0, (128, 64)), (9, (64, 64)), (19, (32, 32, 32))])
+def test_euler_cahn_hilliard_conserves_mass(stencil, n):
+    """The update is dt M L(mu), and every stencil's weights sum to zero on a
+    periodic grid: the field's sum is conserved to rounding."""
+    dx = (1.0,) * len(n)
+    f0 = synth_fields("cahn_hilliard", n, dx, 77)[0]
+    out = gpu_euler("cahn_hilliard", n, dx, 0.01, 200, [f0], "f64", stencil)[0]
+    drift = abs(out.sum() - f0.sum()) / f0.size
+    say("CH mass drift per cell", stencil, drift)
+    assert drift < 1e-14
+
+
+def test_solver_choice_errors():
+    torch, specstep = need_gpu()
+    g = specstep.Grid((32, 32), (1.0, 1.0), dtype="f64", model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1)
+    with pytest.raises(specstep.SpecStepError):
+        specstep.ss_set_solver(g.h, 1, 19)       # 19 points is 3D
+    with pytest.raises(specstep.SpecStepError):
+        specstep.ss_set_solver(g.h, 2, 0)        # unknown solver
+    with pytest.raises(specstep.SpecStepError):
+        specstep.ss_set_solver(g.h, 0, 9)        # the spectral solver takes no stencil
+    g.close()
+    with pytest.raises(specstep.SpecStepError):
+        specstep.Grid((32, 32), (1.0, 2.0), model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1,
+                      solver="euler", stencil=9)   # isotropic stencil, unequal spacing
+    g = specstep.Grid((32, 32), (1.0, 1.0), model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1, solver="euler")
+    g.set_field(0, np.zeros((32, 32)))
+    for call in (lambda: g.autotune(1), lambda: g.structure_factor(0), lambda: g.time_pass("xpass", 2)):
+        with pytest.raises(specstep.SpecStepError):
+            call()
+    g.close()
