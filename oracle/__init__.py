@@ -19,6 +19,10 @@ Contents
                 it is the exact transpose of the map in spectral.py).
   structure.py  the radially averaged structure factor of Sec. 3
                 (Eq. 14, Porod's law).
+  operator_split.py  the procedure of Sec. 2.4.2 that builds the scheme
+                from equation text (linear/nonlinear split, derivative
+                pairing, A and B_i), with the ETD1 and the linearly
+                implicit factors.
 
 The FFT is numpy's (a library primitive); the oracle uses full complex
 transforms over every axis, never a real-to-complex layout.
