@@ -67,7 +67,8 @@ typedef enum {
   SS_CAHN_HILLIARD = 2,
   SS_PFC = 3,
   SS_GRAY_SCOTT = 4,
-  SS_MODEL_C = 5
+  SS_MODEL_C = 5,
+  SS_EQUATIONS = 6      /* equations read at run time: set by ss_set_equations only */
 } ss_model;
 
 /* Create a grid handle.  ndim is 2 or 3; n[0] is the x extent (fastest),
@@ -86,6 +87,60 @@ ss_status ss_create_grid(int ndim, const int64_t n[], const double dx[], ss_dtyp
  * until they are bound/set again); changing only coef or dt keeps them.
  * Errors: SS_ERR_ARG (unknown model, ncoef, non-finite, dt <= 0). */
 ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef, double dt);
+
+/* ---- Equations read at run time ---------------------------------------------
+ * The spectral scheme built from an equation of motion given as text
+ * (Sec. 2.4.2: the procedure that splits any equation into the linear
+ * operator, giving A, and derivative-grouped explicit terms, giving the
+ * B_i and E_i; the update psi^' = A psi^ + sum_i B_i (E_i^0 + E_i^1)^).
+ *
+ * Text: one equation per field (1 or 2 fields, in the order given, which
+ * is the field index), separated by ';' or newlines, each
+ *     name' = expression
+ * with numbers (decimal, optional exponent), the coefficient names of
+ * names[] (values[] holds their values), field names, + - * /, '^' or '**'
+ * with an integer literal exponent 0..16, parentheses, lap(e) and bilap(e)
+ * = lap(lap(e)).  Division only by constant expressions.  Example
+ * (Cahn-Hilliard):  "psi' = M*lap(c2*psi^3 - c1*psi - kappa*lap(psi))".
+ *
+ * The right-hand side is expanded into terms c lap^p (monomial in the
+ * fields).  Terms linear in the field itself form L (symbol lap -> -|k|^2,
+ * at most lap^3, so L(k^2) is at most cubic in k^2).  All other terms --
+ * constants, terms in the other field, nonlinear terms -- are explicit and
+ * are evaluated pointwise from the fields of the current step.  Limits of
+ * the GPU step: the explicit terms of a field all sit under the same
+ * derivative, 1 or lap (one B_i per field), in at most 8 monomials with
+ * exponents at most 7.  A derivative multiplied by a field (psi lap psi)
+ * has no operator form and is refused.
+ *
+ * scheme 0: ETD1 factors A = exp(L dt), B = (exp(L dt) - 1)/L (Eq. 4).
+ * scheme 1: linearly implicit factors A = 1/(1 - L dt), B = dt/(1 - L dt),
+ *   the first-order semi-implicit scheme; requires L(k^2) dt < 1 for all
+ *   k^2 up to the grid's largest, sum_a (pi/dx_a)^2.
+ * Afterwards the grid behaves as with ss_set_model (model SS_EQUATIONS):
+ * ss_step_n, fields, mass log, structure factor, autotune and timing work;
+ * the finite-difference solver, the adjoint and batches are
+ * SS_ERR_UNSUPPORTED.  Replacing equations with the same number of fields
+ * keeps the workspace and fields (like changing coefficients); otherwise
+ * they are dropped.
+ * Errors: SS_ERR_ARG (unreadable text, unknown or duplicate names,
+ * non-finite values, dt <= 0, unknown scheme, 1 - L dt <= 0),
+ * SS_ERR_UNSUPPORTED (a valid equation outside the limits above, or the
+ * finite-difference solver selected). */
+ss_status ss_set_equations(ss_grid g, const char* equations, const char* const names[],
+                           const double values[], int nvalues, double dt, int scheme);
+
+/* Host-only: the split ss_set_equations performs, without a grid or a
+ * device.  out (at least SS_SPLIT_OUT_LEN doubles) receives out[0] = the
+ * number of fields and, for field j at o = out + 1 + 30 j: o[0..3] = the
+ * coefficients of L in 1, k^2, k^4, k^6; o[4] = p, the derivative lap^p
+ * of the explicit terms (-1: none); o[5] = m, their number of monomials;
+ * then for i < m: o[6 + 3i] = coefficient, o[7 + 3i], o[8 + 3i] = the
+ * exponents of fields 0 and 1.  Unused entries are 0.
+ * Errors: as ss_set_equations (no grid checks). */
+#define SS_SPLIT_OUT_LEN 61
+ss_status ss_split_equations(const char* equations, const char* const names[], const double values[],
+                             int nvalues, double* out, int nout);
 
 /* ---- Solver choice ---------------------------------------------------------
  * solver 0 (default): the semi-implicit spectral scheme (Sec. 2.4.2).

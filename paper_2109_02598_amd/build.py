@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspecstep.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["ss_kernels_f32.hip", "ss_kernels_f64.hip", "ss_api.cpp"]
+SOURCES = ["ss_kernels_f32.hip", "ss_kernels_f64.hip", "ss_api.cpp", "ss_equation.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -22,6 +22,7 @@
 
 #include "../../include/specstep.h"
 #include "ss_dispatch.hpp"
+#include "ss_equation.hpp"
 
 namespace {
 
@@ -68,6 +69,8 @@ struct ss_grid_s {
   ss::KField kf[2];
   int nlm = ss::NLIN_POLY;
   double p[5] = {0};
+  ss::NTab tab = {};   // explicit terms of equations read at run time (NLIN_TABLE)
+  int scheme = 0;      // 0: ETD1 factors; 1: linearly implicit (ss_set_equations)
 
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -192,6 +195,8 @@ void build_operators(ss_grid g) {
       g->p[2] = c5;
       break;
     }
+    case SS_EQUATIONS:   // tables come from ss_set_equations
+      break;
   }
 }
 
@@ -304,6 +309,13 @@ void ensure_tiles(ss_grid g) {
   if (g->ndim == 3 && !g->tile_y) g->tile_y = t.y ? t.y : ss::y_tile_default(esz, (int)g->n[1], g->n[2]);
 }
 
+// Coefficients of the x pass's pointwise terms (fixed models) or their
+// monomial table (equations read at run time).
+void fill_nonlinear(ss_grid g, ss::XArgs& a) {
+  for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+  a.tab = g->tab;
+}
+
 template <typename T>
 ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void* in1, void* out0,
                        void* out1, const void* real_in, void* real_out, double scale,
@@ -325,7 +337,7 @@ ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void*
   a.rows_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_step : g->tile_x_io;
   a.tiles_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_ppb : 0;
   a.lb = g->lb;
-  for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+  fill_nonlinear(g, a);
   return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, nlm >= 0 ? nlm : g->nlm, a, g->stream,
                                     take_events(pt, PASS_X)),
                    "x pass launch");
@@ -383,6 +395,7 @@ ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr, int mode = 1) {
   ensure_tiles(g);
   a.lines_per_block = g->tile_k;
   a.lb = g->lb;
+  a.scheme = g->scheme;
   const int nl = (int)nlast;
   return hip_check(ss::run_kpass<T>(nl, a, mode, g->stream, mode == 2 ? ss::LaunchEvents() : take_events(pt, PASS_K)),
                    "k-space pass launch");
@@ -635,7 +648,7 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
           a.rows_per_block = r;
           a.tiles_per_block = ppb;
           a.lb = g->lb;
-          for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+          fill_nonlinear(g, a);
           return hip_check(ss::run_xpass<T>(nx, g->nf, ss::XMODE_STEP, g->nlm, a, g->stream, ev), "autotune x");
         };
         float ms;
@@ -678,6 +691,7 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
         a.a_scale = 1.0;
         a.b_scale = 1.0 / (double)g->cells();
         a.nf = g->nf;
+        a.scheme = g->scheme;
         a.three_d = g->ndim == 3;
         a.lines_per_block = l;
         a.lb = g->lb;
@@ -1146,7 +1160,7 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     a.rows_per_block = g->tile_x_step;
     a.tiles_per_block = g->tile_x_ppb;
     a.lb = g->lb;
-    for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
+    fill_nonlinear(g, a);
     return hip_check(ss::run_xpass<T>(nx, g->nf, ss::XMODE_STEP, g->nlm, a, g->stream, ev), "timed x pass");
   }
   if (pass == PASS_K) {
@@ -1170,6 +1184,7 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     a.a_scale = 1.0;
     a.b_scale = 1.0 / (double)g->cells();
     a.nf = g->nf;
+    a.scheme = g->scheme;
     a.three_d = g->ndim == 3;
     a.lines_per_block = g->tile_k;
     a.lb = g->lb;
@@ -1231,6 +1246,7 @@ ss_status ss_create_grid(int ndim, const int64_t n[], const double dx[], ss_dtyp
 
 ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef, double dt) {
   if (!g) return fail(SS_ERR_ARG, "ss_set_model: null grid");
+  if (model == SS_EQUATIONS) return fail(SS_ERR_ARG, "ss_set_model: equations are set with ss_set_equations");
   const int want = ncoef_of(model);
   if (want < 0) return fail(SS_ERR_ARG, "ss_set_model: unknown model %d", (int)model);
   if (ncoef != want) return fail(SS_ERR_ARG, "ss_set_model: model %d takes %d coefficients, got %d", (int)model, want, ncoef);
@@ -1251,7 +1267,110 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
   for (int i = 0; i < ncoef; ++i) g->coef[i] = coef[i];
   g->dt = dt;
   g->has_model = true;
+  g->scheme = 0;
   build_operators(g);
+  return SS_OK;
+}
+
+namespace {
+
+// Largest value of L(k^2) = l0 + l1 k^2 + l2 k^4 + l3 k^6 over k^2 in
+// [0, kmax2]: the ends and the stationary points inside.
+double max_symbol(const double* l, double kmax2) {
+  auto L = [&](double q) { return l[0] + q * (l[1] + q * (l[2] + q * l[3])); };
+  double best = std::max(L(0.0), L(kmax2));
+  // L'(q) = l1 + 2 l2 q + 3 l3 q^2
+  const double a = 3.0 * l[3], b = 2.0 * l[2], c = l[1];
+  std::vector<double> roots;
+  if (a == 0.0) {
+    if (b != 0.0) roots.push_back(-c / b);
+  } else {
+    const double disc = b * b - 4.0 * a * c;
+    if (disc >= 0.0) {
+      const double sq = std::sqrt(disc);
+      roots.push_back((-b + sq) / (2.0 * a));
+      roots.push_back((-b - sq) / (2.0 * a));
+    }
+  }
+  for (double q : roots)
+    if (q > 0.0 && q < kmax2) best = std::max(best, L(q));
+  return best;
+}
+
+}  // namespace
+
+ss_status ss_split_equations(const char* equations, const char* const names[], const double values[],
+                             int nvalues, double* out, int nout) {
+  if (!out || nout < SS_SPLIT_OUT_LEN) return fail(SS_ERR_ARG, "ss_split_equations: out needs %d doubles", SS_SPLIT_OUT_LEN);
+  ss::EqSplit sp;
+  char msg[256];
+  const int rc = ss::eq_split(equations, names, values, nvalues, &sp, msg, sizeof(msg));
+  if (rc) return fail((ss_status)rc, "ss_split_equations: %s", msg);
+  for (int i = 0; i < SS_SPLIT_OUT_LEN; ++i) out[i] = 0.0;
+  out[0] = sp.nf;
+  for (int j = 0; j < sp.nf; ++j) {
+    double* o = out + 1 + 30 * j;
+    for (int i = 0; i < 4; ++i) o[i] = sp.L[j][i];
+    o[4] = sp.p[j];
+    o[5] = sp.nterm[j];
+    for (int m = 0; m < sp.nterm[j]; ++m) {
+      o[6 + 3 * m] = sp.c[j][m];
+      o[7 + 3 * m] = sp.e[j][m][0];
+      o[8 + 3 * m] = sp.e[j][m][1];
+    }
+  }
+  return SS_OK;
+}
+
+ss_status ss_set_equations(ss_grid g, const char* equations, const char* const names[], const double values[],
+                           int nvalues, double dt, int scheme) {
+  if (!g) return fail(SS_ERR_ARG, "ss_set_equations: null grid");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(SS_ERR_ARG, "ss_set_equations: dt must be finite and > 0");
+  if (scheme != 0 && scheme != 1) return fail(SS_ERR_ARG, "ss_set_equations: unknown scheme %d", scheme);
+  if (g->solver != 0)
+    return fail(SS_ERR_UNSUPPORTED, "ss_set_equations: the finite-difference solver takes the fixed models");
+  ss::EqSplit sp;
+  char msg[256];
+  const int rc = ss::eq_split(equations, names, values, nvalues, &sp, msg, sizeof(msg));
+  if (rc) return fail((ss_status)rc, "ss_set_equations: %s", msg);
+  ss::KField kf[2];
+  ss::NTab tab;
+  memset(kf, 0, sizeof(kf));
+  memset(&tab, 0, sizeof(tab));
+  double kmax2 = 0.0;
+  for (int d = 0; d < g->ndim; ++d) kmax2 += (M_PI / g->dx[d]) * (M_PI / g->dx[d]);
+  for (int j = 0; j < sp.nf; ++j) {
+    for (int i = 0; i < 4; ++i) kf[j].l[i] = sp.L[j][i];
+    if (sp.p[j] == 0) kf[j].n[0] = 1.0;
+    if (sp.p[j] == 1) kf[j].n[1] = -1.0;   // lap -> -k^2
+    tab.cnt[j] = sp.nterm[j];
+    for (int m = 0; m < sp.nterm[j]; ++m) {
+      tab.c[j][m] = sp.c[j][m];
+      tab.e0[j][m] = sp.e[j][m][0];
+      tab.e1[j][m] = sp.e[j][m][1];
+    }
+    if (scheme == 1 && !(max_symbol(kf[j].l, kmax2) * dt < 1.0))
+      return fail(SS_ERR_ARG, "ss_set_equations: 1 - L dt is not positive for every mode of field %d", j);
+  }
+  const bool same = g->has_model && g->model == SS_EQUATIONS && g->nf == sp.nf;
+  if (g->has_model && !same) {
+    g->ws = nullptr;
+    g->ws_bytes = 0;
+    g->field_set[0] = g->field_set[1] = false;
+  }
+  if (!g->has_model || sp.nf != g->nf) g->tile_x_step = g->tile_y = g->tile_k = 0;
+  if (g->has_model && g->model != SS_EQUATIONS) g->lb = -1;
+  g->model = SS_EQUATIONS;
+  g->nf = sp.nf;
+  g->ncoef = 0;
+  g->dt = dt;
+  g->scheme = scheme;
+  for (double& v : g->p) v = 0;
+  g->kf[0] = kf[0];
+  g->kf[1] = kf[1];
+  g->tab = tab;
+  g->nlm = ss::NLIN_TABLE;
+  g->has_model = true;
   return SS_OK;
 }
 
@@ -1265,6 +1384,8 @@ ss_status ss_workspace_size(ss_grid g, size_t* bytes) {
 ss_status ss_set_solver(ss_grid g, int solver, int stencil) {
   if (!g) return fail(SS_ERR_ARG, "ss_set_solver: null grid");
   if (solver != 0 && solver != 1) return fail(SS_ERR_ARG, "ss_set_solver: unknown solver %d", solver);
+  if (solver == 1 && g->has_model && g->model == SS_EQUATIONS)
+    return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the finite-difference solver takes the fixed models");
   if (solver == 1) {
     const bool ok = stencil == 0 || (g->ndim == 2 ? (stencil == 5 || stencil == 9) : (stencil == 7 || stencil == 19));
     if (!ok) return fail(SS_ERR_ARG, "ss_set_solver: stencil %d is not available in %dD", stencil, g->ndim);
@@ -1545,6 +1666,8 @@ ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out) {
     if (!g->has_model) return fail(SS_ERR_STATE, "ss_batch_create: grid %d has no model", i);
     if (g->solver != 0) return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d uses the finite-difference solver", i);
     if (g->nf != 1) return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d has a two-field model", i);
+    if (g->nlm != ss::NLIN_POLY || g->scheme != 0)
+      return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d: batches take the fixed one-field models", i);
     if (!g->ws) return fail(SS_ERR_STATE, "ss_batch_create: grid %d has no workspace", i);
     if (!batch_size_ok(g->n[0]) || !batch_size_ok(g->n[1]))
       return fail(SS_ERR_UNSUPPORTED, "ss_batch_create: grid %d size outside [64, 2048]", i);

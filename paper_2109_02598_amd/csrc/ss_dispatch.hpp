@@ -197,6 +197,8 @@ hipError_t run_xpass(int nx, int nf, int mode, int nlm, XArgs a, hipStream_t s, 
   if (mode == XMODE_FWD) return xdisp<T, 1, XMODE_FWD, NLIN_POLY>(nx, a, s, ev);
   if (mode == XMODE_INV) return xdisp<T, 1, XMODE_INV, NLIN_POLY>(nx, a, s, ev);
   if (nf == 1 && nlm == NLIN_THRESH) return xdisp<T, 1, XMODE_STEP, NLIN_THRESH>(nx, a, s, ev);
+  if (nlm == NLIN_TABLE)
+    return nf == 1 ? xdisp<T, 1, XMODE_STEP, NLIN_TABLE>(nx, a, s, ev) : xdisp<T, 2, XMODE_STEP, NLIN_TABLE>(nx, a, s, ev);
   if (nf == 1) return xdisp<T, 1, XMODE_STEP, NLIN_POLY>(nx, a, s, ev);
   if (nlm == NLIN_GS) return xdisp<T, 2, XMODE_STEP, NLIN_GS>(nx, a, s, ev);
   return xdisp<T, 2, XMODE_STEP, NLIN_MODELC>(nx, a, s, ev);
@@ -232,7 +234,10 @@ hipError_t launch_k(KArgs a, int mode, hipStream_t s, LaunchEvents ev) {
   if (!k_tile_ok(ESZ, NL, a.nlines, a.three_d != 0, L)) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(a.nlines / L), (unsigned)a.nf), block((unsigned)(L * (NL / 8)));
   if (mode == 2) return launch_with(kfwd_kernel<T, NL>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  if (mode == 1 && a.scheme == 1)
+    return launch_with(kpass_kernel<T, NL, true, 1>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
   if (mode == 1) return launch_with(kpass_kernel<T, NL, true>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  if (a.scheme != 0) return hipErrorInvalidValue;   // the three-transform form is ETD1 only
   return launch_with(kpass_kernel<T, NL, false>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
 }
 

@@ -35,7 +35,7 @@ namespace ss {
 enum { XMODE_FWD = 0, XMODE_INV = 1, XMODE_STEP = 2 };
 // NLIN_THRESH is no equation of motion: it maps psi to the occupancy
 // [psi > 0] of the structure factor (Sec. 3).
-enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2, NLIN_THRESH = 3 };
+enum { NLIN_POLY = 0, NLIN_GS = 1, NLIN_MODELC = 2, NLIN_THRESH = 3, NLIN_TABLE = 4 };
 
 constexpr int LDS_BUDGET = 160 * 1024;
 
@@ -112,6 +112,15 @@ constexpr int x_block_threads(int esz, int nx, int nf) {
 // ---------------------------------------------------------------------------
 // x pass
 // ---------------------------------------------------------------------------
+// Explicit terms of an equation read at run time (NLIN_TABLE): field j's
+// pointwise function is E_j = sum_m c[j][m] f0^e0[j][m] f1^e1[j][m],
+// m < cnt[j] (at most 8 monomials, exponents at most 7).
+struct NTab {
+  int cnt[2];
+  int e0[2][8], e1[2][8];
+  double c[2][8];
+};
+
 struct XArgs {
   const void* spec_in[2];   // per field, T[kx][s] (INV, STEP)
   void* spec_out[2];        // per field, (FWD, STEP); may alias spec_in
@@ -125,6 +134,7 @@ struct XArgs {
   int xcd_remap;            // 1: spread consecutive chunks over one XCD
   double scale;             // multiplies the forward output (1/Nx for FWD)
   double p[5];              // nonlinear coefficients
+  NTab tab;                 // NLIN_TABLE: the explicit terms as monomials
 };
 
 template <typename T, int NX, int NF>
@@ -266,6 +276,37 @@ __device__ __forceinline__ void nonlinear(C<T>* c0, C<T>* c1, T p0, T p1, T p2) 
   }
 }
 
+// One monomial sum of the table at one cell (uniform trip counts: the
+// table is the same for every lane).
+template <typename T>
+__device__ __forceinline__ T ntab_eval(const NTab& tb, int j, T u, T v) {
+  T acc = (T)0;
+  for (int m = 0; m < tb.cnt[j]; ++m) {
+    T t = (T)tb.c[j][m];
+    for (int k = 0; k < tb.e0[j][m]; ++k) t *= u;
+    for (int k = 0; k < tb.e1[j][m]; ++k) t *= v;
+    acc += t;
+  }
+  return acc;
+}
+
+// NLIN_TABLE on both packed rows; every E_j reads the fields of the
+// current step (all inputs are read before any output is written).
+template <typename T, int NF>
+__device__ __forceinline__ void nonlinear_table(C<T>* c0, C<T>* c1, const NTab& tb) {
+  if constexpr (NF == 1) {
+    const T x = c0->x, y = c0->y;
+    c0->x = ntab_eval<T>(tb, 0, x, (T)0);
+    c0->y = ntab_eval<T>(tb, 0, y, (T)0);
+  } else {
+    const T ux = c0->x, uy = c0->y, vx = c1->x, vy = c1->y;
+    c0->x = ntab_eval<T>(tb, 0, ux, vx);
+    c0->y = ntab_eval<T>(tb, 0, uy, vy);
+    c1->x = ntab_eval<T>(tb, 1, ux, vx);
+    c1->y = ntab_eval<T>(tb, 1, uy, vy);
+  }
+}
+
 // threads per block of the x pass (launch bound)
 template <typename T, int NX, int NF>
 struct XThreads {
@@ -358,7 +399,8 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
         const T p0 = (T)a.p[0], p1 = (T)a.p[1], p2 = (T)a.p[2];
 #pragma unroll
         for (int e = 0; e < PT; ++e) {
-          if constexpr (NF == 1) nonlinear<T, NLM>(&c[0][e], &c[0][e], p0, p1, p2);
+          if constexpr (NLM == NLIN_TABLE) nonlinear_table<T, NF>(&c[0][e], &c[NF - 1][e], a.tab);
+          else if constexpr (NF == 1) nonlinear<T, NLM>(&c[0][e], &c[0][e], p0, p1, p2);
           else nonlinear<T, NLM>(&c[0][e], &c[NF - 1][e], p0, p1, p2);
         }
       }
@@ -602,6 +644,7 @@ struct KArgs {
   int nf;
   int three_d;
   int lb;                   // log2 of the row block of the spectral layout
+  int scheme;               // 0: ETD1 factors; 1: linearly implicit (selects the kernel)
 };
 
 // A = exp(z) and phi1(z) = (e^z - 1)/z of one mode (Eq. 4; phi1(0) = 1).
@@ -633,15 +676,24 @@ __device__ __forceinline__ void etd1_aphi(T z, T& A, T& phi, T& em) {
   }
 }
 
-// ETD1 factors of one mode (Eq. 4): A = exp(L dt) and B = dt phi1(L dt) N,
-// with the k-space pass scalings folded in.
-template <typename T>
+// Step factors of one mode, with the k-space pass scalings folded in.
+// scheme 0, ETD1 (Eq. 4): A = exp(L dt), B = dt phi1(L dt) N.
+// scheme 1, linearly implicit (the first-order semi-implicit scheme):
+// A = 1/(1 - L dt), B = dt A N (the host has checked 1 - L dt > 0).
+// The scheme is a compile-time choice: a run-time branch here costs the
+// FP64 k-space kernels registers they do not have.
+template <typename T, int SCH = 0>
 __device__ __forceinline__ void etd1_coeffs(const KField& f, T k2, double dt, double as, double bs,
                                             T& ao, T& bo) {
   const T L = (T)f.l[0] + k2 * ((T)f.l[1] + k2 * ((T)f.l[2] + k2 * (T)f.l[3]));
   const T z = L * (T)dt;
   T A, phi, em;
-  etd1_aphi<T>(z, A, phi, em);
+  if constexpr (SCH == 1) {
+    A = (T)1 / ((T)1 - z);
+    phi = A;
+  } else {
+    etd1_aphi<T>(z, A, phi, em);
+  }
   ao = A * (T)as;
   bo = (T)dt * phi * ((T)f.n[0] + (T)f.n[1] * k2) * (T)bs;
 }
@@ -716,7 +768,7 @@ struct KCfg {
 // nonlinear term is transformed; U = A S^ + B N G^ is written back as the
 // new S^ and, inverse transformed, as the new T (two transforms per line;
 // the host passes a_scale = 1).
-template <typename T, int NL, bool HAT = false>
+template <typename T, int NL, bool HAT = false, int SCH = 0>
 __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>* lds) {
   typedef KCfg<T, NL> K;
   constexpr int S = K::S, REG = K::REG;
@@ -791,8 +843,8 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
         const T kl = (T)m * klast_s;
         const T k2_0 = kmid2 + kl * kl;
         T a0, b0, an, bn;
-        etd1_coeffs<T>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
-        etd1_coeffs<T>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
+        etd1_coeffs<T, SCH>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
+        etd1_coeffs<T, SCH>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
         const C<T> cm = cconj<T>(xm[pidx<T>((NL - p) & (NL - 1))]);
         const T ap = (T)0.5 * (a0 + an), am = (T)0.5 * (a0 - an);
         ct[0][e] = mk<T>(ap * ct[0][e].x + am * cm.x, ap * ct[0][e].y + am * cm.y);
@@ -811,8 +863,8 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
       if (packed) {
         const T k2_0 = kmid2 + kl * kl;
         T a0, b0, an, bn;
-        etd1_coeffs<T>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
-        etd1_coeffs<T>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
+        etd1_coeffs<T, SCH>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0);
+        etd1_coeffs<T, SCH>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn);
         const C<T> dm = cconj<T>(xm[pidx<T>((NL - p) & (NL - 1))]);
         const T bp = (T)0.5 * (b0 + bn), bmn = (T)0.5 * (b0 - bn);
         ct[0][e] = mk<T>(ct[0][e].x + bp * cg[0][e].x + bmn * dm.x,
@@ -820,7 +872,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
       } else {
         const T k2 = kxv * kxv + kmid2 + kl * kl;
         T av, bv;
-        etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
+        etd1_coeffs<T, SCH>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
         ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
       }
     }
@@ -836,7 +888,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
       const T kl = (T)m * klast_s;
       const T k2 = kxv * kxv + kmid2 + kl * kl;
       T av, bv;
-      etd1_coeffs<T>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
+      etd1_coeffs<T, SCH>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
       ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
     }
   }
@@ -851,11 +903,11 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   for (int e = 0; e < 8; ++e) *kline_at(so, kline_off(e * S, hx, lb), tb) = ct[0][e];
 }
 
-template <typename T, int NL, bool HAT>
+template <typename T, int NL, bool HAT, int SCH = 0>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : SS_KWAVES)))
 kpass_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
-  kpass_body<T, NL, HAT>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
+  kpass_body<T, NL, HAT, SCH>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
 
 // S^ = FFT(T) / N_last along every line of field blockIdx.y (the stepping

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libspecstep.so")
 SS_OK, SS_ERR_ARG, SS_ERR_UNSUPPORTED, SS_ERR_STATE, SS_ERR_DEVICE, SS_ERR_NONFINITE = range(6)
 SS_F32, SS_F64 = 4, 8
 MODELS = {"allen_cahn": 1, "cahn_hilliard": 2, "pfc": 3, "gray_scott": 4, "model_c": 5}
+SS_EQUATIONS = 6
 NFIELDS = {1: 1, 2: 1, 3: 1, 4: 2, 5: 2}
 
 _lib = None
@@ -65,6 +66,10 @@ def lib():
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
         "ss_structure_factor_nbins": [vp, ctypes.POINTER(cint)],
         "ss_set_solver": [vp, cint, cint],
+        "ss_set_equations": [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl), cint,
+                             dbl, cint],
+        "ss_split_equations": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl), cint,
+                               ctypes.POINTER(dbl), cint],
         "ss_structure_factor": [vp, cint, vp, vp, cint],
         "ss_set_stream": [vp, vp],
         "ss_destroy_grid": [vp],
@@ -205,6 +210,36 @@ def ss_structure_factor(h, field, s_ptr, n_ptr, nbins):
 
 
 SOLVERS = {"spectral": 0, "euler": 1}
+SCHEMES = {"etd1": 0, "implicit": 1}
+SPLIT_OUT_LEN = 61
+
+
+def _coef_arrays(coefs):
+    names = list((coefs or {}).keys())
+    cn = (ctypes.c_char_p * max(1, len(names)))(*[str(k).encode() for k in names])
+    cv = (ctypes.c_double * max(1, len(names)))(*[float(coefs[k]) for k in names])
+    return cn, cv, len(names)
+
+
+def ss_set_equations(h, text, coefs, dt, scheme=0):
+    cn, cv, n = _coef_arrays(coefs)
+    _check(lib().ss_set_equations(h, text.encode(), cn, cv, n, float(dt),
+                                  SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)))
+
+
+def ss_split_equations(text, coefs=None):
+    """The split of ss_set_equations, host only: a list with, per field,
+    {"L": [l0, l1, l2, l3], "p": p, "terms": [(c, e0, e1), ...]}."""
+    cn, cv, n = _coef_arrays(coefs)
+    out = (ctypes.c_double * SPLIT_OUT_LEN)()
+    _check(lib().ss_split_equations(text.encode(), cn, cv, n, out, SPLIT_OUT_LEN))
+    res = []
+    for j in range(int(out[0])):
+        o = out[1 + 30 * j: 31 + 30 * j]
+        m = int(o[5])
+        res.append({"L": list(o[0:4]), "p": int(o[4]),
+                    "terms": [(o[6 + 3 * i], int(o[7 + 3 * i]), int(o[8 + 3 * i])) for i in range(m)]})
+    return res
 
 
 def ss_set_solver(h, solver, stencil=0):
@@ -302,7 +337,11 @@ class Grid:
     """
 
     def __init__(self, n, dx, dtype="f64", model="allen_cahn", coef=(1, 1, 1, 1),
-                 dt=0.1, device="cuda:0", stream=None, solver="spectral", stencil=0):
+                 dt=0.1, device="cuda:0", stream=None, solver="spectral", stencil=0,
+                 equations=None, coefs=None, scheme="etd1"):
+        """``equations`` (text, with coefficient values ``coefs``) replaces
+        ``model``/``coef``: the scheme is built from the equations at run
+        time (ss_set_equations); ``scheme`` is "etd1" or "implicit"."""
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -314,11 +353,17 @@ class Grid:
             stream = torch.cuda.current_stream(self.device).cuda_stream
         self.stream = stream
         self.h = ss_create_grid(self.n, self.dx, self.ss_dtype, stream)
-        self.model_id = MODELS[model] if isinstance(model, str) else int(model)
-        self.nfields = NFIELDS[self.model_id]
         self.dt = float(dt)
-        ss_set_model(self.h, self.model_id, coef, dt)
-        ss_set_solver(self.h, SOLVERS[solver] if isinstance(solver, str) else int(solver), stencil)
+        if equations is not None:
+            self.model_id = SS_EQUATIONS
+            self.nfields = len(ss_split_equations(equations, coefs))
+            ss_set_solver(self.h, SOLVERS[solver] if isinstance(solver, str) else int(solver), stencil)
+            ss_set_equations(self.h, equations, coefs, dt, scheme)
+        else:
+            self.model_id = MODELS[model] if isinstance(model, str) else int(model)
+            self.nfields = NFIELDS[self.model_id]
+            ss_set_model(self.h, self.model_id, coef, dt)
+            ss_set_solver(self.h, SOLVERS[solver] if isinstance(solver, str) else int(solver), stencil)
         nbytes = ss_workspace_size(self.h)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         ss_bind_workspace(self.h, self.workspace.data_ptr(), nbytes)
@@ -335,6 +380,17 @@ class Grid:
         if mid != self.model_id:
             self.model_id = mid
             self.nfields = NFIELDS[mid]
+            nbytes = ss_workspace_size(self.h)
+            self.workspace = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            ss_bind_workspace(self.h, self.workspace.data_ptr(), nbytes)
+
+    def set_equations(self, equations, coefs, dt, scheme="etd1"):
+        nf = len(ss_split_equations(equations, coefs))
+        ss_set_equations(self.h, equations, coefs, dt, scheme)
+        self.dt = float(dt)
+        if self.model_id != SS_EQUATIONS or nf != self.nfields:
+            self.model_id = SS_EQUATIONS
+            self.nfields = nf
             nbytes = ss_workspace_size(self.h)
             self.workspace = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
             ss_bind_workspace(self.h, self.workspace.data_ptr(), nbytes)
