@@ -245,6 +245,57 @@ def run_euler(w, dtype, steps=500):
     return out
 
 
+# the fixed models' equations as text, for the run-time split (coefficient
+# names in the order of each model's coefficient vector)
+MODEL_TEXT = {
+    "cahn_hilliard": ("psi' = M*lap(c2*psi^3 - c1*psi - kappa*lap(psi))", ("M", "kappa", "c1", "c2")),
+    "allen_cahn": ("psi' = M*(kappa*lap(psi) + c1*psi - c2*psi^3)", ("M", "kappa", "c1", "c2")),
+    "pfc": ("psi' = lap((r + q0^4)*psi + 2*q0^2*lap(psi) + bilap(psi) + g2*psi^2 + g3*psi^3)",
+            ("r", "q0", "g2", "g3")),
+    "gray_scott": ("u' = Du*lap(u) - u*v^2 + F*(1 - u); v' = Dv*lap(v) + u*v^2 - (F + k)*v",
+                   ("Du", "Dv", "F", "k")),
+}
+
+
+def run_equations(w, dtype, steps=300):
+    """The same workload driven by its equation read at run time (the x pass
+    evaluates a monomial table, the k-space pass the split's symbol), with
+    the ETD1 and the linearly implicit factors, against the fixed-model
+    kernels: time per step and the mean launch of each pass."""
+    import torch
+    from paper_2109_02598_amd import specstep
+    text, names = MODEL_TEXT[w.model]
+    coefs = dict(zip(names, w.coef))
+    esz = 8 if dtype == "f64" else 4
+    out = {"workload": "%s as the text  %s, %s, %d steps" % (w.name, text, dtype, steps)}
+    for label, kw in (("fixed_model", dict(model=w.model, coef=w.coef)),
+                      ("equations_etd1", dict(equations=text, coefs=coefs, scheme="etd1")),
+                      ("equations_implicit", dict(equations=text, coefs=coefs, scheme="implicit"))):
+        g = specstep.Grid(w.n, w.dx, dtype=dtype, dt=w.dt, **kw)
+        g.autotune(3)
+        for i, f in enumerate(w.fields):
+            g.set_field(i, torch.from_numpy(f).to("cuda:0"))
+        g.step(20)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        passes = {k: g.time_pass(k, 200) for k in (("xpass", "kpass") if len(w.n) == 2
+                                                    else ("xpass", "kpass", "ypass_inv", "ypass_fwd"))}
+        g.close()
+        out[label] = {"value": round(w.cells * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
+                      "us_per_step": round(ms * 1e3 / steps, 2),
+                      "mean_launch_us": {k: round(v * 1e3, 2) for k, v in passes.items()},
+                      "achieved_GBs": {k: round(algorithmic_bytes(k, w, esz) / (v * 1e-3) / 1e9, 1)
+                                       for k, v in passes.items()}}
+    return out
+
+
 def roofline(w, dtype, prof, traffic_rec):
     esz = 8 if dtype == "f64" else 4
     tiles = prof.pop("tiles", None)
@@ -303,6 +354,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use the default tiles")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-grid run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-euler", action="store_true", help="skip the finite-difference solver timing")
+    ap.add_argument("--no-equations", action="store_true", help="skip the run-time equations timing")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (for scaling "
@@ -353,8 +406,14 @@ def main():
     if not args.no_adjoint:
         print("bench: adjoint workload", file=sys.stderr, flush=True)
         adj = run_adjoint()
-    print("bench: forward-Euler finite differences", file=sys.stderr, flush=True)
-    euler = run_euler(w, args.dtype)
+    euler = None
+    if not args.no_euler:
+        print("bench: forward-Euler finite differences", file=sys.stderr, flush=True)
+        euler = run_euler(w, args.dtype)
+    equations = None
+    if w.model in MODEL_TEXT and not args.no_equations:
+        print("bench: equations read at run time", file=sys.stderr, flush=True)
+        equations = run_equations(w, args.dtype)
     batch = None
     if not args.no_batch:
         print("bench: batched 64-grid workload", file=sys.stderr, flush=True)
@@ -383,6 +442,7 @@ def main():
             args.dtype: sf1, other: sf2},
         "batched": batch,
         "euler_fd": euler,
+        "equations": equations,
         "adjoint": adj,
         "wall_s_timed_region": round(wall, 4),
     }

@@ -1343,12 +1343,15 @@ ss_status ss_set_equations(ss_grid g, const char* equations, const char* const n
     for (int i = 0; i < 4; ++i) kf[j].l[i] = sp.L[j][i];
     if (sp.p[j] == 0) kf[j].n[0] = 1.0;
     if (sp.p[j] == 1) kf[j].n[1] = -1.0;   // lap -> -k^2
-    tab.cnt[j] = sp.nterm[j];
+    // monomials -> dense table: a[j][power of field 1][power of field 0]
     for (int m = 0; m < sp.nterm[j]; ++m) {
-      tab.c[j][m] = sp.c[j][m];
-      tab.e0[j][m] = sp.e[j][m][0];
-      tab.e1[j][m] = sp.e[j][m][1];
+      const int e0 = sp.e[j][m][0], e1 = sp.e[j][m][1];
+      tab.a[j][e1][e0] += sp.c[j][m];
+      tab.du[j][e1] = std::max(tab.du[j][e1], e0);
+      tab.dv[j] = std::max(tab.dv[j], e1);
     }
+    for (int k = 0; k < 8; ++k)
+      for (int i = 0; i < 8; ++i) tab.af[j][k][i] = (float)tab.a[j][k][i];
     if (scheme == 1 && !(max_symbol(kf[j].l, kmax2) * dt < 1.0))
       return fail(SS_ERR_ARG, "ss_set_equations: 1 - L dt is not positive for every mode of field %d", j);
   }

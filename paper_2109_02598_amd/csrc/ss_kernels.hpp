@@ -112,13 +112,15 @@ constexpr int x_block_threads(int esz, int nx, int nf) {
 // ---------------------------------------------------------------------------
 // x pass
 // ---------------------------------------------------------------------------
-// Explicit terms of an equation read at run time (NLIN_TABLE): field j's
-// pointwise function is E_j = sum_m c[j][m] f0^e0[j][m] f1^e1[j][m],
-// m < cnt[j] (at most 8 monomials, exponents at most 7).
+// Explicit terms of an equation read at run time (NLIN_TABLE), as dense
+// polynomials: field j's pointwise function is
+//   E_j(u, v) = sum_{k <= dv[j]} v^k H_jk(u),  H_jk(u) = sum_{i <= du[j][k]} a[j][k][i] u^i
+// with u, v the fields 0 and 1 (exponents at most 7); af is a in FP32.
 struct NTab {
-  int cnt[2];
-  int e0[2][8], e1[2][8];
-  double c[2][8];
+  int dv[2];
+  int du[2][8];
+  double a[2][8][8];
+  float af[2][8][8];
 };
 
 struct XArgs {
@@ -276,34 +278,57 @@ __device__ __forceinline__ void nonlinear(C<T>* c0, C<T>* c1, T p0, T p1, T p2) 
   }
 }
 
-// One monomial sum of the table at one cell (uniform trip counts: the
-// table is the same for every lane).
-template <typename T>
-__device__ __forceinline__ T ntab_eval(const NTab& tb, int j, T u, T v) {
-  T acc = (T)0;
-  for (int m = 0; m < tb.cnt[j]; ++m) {
-    T t = (T)tb.c[j][m];
-    for (int k = 0; k < tb.e0[j][m]; ++k) t *= u;
-    for (int k = 0; k < tb.e1[j][m]; ++k) t *= v;
-    acc += t;
+// E_j of the table on W values at once: Horner in u for each power of v
+// (the coefficients unrolled over their 8 slots with uniform guards, so
+// their loads sit at fixed offsets and serve all W values), then Horner
+// in v.
+template <typename T, int NF, int W>
+__device__ __forceinline__ void ntab_eval(const NTab& tb, int j, const T (&u)[W], const T (&v)[W], T (&acc)[W]) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc[w] = (T)0;
+  const int kmax = NF == 2 ? tb.dv[j] : 0;
+  for (int k = kmax; k >= 0; --k) {
+    const int dk = tb.du[j][k];
+    T h[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) h[w] = (T)0;
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+      if (i <= dk) {
+        const T ai = sizeof(T) == 8 ? (T)tb.a[j][k][i] : (T)tb.af[j][k][i];
+#pragma unroll
+        for (int w = 0; w < W; ++w) h[w] = h[w] * u[w] + ai;
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = NF == 2 ? acc[w] * v[w] + h[w] : h[w];
   }
-  return acc;
 }
 
-// NLIN_TABLE on both packed rows; every E_j reads the fields of the
-// current step (all inputs are read before any output is written).
-template <typename T, int NF>
-__device__ __forceinline__ void nonlinear_table(C<T>* c0, C<T>* c1, const NTab& tb) {
-  if constexpr (NF == 1) {
-    const T x = c0->x, y = c0->y;
-    c0->x = ntab_eval<T>(tb, 0, x, (T)0);
-    c0->y = ntab_eval<T>(tb, 0, y, (T)0);
-  } else {
-    const T ux = c0->x, uy = c0->y, vx = c1->x, vy = c1->y;
-    c0->x = ntab_eval<T>(tb, 0, ux, vx);
-    c0->y = ntab_eval<T>(tb, 0, uy, vy);
-    c1->x = ntab_eval<T>(tb, 1, ux, vx);
-    c1->y = ntab_eval<T>(tb, 1, uy, vy);
+// NLIN_TABLE over a thread's PT cells (two packed rows each), in chunks
+// of 4 cells; every E_j reads the fields of the current step (a chunk's
+// inputs are all read before its outputs are written).
+template <typename T, int NF, int PT>
+__device__ __forceinline__ void nonlinear_table(C<T> (&c)[NF][PT], const NTab& tb) {
+  constexpr int CH = 4, W = 2 * CH;
+  static_assert(PT % CH == 0, "chunk size");
+#pragma unroll
+  for (int e0 = 0; e0 < PT; e0 += CH) {
+    T u[W], v[W], r0[W], r1[W];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      u[2 * q] = c[0][e0 + q].x;
+      u[2 * q + 1] = c[0][e0 + q].y;
+      v[2 * q] = c[NF - 1][e0 + q].x;
+      v[2 * q + 1] = c[NF - 1][e0 + q].y;
+    }
+    ntab_eval<T, NF, W>(tb, 0, u, v, r0);
+    if constexpr (NF == 2) ntab_eval<T, NF, W>(tb, 1, u, v, r1);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      c[0][e0 + q] = mk<T>(r0[2 * q], r0[2 * q + 1]);
+      if constexpr (NF == 2) c[1][e0 + q] = mk<T>(r1[2 * q], r1[2 * q + 1]);
+    }
   }
 }
 
@@ -396,12 +421,15 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
         }
         continue;
       } else {
-        const T p0 = (T)a.p[0], p1 = (T)a.p[1], p2 = (T)a.p[2];
+        if constexpr (NLM == NLIN_TABLE) {
+          nonlinear_table<T, NF, PT>(c, a.tab);
+        } else {
+          const T p0 = (T)a.p[0], p1 = (T)a.p[1], p2 = (T)a.p[2];
 #pragma unroll
-        for (int e = 0; e < PT; ++e) {
-          if constexpr (NLM == NLIN_TABLE) nonlinear_table<T, NF>(&c[0][e], &c[NF - 1][e], a.tab);
-          else if constexpr (NF == 1) nonlinear<T, NLM>(&c[0][e], &c[0][e], p0, p1, p2);
-          else nonlinear<T, NLM>(&c[0][e], &c[NF - 1][e], p0, p1, p2);
+          for (int e = 0; e < PT; ++e) {
+            if constexpr (NF == 1) nonlinear<T, NLM>(&c[0][e], &c[0][e], p0, p1, p2);
+            else nonlinear<T, NLM>(&c[0][e], &c[NF - 1][e], p0, p1, p2);
+          }
         }
       }
     }
