@@ -289,15 +289,17 @@ __device__ __forceinline__ void ntab_eval(const NTab& tb, int j, const T (&u)[W]
   const int kmax = NF == 2 ? tb.dv[j] : 0;
   for (int k = kmax; k >= 0; --k) {
     const int dk = tb.du[j][k];
+    T ak[8];   // the row, loaded whole before the guards: one batch of loads
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ak[i] = sizeof(T) == 8 ? (T)tb.a[j][k][i] : (T)tb.af[j][k][i];
     T h[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) h[w] = (T)0;
 #pragma unroll
     for (int i = 7; i >= 0; --i) {
       if (i <= dk) {
-        const T ai = sizeof(T) == 8 ? (T)tb.a[j][k][i] : (T)tb.af[j][k][i];
 #pragma unroll
-        for (int w = 0; w < W; ++w) h[w] = h[w] * u[w] + ai;
+        for (int w = 0; w < W; ++w) h[w] = h[w] * u[w] + ak[i];
       }
     }
 #pragma unroll
