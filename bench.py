@@ -72,11 +72,19 @@ def algorithmic_bytes(pass_name, w, esz):
             "ypass_inv": 2 * n, "ypass_fwd": 2 * n}[pass_name]
 
 
+PASSES = {2: ("xpass", "kpass"), 3: ("xpass", "kpass", "ypass_inv", "ypass_fwd")}
+
+
 def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
     import torch
     from paper_2109_02598_amd import specstep
     g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=w.dt)
     tiles = g.autotune(5) if autotune else g.tiles()
+    # mean launch of each pass from back-to-back launches between two events
+    # (per-launch events add a completion fence to every launch), taken
+    # before the fields are loaded, when the passes run on the step's own
+    # arrays
+    b2b = {k: g.time_pass(k, 200) for k in PASSES[len(w.n)]}
     for i, f in enumerate(w.fields):
         g.set_field(i, torch.from_numpy(f).to("cuda:0"))
     g.enable_mass_log(warmup + steps + profile_steps)
@@ -94,9 +102,7 @@ def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     prof = g.step_profiled(profile_steps)
-    # mean launch time of each pass from back-to-back launches between two
-    # events (per-launch events add a completion fence to every launch)
-    prof["mean_b2b"] = {k: g.time_pass(k, 200) for k in prof}
+    prof["mean_b2b"] = b2b
     mass = g.mass_log()
     # one radially averaged structure factor of the evolved field (x pass with
     # the occupancy threshold, line transforms, binning), back to back
@@ -273,6 +279,7 @@ def run_equations(w, dtype, steps=300):
                       ("equations_implicit", dict(equations=text, coefs=coefs, scheme="implicit"))):
         g = specstep.Grid(w.n, w.dx, dtype=dtype, dt=w.dt, **kw)
         g.autotune(3)
+        passes = {k: g.time_pass(k, 200) for k in PASSES[len(w.n)]}   # before the fields: step's arrays
         for i, f in enumerate(w.fields):
             g.set_field(i, torch.from_numpy(f).to("cuda:0"))
         g.step(20)
@@ -285,8 +292,6 @@ def run_equations(w, dtype, steps=300):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        passes = {k: g.time_pass(k, 200) for k in (("xpass", "kpass") if len(w.n) == 2
-                                                    else ("xpass", "kpass", "ypass_inv", "ypass_fwd"))}
         g.close()
         out[label] = {"value": round(w.cells * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
                       "us_per_step": round(ms * 1e3 / steps, 2),

@@ -209,9 +209,14 @@ ss_status ss_step_n_profiled(ss_grid g, int64_t nsteps, double* pass_ms, int64_t
 /* Mean duration in milliseconds of one launch of pass kind `pass` (as in
  * ss_step_n_profiled) with the current tiling, from `nlaunch` back-to-back
  * launches between two events on the grid's stream (after one warm-up
- * launch).  The launches leave the fields untouched: the x pass reads the
- * state and writes the scratch arrays, the k-space and y passes run on
- * the scratch and staging arrays.  For measurement.  Synchronises. */
+ * launch).  While no field is stored (after binding the workspace, before
+ * ss_set_field) every pass runs on the step's own arrays, so it moves the
+ * traffic a step moves; the workspace contents are then undefined.  Once a
+ * field is stored the launches leave the fields untouched: the x pass
+ * reads the state and writes the scratch arrays, the k-space and y passes
+ * run in place on the scratch and staging arrays (fewer distinct arrays
+ * than a step: where a step's arrays outgrow the 256 MB Infinity Cache
+ * these read faster than in a step).  For measurement.  Synchronises. */
 ss_status ss_time_pass(ss_grid g, int pass, int nlaunch, double* mean_ms);
 
 /* Choose the work decomposition of every kernel of the step for this
@@ -219,8 +224,10 @@ ss_status ss_time_pass(ss_grid g, int pass, int nlaunch, double* mean_ms);
  * times on the grid's stream and keeping the fastest.  The tilings do not
  * change any result (each line is transformed by the same code whatever
  * its workgroup).  The choice is also remembered for later grids of the
- * same shape, dtype and model field count.  Only the scratch and staging
- * parts of the workspace are written: the fields are untouched.
+ * same shape, dtype and model field count.  Timing as ss_time_pass: while
+ * no field is stored the passes run on the step's own arrays (best called
+ * then); afterwards only the scratch and staging parts of the workspace
+ * are written and the fields are untouched.
  * Synchronises the stream.  Errors: SS_ERR_STATE (no model/workspace),
  * SS_ERR_ARG (reps outside [1, 1000]), SS_ERR_DEVICE. */
 ss_status ss_autotune(ss_grid g, int reps);

@@ -933,8 +933,11 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   for (int e = 0; e < 8; ++e) *kline_at(so, kline_off(e * S, hx, lb), tb) = ct[0][e];
 }
 
+// FP64: three waves per SIMD (168 VGPRs), except 128- and 256-point lines,
+// whose 3D plane pairing needs ~176 VGPRs (spills under the cap of three).
 template <typename T, int NL, bool HAT, int SCH = 0>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : SS_KWAVES)))
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? ((NL == 128 || NL == 256) ? 2 : 3) : SS_KWAVES)))
 kpass_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
   kpass_body<T, NL, HAT, SCH>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
