@@ -142,3 +142,48 @@ def test_replacing_equations_and_errors():
     g.set_equations("u' = lap(u) - v; v' = u", {}, 0.1)
     assert g.nfields == 2
     g.close()
+
+
+# the table's extremes: degree 7 in either field, eight monomials, no
+# explicit term at all, L up to lap^3; long and short lines
+EDGE = {
+    "no_explicit_terms": ("psi' = 0.3*lap(psi) - 0.01*bilap(psi) - 0.2*psi", {}, 1),
+    "degree_7_eight_monomials": ("x' = lap(x) - 0.1*x + 0.01*(1 + x^2 + x^3 - x^4 + x^5/5 - x^6/6 + x^7/7) - 0.02*x^3",
+                                 {}, 1),
+    "lap_cubed": ("p' = 0.05*lap(lap(lap(p))) + 0.1*lap(p) - 0.3*p - p^3 + 0.2*p^2", {}, 1),
+    "two_fields_degree_7": ("a' = lap(a) - a + 0.01*b^7 - 0.02*a^3*b^2 + 0.03*a^7\n"
+                            "b' = 0.5*lap(b) - 0.1*b + 0.05*a^2*b^3 - 0.01*a^7*b^7", {}, 2),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name", sorted(EDGE))
+@pytest.mark.parametrize("n", [(4096, 8), (8, 1024), (16, 8, 8)])
+def test_table_extremes_and_ragged_shapes(name, n, dtype):
+    text, coefs, nf = EDGE[name]
+    sp = osp.parse(text, coefs)
+    assert len(sp.fields) == nf
+    dx = tuple(1.0 + 0.03 * i for i in range(len(n)))
+    shape = tuple(reversed(n))
+    f0 = as_input(smooth_fields(nf, shape, 41, amp=0.6, offsets=(0.2, -0.3)), dtype)
+    got, _ = gpu_equations(text, coefs, n, dx, 0.02, 30, f0, dtype)
+    want = osp.step_n(f0, sp, 0.02, dx, 30)
+    check(got, want, dtype, (name, n))
+
+
+def test_the_library_split_of_the_extremes_is_the_oracles():
+    _, specstep = need_gpu()
+    for name, (text, coefs, nf) in EDGE.items():
+        got = specstep.ss_split_equations(text, coefs)
+        sp = osp.parse(text, coefs)
+        assert len(got) == nf
+        for j in range(nf):
+            merged = {}
+            for _, e0, e1 in sp.channels[j]:
+                for ex, c in list(e0.items()) + list(e1.items()):
+                    key = tuple(ex) + (0,) * (2 - len(ex))
+                    merged[key] = merged.get(key, 0.0) + c
+            lib = {(e0, e1): c for c, e0, e1 in got[j]["terms"]}
+            assert set(lib) == set(merged), name
+            for k in lib:
+                assert lib[k] == pytest.approx(merged[k], rel=1e-14), (name, k)
