@@ -820,6 +820,24 @@ ss_status autotune_t(ss_grid g, int reps) {
   g->tile_x_ppb = bppb;
   g->tile_k = bk;
   g->tile_y = by;
+  if (free_layout) {
+    // the dominant pass's tiling, settled by whole steps as well: single
+    // launches repeated on the same arrays can rank tilings differently
+    // from steps once the arrays outgrow the Infinity Cache
+    const int esz = esz_of(g);
+    float best_step = 1e30f;
+    for (int l = 1; l <= 512; l *= 2) {
+      if (!ss::k_tile_ok(esz, nlast(g), nlines_k(g), g->ndim == 3, l)) continue;
+      g->tile_k = l;
+      float ms;
+      SS_TRY(time_whole_steps<T>(g, 4 * reps, &ms));
+      if (ms < best_step) {
+        best_step = ms;
+        bk = l;
+      }
+    }
+    g->tile_k = bk;
+  }
   std::lock_guard<std::mutex> lk(g_tile_mu);
   g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k, g->tile_x_ppb, g->lb};
   return SS_OK;

@@ -232,11 +232,13 @@ hipError_t launch_k(KArgs a, int mode, hipStream_t s, LaunchEvents ev) {
   constexpr int ESZ = (int)sizeof(C<T>);
   const int L = a.lines_per_block;
   if (!k_tile_ok(ESZ, NL, a.nlines, a.three_d != 0, L)) return hipErrorInvalidConfiguration;
+  // threads per line: NL/8, or NL/k_pts for the stepping form
   dim3 grid((unsigned)(a.nlines / L), (unsigned)a.nf), block((unsigned)(L * (NL / 8)));
+  dim3 block_hat((unsigned)(L * (NL / k_pts(ESZ, NL))));
   if (mode == 2) return launch_with(kfwd_kernel<T, NL>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
   if (mode == 1 && a.scheme == 1)
-    return launch_with(kpass_kernel<T, NL, true, 1>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
-  if (mode == 1) return launch_with(kpass_kernel<T, NL, true>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+    return launch_with(kpass_kernel<T, NL, true, 1>, grid, block_hat, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  if (mode == 1) return launch_with(kpass_kernel<T, NL, true>, grid, block_hat, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
   if (a.scheme != 0) return hipErrorInvalidValue;   // the three-transform form is ETD1 only
   return launch_with(kpass_kernel<T, NL, false>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
 }

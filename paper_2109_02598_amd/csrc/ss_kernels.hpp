@@ -85,14 +85,26 @@ constexpr int y_reg(int esz, int ny) {
 }
 constexpr int64_t y_lds(int esz, int ny, int lines) { return (int64_t)lines * y_reg(esz, ny) * esz; }
 constexpr int k_reg(int esz, int nl) { return padded_len_e(esz, nl); }
-// twiddle bases per thread of an nl-point transform (Twiddles<T, nl>::NW)
-constexpr int k_nw(int nl) {
-  return ((ilog2c(nl) + 2) / 3) > 1 ? ((ilog2c(nl) + 2) / 3) - 1 : 1;
+// twiddle bases per thread of an nl-point transform with p points per
+// thread (Twiddles<T, nl, p>::NW)
+constexpr int k_nw(int nl, int p = 8) {
+  return ((ilog2c(nl) + ilog2c(p) - 1) / ilog2c(p)) > 1 ? ((ilog2c(nl) + ilog2c(p) - 1) / ilog2c(p)) - 1 : 1;
 }
-// FP64 k-space blocks keep the twiddle bases in LDS after the line regions
-constexpr int64_t k_lds(int esz, int nl, int lines) {
-  return (int64_t)lines * (k_reg(esz, nl) + (esz == 16 ? (nl / 8) * k_nw(nl) : 0)) * esz;
+// points per thread of the stepping-form k-space pass.  Eight: with 16 the
+// FP64 pass spills even at 256 VGPRs, and the FP32 pass drops to two waves
+// per SIMD and ran 6% slower at 2048 points.
+constexpr int k_pts(int, int) { return 8; }
+// FP64 k-space blocks keep the twiddle bases of the stepping-form pass in
+// LDS after the line regions
+// (sized for 8 points per thread, the three-transform form's, or the
+// stepping form's count, whichever needs more)
+constexpr int64_t k_twl(int esz, int nl) {
+  return esz != 16 ? 0
+                   : ((nl / 8) * k_nw(nl, 8) > (nl / k_pts(esz, nl)) * k_nw(nl, k_pts(esz, nl))
+                          ? (nl / 8) * k_nw(nl, 8)
+                          : (nl / k_pts(esz, nl)) * k_nw(nl, k_pts(esz, nl)));
 }
+constexpr int64_t k_lds(int esz, int nl, int lines) { return (int64_t)lines * (k_reg(esz, nl) + k_twl(esz, nl)) * esz; }
 
 #ifndef SS_XPTS16
 #define SS_XPTS16 1
@@ -754,12 +766,12 @@ __device__ __forceinline__ P* kline_at(P* base, int64_t uo, uint32_t tb) {
 
 // Twiddle bases of a k-space thread: from registers (FP32) or from its LDS
 // entries (FP64).
-template <typename T, int NL>
-__device__ __forceinline__ Twiddles<T, NL> ktw(const Twiddles<T, NL>& tw, const C<T>* twl, int stride) {
+template <typename T, int NL, int P = 8>
+__device__ __forceinline__ Twiddles<T, NL, P> ktw(const Twiddles<T, NL, P>& tw, const C<T>* twl, int stride) {
   if constexpr (sizeof(T) == 8) {
-    Twiddles<T, NL> r;
+    Twiddles<T, NL, P> r;
 #pragma unroll
-    for (int i = 0; i < Twiddles<T, NL>::NW; ++i) r.w[i] = twl[i * stride];
+    for (int i = 0; i < Twiddles<T, NL, P>::NW; ++i) r.w[i] = twl[i * stride];
     return r;
   } else {
     return tw;
@@ -784,9 +796,9 @@ __device__ __forceinline__ void kline_slot(int slot, int J, int three_d, int& kx
   }
 }
 
-template <typename T, int NL>
+template <typename T, int NL, int P = 8>
 struct KCfg {
-  static constexpr int S = NL / 8;
+  static constexpr int S = NL / P;
   static constexpr int ESZ = (int)sizeof(C<T>);
   static constexpr int REG = k_reg(ESZ, NL);
 };
@@ -798,9 +810,9 @@ struct KCfg {
 // nonlinear term is transformed; U = A S^ + B N G^ is written back as the
 // new S^ and, inverse transformed, as the new T (two transforms per line;
 // the host passes a_scale = 1).
-template <typename T, int NL, bool HAT = false, int SCH = 0>
+template <typename T, int NL, bool HAT = false, int SCH = 0, int P = 8>
 __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>* lds) {
-  typedef KCfg<T, NL> K;
+  typedef KCfg<T, NL, P> K;
   constexpr int S = K::S, REG = K::REG;
   const int tid = threadIdx.x;
   const int ls = tid / S, t = tid - ls * S;
@@ -821,9 +833,14 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   const C<T>* gn = (const C<T>*)F.nonlin + lbase;
   C<T>* so = (C<T>*)(F.out ? F.out : F.state) + lbase;
 
-  C<T> ct[1][8], cg[1][8];
+  C<T> ct[1][P], cg[1][P];
+  // the three-transform form transforms the state first; the stepping
+  // form reads S^ only for the update, after the nonlinear term's
+  // transform (fewer live registers during it)
+  if constexpr (!HAT) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) ct[0][e] = *kline_at(st, kline_off(e * S, hx, lb), tb);
+    for (int e = 0; e < P; ++e) ct[0][e] = *kline_at(st, kline_off(e * S, hx, lb), tb);
+  }
   // one LDS region per line serves all three transforms in turn
   C<T>* x[1] = {lds + ls * REG};
   // FP64 parks the twiddle bases in LDS between the transforms (entry i of
@@ -831,16 +848,21 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   // a SIMD.  Each thread reads back only what it wrote.
   C<T>* const twl = lds + a.lines_per_block * REG + ls * S + t;
   const int twstride = a.lines_per_block * S;
-  static_assert(Twiddles<T, NL>::NW == k_nw(NL), "LDS twiddle table size");
-  const Twiddles<T, NL> tw = make_twiddles<T, NL>(t);
+  static_assert(Twiddles<T, NL, P>::NW == k_nw(NL, P), "LDS twiddle table size");
+  static_assert(sizeof(T) != 8 || (NL / P) * k_nw(NL, P) <= k_twl(16, NL), "LDS twiddle table size");
+  const Twiddles<T, NL, P> tw = make_twiddles<T, NL, P>(t);
   if constexpr (sizeof(T) == 8) {
 #pragma unroll
-    for (int i = 0; i < Twiddles<T, NL>::NW; ++i) twl[i * twstride] = tw.w[i];
+    for (int i = 0; i < Twiddles<T, NL, P>::NW; ++i) twl[i * twstride] = tw.w[i];
   }
-  if constexpr (!HAT) fft_lines<T, NL, -1, 1>(ct, x, t, ktw<T, NL>(tw, twl, twstride));
+  if constexpr (!HAT) fft_lines<T, NL, -1, 1, P>(ct, x, t, ktw<T, NL, P>(tw, twl, twstride));
 #pragma unroll
-  for (int e = 0; e < 8; ++e) cg[0][e] = *kline_at(gn, kline_off(e * S, hx, lb), tb);
-  fft_lines<T, NL, -1, 1>(cg, x, t, ktw<T, NL>(tw, twl, twstride));
+  for (int e = 0; e < P; ++e) cg[0][e] = *kline_at(gn, kline_off(e * S, hx, lb), tb);
+  fft_lines<T, NL, -1, 1, P>(cg, x, t, ktw<T, NL, P>(tw, twl, twstride));
+  if constexpr (HAT) {
+#pragma unroll
+    for (int e = 0; e < P; ++e) ct[0][e] = *kline_at(st, kline_off(e * S, hx, lb), tb);
+  }
 
   // wavenumbers: k_last from the position, k_mid from kyi (3D), k_x from kxi
   const T kxv = (T)kxi * (T)a.sx;
@@ -862,11 +884,11 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     const C<T>* xm = lds + mls * REG;
     const T kny = (T)(a.nx / 2) * (T)a.sx;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[0][pidx<T>(t + e * S)] = ct[0][e];
+    for (int e = 0; e < P; ++e) x[0][pidx<T>(t + e * S)] = ct[0][e];
     __syncthreads();
     if (packed) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < P; ++e) {
         __builtin_amdgcn_sched_barrier(0);
         const int p = t + e * S;
         const int m = p <= NL / 2 ? p : p - NL;
@@ -882,10 +904,10 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[0][pidx<T>(t + e * S)] = cg[0][e];
+    for (int e = 0; e < P; ++e) x[0][pidx<T>(t + e * S)] = cg[0][e];
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < P; ++e) {
       __builtin_amdgcn_sched_barrier(0);
       const int p = t + e * S;
       const int m = p <= NL / 2 ? p : p - NL;
@@ -911,7 +933,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     __syncthreads();
   } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < P; ++e) {
       __builtin_amdgcn_sched_barrier(0);
       const int p = t + e * S;
       const int m = p <= NL / 2 ? p : p - NL;
@@ -926,11 +948,11 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   if constexpr (HAT) {
     C<T>* sh = (C<T>*)F.shat + lbase;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) *kline_at(sh, kline_off(e * S, hx, lb), tb) = ct[0][e];
+    for (int e = 0; e < P; ++e) *kline_at(sh, kline_off(e * S, hx, lb), tb) = ct[0][e];
   }
-  fft_lines<T, NL, +1, 1>(ct, x, t, ktw<T, NL>(tw, twl, twstride));
+  fft_lines<T, NL, +1, 1, P>(ct, x, t, ktw<T, NL, P>(tw, twl, twstride));
 #pragma unroll
-  for (int e = 0; e < 8; ++e) *kline_at(so, kline_off(e * S, hx, lb), tb) = ct[0][e];
+  for (int e = 0; e < P; ++e) *kline_at(so, kline_off(e * S, hx, lb), tb) = ct[0][e];
 }
 
 // FP64: three waves per SIMD (168 VGPRs), except 128- and 256-point lines,
@@ -940,7 +962,8 @@ __global__ void __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? ((NL == 128 || NL == 256) ? 2 : 3) : SS_KWAVES)))
 kpass_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
-  kpass_body<T, NL, HAT, SCH>(a, blockIdx.x, blockIdx.y, reinterpret_cast<C<T>*>(ss_dyn_lds));
+  kpass_body<T, NL, HAT, SCH, HAT ? k_pts((int)sizeof(C<T>), NL) : 8>(a, blockIdx.x, blockIdx.y,
+                                                                      reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
 
 // S^ = FFT(T) / N_last along every line of field blockIdx.y (the stepping
