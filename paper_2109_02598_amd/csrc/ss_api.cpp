@@ -837,6 +837,27 @@ ss_status autotune_t(ss_grid g, int reps) {
       }
     }
     g->tile_k = bk;
+    // then the x pass's tiling, the same way
+    const int64_t rows = g->n[1] * g->n[2];
+    const int nx = (int)g->n[0];
+    best_step = 1e30f;
+    for (int r = 2; r <= 64; r *= 2)
+      for (int ppb : {0, 2, 4, 8}) {
+        if (!ss::x_tile_ok(esz, nx, g->nf, rows, r)) continue;
+        if (ppb && !ss::x_pp_ok(esz, nx, g->nf, rows, r)) continue;
+        if (ppb && rows / r < 2 * ppb) continue;
+        g->tile_x_step = r;
+        g->tile_x_ppb = ppb;
+        float ms;
+        SS_TRY(time_whole_steps<T>(g, 4 * reps, &ms));
+        if (ms < best_step) {
+          best_step = ms;
+          bx = r;
+          bppb = ppb;
+        }
+      }
+    g->tile_x_step = bx;
+    g->tile_x_ppb = bppb;
   }
   std::lock_guard<std::mutex> lk(g_tile_mu);
   g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k, g->tile_x_ppb, g->lb};
