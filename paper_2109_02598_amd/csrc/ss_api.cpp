@@ -283,9 +283,14 @@ bool blk_ok(ss_grid g, int64_t B) {
   if (g->ndim == 3 && B > g->n[2]) return false;
   return true;
 }
+// The k-space pass reads a line in runs of B elements (one run per row
+// block).  Runs shorter than a 128-byte L2 line leave the rest of the line
+// to the neighbouring kx line, which usually runs on another XCD: each L2
+// then fetches the whole line and the fabric carries up to twice the bytes
+// (hidden by the Infinity Cache in time, not in traffic).  The default and
+// the tuner's candidates therefore fill whole lines where the grid allows.
 int64_t blk_default(ss_grid g) {
-  // 64-byte chunks along the k-space lines
-  int64_t B = 64 / esz_of(g);
+  int64_t B = 128 / esz_of(g);
   while (!blk_ok(g, B)) B /= 2;
   return B;
 }
@@ -781,6 +786,18 @@ ss_status time_whole_steps(ss_grid g, int n, float* ms) {
   return st;
 }
 
+// Whole-step time of the current tiling for the tuner: the better of two
+// runs of 10*reps steps (candidates differ by 1-2%, about the spread of
+// one short run).
+template <typename T>
+ss_status tune_steps(ss_grid g, int reps, float* ms) {
+  float a, b;
+  SS_TRY(time_whole_steps<T>(g, 10 * reps, &a));
+  SS_TRY(time_whole_steps<T>(g, 10 * reps, &b));
+  *ms = std::min(a, b);
+  return SS_OK;
+}
+
 template <typename T>
 ss_status autotune_t(ss_grid g, int reps) {
   // The row block of the layout can change only while no field is stored.
@@ -788,8 +805,8 @@ ss_status autotune_t(ss_grid g, int reps) {
   std::vector<int> lbs;
   if (free_layout) {
     const int64_t rows = g->n[1] * g->n[2];
-    for (int64_t B : {blk_default(g), rows, (int64_t)16, (int64_t)8, (int64_t)4, (int64_t)2}) {
-      if (!blk_ok(g, B)) continue;
+    for (int64_t B : {blk_default(g), rows, (int64_t)64, (int64_t)32, (int64_t)16, (int64_t)8}) {
+      if (!blk_ok(g, B) || B < blk_default(g)) continue;
       const int lb = ilog2i(B);
       if (std::find(lbs.begin(), lbs.end(), lb) == lbs.end()) lbs.push_back(lb);
     }
@@ -805,7 +822,7 @@ ss_status autotune_t(ss_grid g, int reps) {
     SS_TRY(autotune_tiles<T>(g, reps, &tot));
     // layouts compared by whole steps: the passes' per-launch times do not
     // see how one pass's writes meet the next one's reads
-    if (lbs.size() > 1) SS_TRY(time_whole_steps<T>(g, 4 * reps, &tot));
+    if (lbs.size() > 1) SS_TRY(tune_steps<T>(g, reps, &tot));
     if (tot < best) {
       best = tot;
       best_lb = lb;
@@ -830,7 +847,7 @@ ss_status autotune_t(ss_grid g, int reps) {
       if (!ss::k_tile_ok(esz, nlast(g), nlines_k(g), g->ndim == 3, l)) continue;
       g->tile_k = l;
       float ms;
-      SS_TRY(time_whole_steps<T>(g, 4 * reps, &ms));
+      SS_TRY(tune_steps<T>(g, reps, &ms));
       if (ms < best_step) {
         best_step = ms;
         bk = l;
@@ -849,7 +866,7 @@ ss_status autotune_t(ss_grid g, int reps) {
         g->tile_x_step = r;
         g->tile_x_ppb = ppb;
         float ms;
-        SS_TRY(time_whole_steps<T>(g, 4 * reps, &ms));
+        SS_TRY(tune_steps<T>(g, reps, &ms));
         if (ms < best_step) {
           best_step = ms;
           bx = r;
