@@ -440,7 +440,7 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic (seeded SplitMix64 uniform noise)",
-        "config": {"workload": w.name, "model": w.model, "grid": list(w.n), "dx": list(w.dx),
+        "config": {"workload": w.name, "equation": w.model, "grid": list(w.n), "dx": list(w.dx),
                    "dt": w.dt, "coef": list(w.coef), "mass_log": True, "parallelism": "1 GPU"},
         "roofline": roof,
         "other_dtype": {"dtype": other, "value": round(w.cells * args.steps / (ms2 * 1e-3), 1),
