@@ -94,6 +94,7 @@ struct ss_grid_s {
   // tiling of each pass (rows or lines per workgroup); 0 = not chosen yet
   int tile_x_step = 0, tile_x_io = 0, tile_y = 0, tile_k = 0;
   int tile_x_ppb = 0;   // x pass tiles per block (> 1: persistent, prefetching)
+  bool step_inplace = true;   // stepping-form passes in place on the state (else G in scratch)
   int lb = -1;          // log2 of the row block B of the spectral layout (-1: not chosen)
 
   // reverse mode: caller-owned workspace with checkpoints and segment
@@ -258,6 +259,7 @@ ss::LaunchEvents take_events(PassTimer* pt, int kind) {
 typedef std::tuple<int, int, int64_t, int64_t, int64_t, int> TileKey;  // ndim, esz, nx, ny, nz, nf
 struct Tiles {
   int x_step, y, k, x_ppb, lb;
+  int inplace;   // -1: not chosen
 };
 std::mutex g_tile_mu;
 std::map<TileKey, Tiles> g_tile_cache;
@@ -299,7 +301,7 @@ void ensure_tiles(ss_grid g) {
   const int esz = esz_of(g);
   if (!g->tile_x_io) g->tile_x_io = ss::x_tile_default(esz, (int)g->n[0], 1, g->n[1] * g->n[2]);
   if (g->lb >= 0 && g->tile_x_step && g->tile_k && (g->ndim == 2 || g->tile_y)) return;
-  Tiles t = {0, 0, 0, 0, -1};
+  Tiles t = {0, 0, 0, 0, -1, -1};
   {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     auto it = g_tile_cache.find(tile_key(g));
@@ -312,6 +314,7 @@ void ensure_tiles(ss_grid g) {
   }
   if (!g->tile_k) g->tile_k = t.k ? t.k : ss::k_tile_default(esz, nlast(g), nlines_k(g), g->ndim == 3);
   if (g->ndim == 3 && !g->tile_y) g->tile_y = t.y ? t.y : ss::y_tile_default(esz, (int)g->n[1], g->n[2]);
+  if (t.inplace >= 0) g->step_inplace = t.inplace != 0;
 }
 
 // Coefficients of the x pass's pointwise terms (fixed models) or their
@@ -371,14 +374,14 @@ ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double sca
 // out; mode 0: T and G in, T out (three transforms); mode 2: refresh S^
 // from T.
 template <typename T>
-ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr, int mode = 1) {
+ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr, int mode = 1, bool inplace = false) {
   ss::KArgs a;
   memset(&a, 0, sizeof(a));
   const bool three = g->ndim == 3;
   for (int f = 0; f < g->nf; ++f) {
     a.fld[f] = g->kf[f];
     a.fld[f].state = g->state[f];
-    a.fld[f].nonlin = g->scratch[f];
+    a.fld[f].nonlin = inplace ? g->state[f] : g->scratch[f];
     a.fld[f].shat = g->shat[f];
   }
   a.J = three ? (int)g->n[1] : 1;
@@ -422,16 +425,23 @@ ss_status ensure_shat(ss_grid g) {
 // so both follow the same arithmetic).
 template <typename T>
 ss_status step_once(ss_grid g, PassTimer* pt, bool hat = true) {
+  // The stepping form runs every pass in place on the state arrays (each
+  // workgroup reads its tile or lines whole before writing them; the
+  // k-space pass writes T over G): a step touches the state and its
+  // spectrum only, half the arrays, which keeps more of them in the
+  // Infinity Cache.  The three-transform form reads T and G together and
+  // keeps G in the scratch arrays.
+  const bool inplace = hat && g->step_inplace;
+  void** G = inplace ? g->state : g->scratch;
   if (g->ndim == 2) {
-    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], g->scratch[0],
-                           g->scratch[1], nullptr, nullptr, 1.0, pt));
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], G[0], G[1], nullptr, nullptr,
+                           1.0, pt));
   } else {
-    for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, +1, g->state[f], g->scratch[f], 1.0, pt));
-    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->scratch[0], g->scratch[1], g->scratch[0],
-                           g->scratch[1], nullptr, nullptr, 1.0, pt));
-    for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, -1, g->scratch[f], g->scratch[f], 1.0, pt));
+    for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, +1, g->state[f], G[f], 1.0, pt));
+    SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, G[0], G[1], G[0], G[1], nullptr, nullptr, 1.0, pt));
+    for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, -1, G[f], G[f], 1.0, pt));
   }
-  SS_TRY(launch_kpass<T>(g, pt, hat ? 1 : 0));
+  SS_TRY(launch_kpass<T>(g, pt, hat ? 1 : 0, inplace));
   if (!hat) g->shat_valid = false;
   g->log_count++;
   return SS_OK;
@@ -629,7 +639,10 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
   const int nx = (int)g->n[0];
   const int64_t rows = g->n[1] * g->n[2];
   float sum = 0.f;
-  // x pass (STEP): reads the state, writes the scratch arrays only
+  // while no field is stored the passes run on the step's own arrays (all
+  // in place on the state); otherwise the fields are left alone
+  const bool free_arrays = !g->field_set[0] && !g->field_set[1];
+  // x pass (STEP): reads the state, writes it (free) or the scratch arrays
   {
     int best_r = 0, best_ppb = 0;
     float best = 1e30f;
@@ -643,8 +656,8 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
           memset(&a, 0, sizeof(a));
           a.spec_in[0] = g->state[0];
           a.spec_in[1] = g->state[1];
-          a.spec_out[0] = g->scratch[0];
-          a.spec_out[1] = g->scratch[1];
+          a.spec_out[0] = free_arrays ? g->state[0] : g->scratch[0];
+          a.spec_out[1] = free_arrays ? g->state[1] : g->scratch[1];
           a.rows = rows;
           a.nz = (int)g->n[2];
           a.ny = (int)g->n[1];
@@ -669,10 +682,9 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
     sum += best;
   }
   // k-space pass: while no field is stored, on the step's own arrays (the
-  // traffic the step sees: S^, G -> S^, T); otherwise on the scratch (as
-  // S^) and staging arrays, so the fields are untouched
+  // traffic the step sees: S^, G -> S^, T over G); otherwise on the scratch
+  // (as S^) and staging arrays, so the fields are untouched
   {
-    const bool free_arrays = !g->field_set[0] && !g->field_set[1];
     const int nl = nlast(g);
     const int64_t nlines = nlines_k(g);
     int best_l = 0;
@@ -686,10 +698,10 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
         // per thread in place) arrays: the fields are untouched
         for (int f = 0; f < g->nf; ++f) {
           a.fld[f] = g->kf[f];
-          if (free_arrays) {          // the step's own array roles
+          if (free_arrays) {          // the step's own array roles (in place on the state)
             a.fld[f].shat = g->shat[f];
             a.fld[f].state = g->state[f];
-            a.fld[f].nonlin = g->scratch[f];
+            a.fld[f].nonlin = g->state[f];
           } else {
             a.fld[f].shat = g->scratch[f];
             a.fld[f].state = g->staging;
@@ -731,8 +743,8 @@ ss_status autotune_tiles(ss_grid g, int reps, float* total) {
       auto launch = [&](ss::LaunchEvents ev) {
         ss::YArgs a;
         memset(&a, 0, sizeof(a));
-        a.in = g->scratch[0];
-        a.out = g->scratch[0];
+        a.in = free_arrays ? g->state[0] : g->scratch[0];
+        a.out = free_arrays ? g->state[0] : g->scratch[0];
         a.ny = (int)g->n[1];
         a.nz = (int)g->n[2];
         a.hx = nx / 2;
@@ -838,6 +850,15 @@ ss_status autotune_t(ss_grid g, int reps) {
   g->tile_k = bk;
   g->tile_y = by;
   if (free_layout) {
+    // whether the passes run in place on the state: fewer arrays in the
+    // caches, against the in-place x pass's access pattern (slower for
+    // FP32 in 2D)
+    float t_in, t_out;
+    g->step_inplace = true;
+    SS_TRY(tune_steps<T>(g, reps, &t_in));
+    g->step_inplace = false;
+    SS_TRY(tune_steps<T>(g, reps, &t_out));
+    g->step_inplace = t_in <= t_out;
     // the dominant pass's tiling, settled by whole steps as well: single
     // launches repeated on the same arrays can rank tilings differently
     // from steps once the arrays outgrow the Infinity Cache
@@ -877,7 +898,8 @@ ss_status autotune_t(ss_grid g, int reps) {
     g->tile_x_ppb = bppb;
   }
   std::lock_guard<std::mutex> lk(g_tile_mu);
-  g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k, g->tile_x_ppb, g->lb};
+  g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k, g->tile_x_ppb, g->lb,
+                                     g->step_inplace ? 1 : 0};
   return SS_OK;
 }
 
@@ -1239,12 +1261,11 @@ bool finite_all(const double* v, int n) {
 namespace {
 
 // Launch one pass of the current tiling for timing.  While no field is
-// stored, every pass runs on the step's own arrays (the traffic a step
-// sees).  Otherwise in a form that leaves the fields alone: the x pass
-// reads the state and writes the scratch arrays (as in a step); the
-// k-space pass runs on the scratch arrays with the staging array as
-// nonlinear term and output, in place; the y passes run in place on
-// scratch 0.  The in-place forms touch fewer distinct arrays than a step,
+// stored, every pass runs as in a step, in place on the state arrays.
+// Otherwise in a form that leaves the fields alone: the x pass reads the
+// state and writes the scratch arrays; the k-space pass runs on the
+// scratch arrays with the staging array as nonlinear term and output, in
+// place; the y passes run in place on scratch 0.  The in-place forms touch fewer distinct arrays than a step,
 // so where the step's arrays outgrow the Infinity Cache they can read fast.
 template <typename T>
 ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
@@ -1256,8 +1277,8 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
     memset(&a, 0, sizeof(a));
     a.spec_in[0] = g->state[0];
     a.spec_in[1] = g->state[1];
-    a.spec_out[0] = g->scratch[0];
-    a.spec_out[1] = g->scratch[1];
+    a.spec_out[0] = free_arrays ? g->state[0] : g->scratch[0];
+    a.spec_out[1] = free_arrays ? g->state[1] : g->scratch[1];
     a.rows = rows;
     a.nz = (int)g->n[2];
     a.ny = (int)g->n[1];
@@ -1278,7 +1299,7 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
       if (free_arrays) {
         a.fld[f].shat = g->shat[f];
         a.fld[f].state = g->state[f];
-        a.fld[f].nonlin = g->scratch[f];
+        a.fld[f].nonlin = g->state[f];
       } else {
         a.fld[f].shat = g->scratch[f];
         a.fld[f].state = g->staging;
@@ -1305,8 +1326,8 @@ ss_status launch_timed_pass(ss_grid g, int pass, ss::LaunchEvents ev) {
   if (g->ndim == 3 && (pass == PASS_YINV || pass == PASS_YFWD)) {
     ss::YArgs a;
     memset(&a, 0, sizeof(a));
-    a.in = (free_arrays && pass == PASS_YINV) ? g->state[0] : g->scratch[0];   // a step: state -> scratch
-    a.out = g->scratch[0];
+    a.in = free_arrays ? g->state[0] : g->scratch[0];   // a step: in place on the state
+    a.out = free_arrays ? g->state[0] : g->scratch[0];
     a.ny = (int)g->n[1];
     a.nz = (int)g->n[2];
     a.scale = 1.0;
