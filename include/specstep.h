@@ -226,8 +226,11 @@ ss_status ss_time_pass(ss_grid g, int pass, int nlaunch, double* mean_ms);
  * its workgroup).  The choice is also remembered for later grids of the
  * same shape, dtype and model field count.  Timing as ss_time_pass: while
  * no field is stored the passes run on the step's own arrays (best called
- * then); afterwards only the scratch and staging parts of the workspace
- * are written and the fields are untouched.
+ * then), layouts and the dominant tilings are compared by timing whole
+ * steps, and so is whether a step's passes run in place on the state
+ * arrays or write the nonlinear term to the scratch arrays (results are
+ * bitwise the same); afterwards only the scratch and staging parts of the
+ * workspace are written and the fields are untouched.
  * Synchronises the stream.  Errors: SS_ERR_STATE (no model/workspace),
  * SS_ERR_ARG (reps outside [1, 1000]), SS_ERR_DEVICE. */
 ss_status ss_autotune(ss_grid g, int reps);
