@@ -969,8 +969,10 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     if (L < 1 || !ss::k_tile_ok(esz, ny, nx / 2, false, L)) return false;
     ss::BatchMember m;
     memset(&m, 0, sizeof(m));
+    // in place on the state, as the single-grid step: two arrays per member
+    // (T, S^) keep more of the batch in the Infinity Cache
     m.x.spec_in[0] = g->state[0];
-    m.x.spec_out[0] = g->scratch[0];
+    m.x.spec_out[0] = g->state[0];
     m.x.rows = ny;
     m.x.nz = 1;
     m.x.ny = ny;
@@ -982,7 +984,7 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     for (int i = 0; i < 5; ++i) m.x.p[i] = g->p[i];
     m.k.fld[0] = g->kf[0];
     m.k.fld[0].state = g->state[0];
-    m.k.fld[0].nonlin = g->scratch[0];
+    m.k.fld[0].nonlin = g->state[0];
     m.k.fld[0].shat = g->shat[0];
     m.k.nlines = nx / 2;
     m.k.J = 1;
@@ -1008,8 +1010,10 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     if (lx > lds_x) lds_x = lx;
     if (lk > lds_k) lds_k = lk;
     tab.push_back(m);
-    // tuning copy: the k pass runs on the scratch (as S^) and staging (G in,
-    // T out) arrays
+    // tuning copy, which leaves the fields alone: the x pass writes the
+    // scratch array; the k pass runs on the scratch (as S^) and staging (G
+    // in, T out) arrays
+    m.x.spec_out[0] = g->scratch[0];
     m.k.fld[0].shat = g->scratch[0];
     m.k.fld[0].state = g->staging;
     m.k.fld[0].nonlin = g->staging;
