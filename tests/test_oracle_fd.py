@@ -28,12 +28,18 @@ def symbol(stencil, theta):
     if stencil == 19:
         pairs = c[0] * c[1] + c[0] * c[2] + c[1] * c[2]
         return (2 * 2 * sum(c) + 4 * pairs - 24) / 6.0
+    if stencil == 27:
+        pairs = c[0] * c[1] + c[0] * c[2] + c[1] * c[2]
+        return (14 * 2 * sum(c) + 3 * 4 * pairs + 8 * c[0] * c[1] * c[2] - 128) / 30.0
+    if stencil == 4:
+        return sum((-2 * np.cos(2 * t) + 32 * np.cos(t) - 30) / 12.0 for t in theta)
     raise ValueError(stencil)
 
 
 @pytest.mark.parametrize("stencil,shape,m", [
     (5, (16, 32), (3, 5)), (9, (16, 32), (3, 5)), (9, (32, 32), (7, 7)),
     (7, (8, 16, 32), (1, 3, 5)), (19, (8, 16, 32), (1, 3, 5)), (19, (16, 16, 16), (4, 4, 4)),
+    (27, (8, 16, 32), (1, 3, 5)), (27, (16, 16, 16), (4, 4, 4)), (4, (16, 32), (3, 5)), (4, (8, 16, 32), (1, 3, 5)),
 ])
 def test_stencil_symbol_on_plane_waves(stencil, shape, m):
     f = plane(shape, m)
@@ -42,8 +48,9 @@ def test_stencil_symbol_on_plane_waves(stencil, shape, m):
     np.testing.assert_allclose(got, symbol(stencil, theta) * f, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("stencil,d", [(5, 2), (9, 2), (7, 3), (19, 3)])
-def test_second_order_convergence(stencil, d):
+@pytest.mark.parametrize("stencil,d,order", [(5, 2, 2), (9, 2, 2), (7, 3, 2), (19, 3, 2), (27, 3, 2), (4, 2, 4),
+                                             (4, 3, 4)])
+def test_convergence_order(stencil, d, order):
     errs = []
     for n in (16, 32):
         L = 2 * np.pi
@@ -60,7 +67,8 @@ def test_second_order_convergence(stencil, d):
         got = fd.laplacian(f, (h,) * d, stencil)
         errs.append(np.max(np.abs(got - exact)))
     ratio = errs[0] / errs[1]
-    assert 3.8 < ratio < 4.2, (stencil, errs)
+    want = 2.0 ** order
+    assert 0.95 * want < ratio < 1.05 * want, (stencil, errs)
 
 
 def test_isotropy_of_the_leading_error():
@@ -84,11 +92,14 @@ def test_isotropy_of_the_leading_error():
     assert max(e) / min(e) - 1 < 0.05
     e7 = [err(7, m, 3) for m in ((7, 1, 0), (5, 5, 0), (3, 4, 5))]
     assert max(e7) / min(e7) > 1.5
+    e27 = [err(27, m, 3) for m in ((7, 1, 0), (5, 5, 0), (3, 4, 5))]
+    assert max(e27) / min(e27) - 1 < 0.05
 
 
 @pytest.mark.parametrize("model,d,stencil,ns", [("allen_cahn", 2, 9, (32, 64)), ("cahn_hilliard", 2, 9, (32, 64)),
                                                 ("gray_scott", 2, 9, (32, 64)), ("allen_cahn", 3, 19, (32, 64)),
-                                                ("pfc", 3, 19, (64, 128))])
+                                                ("pfc", 3, 19, (64, 128)), ("cahn_hilliard", 3, 27, (32, 64)),
+                                                ("allen_cahn", 2, 4, (32, 64)), ("gray_scott", 3, 4, (32, 64))])
 def test_isotropic_euler_converges_with_the_axiswise_one(model, d, stencil, ns):
     """One forward-Euler increment with either stencil family, on a smooth
     field at two resolutions: the two agree to second order in h (PFC's
