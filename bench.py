@@ -228,7 +228,7 @@ def run_euler(w, dtype, steps=500):
     out = {"workload": "%s, forward Euler, %s, %d steps (dt 0.01)" % (w.name, dtype, steps)}
     esz = 8 if dtype == "f64" else 4
     nfa = {"allen_cahn": 2, "cahn_hilliard": 5, "pfc": 8, "gray_scott": 4, "model_c": 6}[w.model]
-    for st in ((0, 9) if len(w.n) == 2 else (0, 19)):
+    for st in ((0, 9, 4) if len(w.n) == 2 else (0, 19, 27, 4)):
         g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=0.01,
                           solver="euler", stencil=st)
         for i, f in enumerate(w.fields):
@@ -244,7 +244,7 @@ def run_euler(w, dtype, steps=500):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         g.close()
-        name = "axis-wise" if st == 0 else "isotropic %d-point" % st
+        name = {0: "axis-wise", 4: "fourth-order axis-wise"}.get(st, "isotropic %d-point" % st)
         out[name] = {"value": round(w.cells * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
                      "us_per_step": round(ms * 1e3 / steps, 2),
                      "achieved_GBs": round(nfa * w.cells * esz * steps / (ms * 1e-3) / 1e9, 1)}

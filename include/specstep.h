@@ -151,7 +151,11 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
  *   stencil 0 (or 5 in 2D, 7 in 3D): axis-wise central differences,
  *   sum_a (f[-1] - 2 f + f[+1]) / dx_a^2;  stencil 9 (2D) or 19 (3D): the
  *   isotropic stencils (4 edge + 1 corner - 20 centre) / (6 h^2) and
- *   (2 face + 1 edge - 24 centre) / (6 h^2), which need equal spacings.
+ *   (2 face + 1 edge - 24 centre) / (6 h^2), which need equal spacings;
+ *   stencil 27 (3D): the isotropic (14 face + 3 edge + 1 corner
+ *   - 128 centre) / (30 h^2), equal spacings; stencil 4: the fourth-order
+ *   axis-wise stencil (fourth-order family, 9 points in 2D, 13 in 3D),
+ *   sum_a (-f[-2] + 16 f[-1] - 30 f + 16 f[+1] - f[+2]) / (12 dx_a^2).
  *   Explicit: stable only for dt below the stencil's limit (the caller's
  *   choice).  The fields live in real space; ss_set_field / ss_get_field /
  *   ss_step_n work as with the spectral solver; the mass log is not

@@ -462,6 +462,7 @@ ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* o
   a.lxy = ilog2i(g->n[0] * g->n[1]);
   for (int d = 0; d < 3; ++d) a.ih2[d] = d < g->ndim ? 1.0 / (g->dx[d] * g->dx[d]) : 0.0;
   a.i6h2 = 1.0 / (6.0 * g->dx[0] * g->dx[0]);
+  a.i30h2 = 1.0 / (30.0 * g->dx[0] * g->dx[0]);
   a.dt = g->dt;
   a.op = op;
   if (op == ss::FD_UPD) {
@@ -469,7 +470,7 @@ ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* o
   } else {
     for (int i = 0; i < g->ncoef && i < 6; ++i) a.p[i] = g->coef[i];
   }
-  const int st = (g->stencil == 9 || g->stencil == 19) ? g->stencil : 0;
+  const int st = (g->stencil == 9 || g->stencil == 19 || g->stencil == 27 || g->stencil == 4) ? g->stencil : 0;
   hipError_t e = g->dtype == SS_F64 ? ss::run_fd<double>(g->ndim, st, a, g->stream)
                                     : ss::run_fd<float>(g->ndim, st, a, g->stream);
   return hip_check(e, "finite-difference launch");
@@ -1527,9 +1528,10 @@ ss_status ss_set_solver(ss_grid g, int solver, int stencil) {
   if (solver == 1 && g->has_model && g->model == SS_EQUATIONS)
     return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the finite-difference solver takes the fixed models");
   if (solver == 1) {
-    const bool ok = stencil == 0 || (g->ndim == 2 ? (stencil == 5 || stencil == 9) : (stencil == 7 || stencil == 19));
+    const bool ok = stencil == 0 || stencil == 4 ||
+                    (g->ndim == 2 ? (stencil == 5 || stencil == 9) : (stencil == 7 || stencil == 19 || stencil == 27));
     if (!ok) return fail(SS_ERR_ARG, "ss_set_solver: stencil %d is not available in %dD", stencil, g->ndim);
-    if (stencil == 9 || stencil == 19)
+    if (stencil == 9 || stencil == 19 || stencil == 27)
       for (int d = 1; d < g->ndim; ++d)
         if (std::fabs(g->dx[d] - g->dx[0]) > 1e-12 * g->dx[0])
           return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the isotropic stencil needs equal spacings");

@@ -291,6 +291,9 @@ hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
   if (dim == 2 && stencil == 9) return launch_with(fd_kernel<T, 2, 9>, grid, block, 0, s, LaunchEvents(), a);
   if (dim == 3 && stencil == 0) return launch_with(fd_kernel<T, 3, 0>, grid, block, 0, s, LaunchEvents(), a);
   if (dim == 3 && stencil == 19) return launch_with(fd_kernel<T, 3, 19>, grid, block, 0, s, LaunchEvents(), a);
+  if (dim == 3 && stencil == 27) return launch_with(fd_kernel<T, 3, 27>, grid, block, 0, s, LaunchEvents(), a);
+  if (dim == 2 && stencil == 4) return launch_with(fd_kernel<T, 2, 4>, grid, block, 0, s, LaunchEvents(), a);
+  if (dim == 3 && stencil == 4) return launch_with(fd_kernel<T, 3, 4>, grid, block, 0, s, LaunchEvents(), a);
   return hipErrorInvalidValue;
 }
 

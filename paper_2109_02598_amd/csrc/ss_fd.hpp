@@ -6,7 +6,12 @@
 //           sum over axes of (f[-1] - 2 f + f[+1]) / h_a^2;
 //   ST = 9  2D isotropic: (4 sum(edge neighbours) + sum(corners) - 20 f) / (6 h^2);
 //   ST = 19 3D isotropic: (2 sum(face neighbours) + sum(edge neighbours)
-//           - 24 f) / (6 h^2)   (equal spacing on every axis).
+//           - 24 f) / (6 h^2)   (equal spacing on every axis);
+//   ST = 27 3D isotropic: (14 sum(faces) + 3 sum(edges) + sum(corners)
+//           - 128 f) / (30 h^2) (equal spacing);
+//   ST = 4  fourth-order axis-wise (the fourth-order family; 9 points in
+//           2D, 13 in 3D): sum over axes of
+//           (-f[-2] + 16 f[-1] - 30 f + 16 f[+1] - f[+2]) / (12 h_a^2).
 // The leading error of the isotropic stencils depends on |k| only.
 //
 // One launch applies one operation at every cell (thread per cell, x
@@ -36,7 +41,8 @@ struct FDArgs {
   int64_t nx, ny, nz;        // nz = 1 in 2D
   int lx, lxy;               // log2(nx), log2(nx * ny)
   double ih2[3];             // 1 / h_a^2 (x, y, z) for the axis-wise stencil
-  double i6h2;               // 1 / (6 h^2) for the isotropic stencils
+  double i6h2;               // 1 / (6 h^2) for the 9- and 19-point stencils
+  double i30h2;              // 1 / (30 h^2) for the 27-point stencil
   double dt;
   double p[6];               // operation coefficients
   int op;
@@ -54,6 +60,12 @@ __device__ __forceinline__ T fd_lap(const T* __restrict__ f, int64_t x, int64_t 
           (at(0, -1, 0) + at(0, 1, 0) - (T)2 * c) * (T)a.ih2[1];
     if constexpr (DIM == 3) s += (at(0, 0, -1) + at(0, 0, 1) - (T)2 * c) * (T)a.ih2[2];
     return s;
+  } else if constexpr (ST == 4) {
+    T s = (-(at(-2, 0, 0) + at(2, 0, 0)) + (T)16 * (at(-1, 0, 0) + at(1, 0, 0)) - (T)30 * c) * (T)a.ih2[0] +
+          (-(at(0, -2, 0) + at(0, 2, 0)) + (T)16 * (at(0, -1, 0) + at(0, 1, 0)) - (T)30 * c) * (T)a.ih2[1];
+    if constexpr (DIM == 3)
+      s += (-(at(0, 0, -2) + at(0, 0, 2)) + (T)16 * (at(0, 0, -1) + at(0, 0, 1)) - (T)30 * c) * (T)a.ih2[2];
+    return s * ((T)1 / (T)12);
   } else if constexpr (ST == 9) {
     const T edge = at(-1, 0, 0) + at(1, 0, 0) + at(0, -1, 0) + at(0, 1, 0);
     const T corner = at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0);
@@ -63,7 +75,13 @@ __device__ __forceinline__ T fd_lap(const T* __restrict__ f, int64_t x, int64_t 
     const T edge = at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0) +
                    at(-1, 0, -1) + at(1, 0, -1) + at(-1, 0, 1) + at(1, 0, 1) +
                    at(0, -1, -1) + at(0, 1, -1) + at(0, -1, 1) + at(0, 1, 1);
-    return ((T)2 * face + edge - (T)24 * c) * (T)a.i6h2;
+    if constexpr (ST == 19) {
+      return ((T)2 * face + edge - (T)24 * c) * (T)a.i6h2;
+    } else {   // 27
+      const T corner = at(-1, -1, -1) + at(1, -1, -1) + at(-1, 1, -1) + at(1, 1, -1) +
+                       at(-1, -1, 1) + at(1, -1, 1) + at(-1, 1, 1) + at(1, 1, 1);
+      return ((T)14 * face + (T)3 * edge + corner - (T)128 * c) * (T)a.i30h2;
+    }
   }
 }
 

@@ -30,21 +30,25 @@ def gpu_euler(model, n, dx, dt, steps, fields, dtype, stencil):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc", "gray_scott", "model_c"])
-@pytest.mark.parametrize("n,stencil", [((64, 32), 0), ((32, 64), 9), ((16, 8, 32), 0), ((16, 16, 16), 19)])
+@pytest.mark.parametrize("n,stencil", [((64, 32), 0), ((32, 64), 9), ((16, 8, 32), 0), ((16, 16, 16), 19),
+                                       ((16, 16, 16), 27), ((32, 64), 4), ((16, 8, 32), 4)])
 def test_euler_vs_oracle(model, n, stencil, dtype):
     dx = (1.0,) * len(n)
     steps = 20
+    # the fourth-order stencil's largest eigenvalue is 4/3 of the second-order one's
+    dt = DT[model] * (0.5 if stencil == 4 else 1.0)
     fields = synth_fields(model, n, dx, 500 + len(n))
-    got = gpu_euler(model, n, dx, DT[model], steps, [f.astype(np.float32) if dtype == "f32" else f for f in fields],
+    got = gpu_euler(model, n, dx, dt, steps, [f.astype(np.float32) if dtype == "f32" else f for f in fields],
                     dtype, stencil)
-    ref = fd_euler.euler_n(as_input(fields, dtype), model, COEF_FD[model], DT[model], dx, steps, stencil)
+    ref = fd_euler.euler_n(as_input(fields, dtype), model, COEF_FD[model], dt, dx, steps, stencil)
     for a, b in zip(got, ref):
         e = rel_l2(a, b)
         say(model, n, stencil, dtype, "rel_l2 %.3e" % e)
         assert e <= TOL[dtype]
 
 
-@pytest.mark.parametrize("stencil,n", [(0, (128, 64)), (9, (64, 64)), (19, (32, 32, 32))])
+@pytest.mark.parametrize("stencil,n", [(0, (128, 64)), (9, (64, 64)), (19, (32, 32, 32)), (27, (32, 32, 32)),
+                                       (4, (64, 128))])
 def test_euler_cahn_hilliard_conserves_mass(stencil, n):
     """The update is dt M L(mu), and every stencil's weights sum to zero on a
     periodic grid: the field's sum is conserved to rounding."""
@@ -61,6 +65,8 @@ def test_solver_choice_errors():
     g = specstep.Grid((32, 32), (1.0, 1.0), dtype="f64", model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1)
     with pytest.raises(specstep.SpecStepError):
         specstep.ss_set_solver(g.h, 1, 19)       # 19 points is 3D
+    with pytest.raises(specstep.SpecStepError):
+        specstep.ss_set_solver(g.h, 1, 27)       # 27 points is 3D
     with pytest.raises(specstep.SpecStepError):
         specstep.ss_set_solver(g.h, 2, 0)        # unknown solver
     with pytest.raises(specstep.SpecStepError):
