@@ -301,6 +301,28 @@ def run_equations(w, dtype, steps=300):
     return out
 
 
+def run_others(skip, steps=200):
+    """The other workloads of the benchmark set (PFC 256^3, GS 512^2, AC
+    128^2), both precisions, 200 timed steps each: cell-updates/s and the
+    roofline of each one's dominant kernel."""
+    out = {}
+    for name in ("pfc256", "gs512", "ac128"):
+        if name == skip:
+            continue
+        w = workloads()[name]()
+        res = {"workload": w.name}
+        for dt in ("f64", "f32"):
+            ms, _, prof, _ = run_gpu(w, dt, steps, 20, 50)
+            prof.pop("structure_factor", None)
+            r = roofline(w, dt, prof, load_traffic(name, dt))
+            res[dt] = {"value": round(w.cells * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
+                       "ms_per_step": round(ms / steps, 5),
+                       "roofline": {k: r[k] for k in ("kernel", "achieved", "frac", "traffic", "mean_launch_us",
+                                                      "tiles")}}
+        out[name] = res
+    return out
+
+
 def roofline(w, dtype, prof, traffic_rec):
     """Roofline of the dominant kernel: algorithmic bytes per launch over its
     mean launch duration inside steps (HIP events around every launch of
@@ -365,6 +387,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-euler", action="store_true", help="skip the finite-difference solver timing")
     ap.add_argument("--no-equations", action="store_true", help="skip the run-time equations timing")
+    ap.add_argument("--no-others", action="store_true", help="skip the other workloads (PFC 256^3, GS, AC)")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (for scaling "
@@ -423,6 +446,10 @@ def main():
     if w.model in MODEL_TEXT and not args.no_equations:
         print("bench: equations read at run time", file=sys.stderr, flush=True)
         equations = run_equations(w, args.dtype)
+    others = None
+    if not args.no_others:
+        print("bench: the other workloads", file=sys.stderr, flush=True)
+        others = run_others(args.workload)
     batch = None
     if not args.no_batch:
         print("bench: batched 64-grid workload", file=sys.stderr, flush=True)
@@ -452,6 +479,7 @@ def main():
         "batched": batch,
         "euler_fd": euler,
         "equations": equations,
+        "other_workloads": others,
         "adjoint": adj,
         "wall_s_timed_region": round(wall, 4),
     }
