@@ -253,6 +253,17 @@ ss_status ss_autotune(ss_grid g, int reps);
 ss_status ss_get_tiles(ss_grid g, int tiles[6]);
 ss_status ss_set_tiles(ss_grid g, const int tiles[6]);
 
+/* Read / override which arrays a (stepping-form) step uses, chosen by
+ * ss_autotune: 1 (default) every pass in place on the state arrays (the
+ * k-space pass writes the new state over the nonlinear term), 0 the
+ * nonlinear term in the scratch arrays and the new state back to the
+ * state arrays, 2 the nonlinear term in the scratch arrays with the new
+ * state written over it, after which the two arrays swap roles.  Results
+ * are bitwise the same; only the memory traffic pattern differs.
+ * Errors: SS_ERR_ARG (null, arrangement outside 0..2). */
+ss_status ss_get_step_arrangement(ss_grid g, int* arr);
+ss_status ss_set_step_arrangement(ss_grid g, int arr);
+
 /* ---- Reverse mode (adjoint) of ss_step_n ---------------------------------
  *
  * Gradients of a scalar J(q^T) of the fields after nsteps steps with

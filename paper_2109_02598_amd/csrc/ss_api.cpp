@@ -94,7 +94,10 @@ struct ss_grid_s {
   // tiling of each pass (rows or lines per workgroup); 0 = not chosen yet
   int tile_x_step = 0, tile_x_io = 0, tile_y = 0, tile_k = 0;
   int tile_x_ppb = 0;   // x pass tiles per block (> 1: persistent, prefetching)
-  bool step_inplace = true;   // stepping-form passes in place on the state (else G in scratch)
+  // arrays of a stepping-form step: 1 (default) every pass in place on the
+  // state; 0 G in the scratch arrays, T back to the state; 2 G in the
+  // scratch arrays and T over it, then state and scratch swap roles
+  int step_arr = 1;
   int lb = -1;          // log2 of the row block B of the spectral layout (-1: not chosen)
 
   // reverse mode: caller-owned workspace with checkpoints and segment
@@ -259,7 +262,7 @@ ss::LaunchEvents take_events(PassTimer* pt, int kind) {
 typedef std::tuple<int, int, int64_t, int64_t, int64_t, int> TileKey;  // ndim, esz, nx, ny, nz, nf
 struct Tiles {
   int x_step, y, k, x_ppb, lb;
-  int inplace;   // -1: not chosen
+  int arr;   // step arrangement, -1: not chosen
 };
 std::mutex g_tile_mu;
 std::map<TileKey, Tiles> g_tile_cache;
@@ -314,7 +317,7 @@ void ensure_tiles(ss_grid g) {
   }
   if (!g->tile_k) g->tile_k = t.k ? t.k : ss::k_tile_default(esz, nlast(g), nlines_k(g), g->ndim == 3);
   if (g->ndim == 3 && !g->tile_y) g->tile_y = t.y ? t.y : ss::y_tile_default(esz, (int)g->n[1], g->n[2]);
-  if (t.inplace >= 0) g->step_inplace = t.inplace != 0;
+  if (t.arr >= 0) g->step_arr = t.arr;
 }
 
 // Coefficients of the x pass's pointwise terms (fixed models) or their
@@ -374,14 +377,15 @@ ss_status launch_ypass(ss_grid g, int dir, const void* in, void* out, double sca
 // out; mode 0: T and G in, T out (three transforms); mode 2: refresh S^
 // from T.
 template <typename T>
-ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr, int mode = 1, bool inplace = false) {
+ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr, int mode = 1, int arr = 0) {
   ss::KArgs a;
   memset(&a, 0, sizeof(a));
   const bool three = g->ndim == 3;
   for (int f = 0; f < g->nf; ++f) {
     a.fld[f] = g->kf[f];
     a.fld[f].state = g->state[f];
-    a.fld[f].nonlin = inplace ? g->state[f] : g->scratch[f];
+    a.fld[f].nonlin = arr == 1 ? g->state[f] : g->scratch[f];   // G
+    a.fld[f].out = arr == 2 ? g->scratch[f] : nullptr;           // T: over G, else to the state
     a.fld[f].shat = g->shat[f];
   }
   a.J = three ? (int)g->n[1] : 1;
@@ -425,14 +429,15 @@ ss_status ensure_shat(ss_grid g) {
 // so both follow the same arithmetic).
 template <typename T>
 ss_status step_once(ss_grid g, PassTimer* pt, bool hat = true) {
-  // The stepping form runs every pass in place on the state arrays (each
-  // workgroup reads its tile or lines whole before writing them; the
-  // k-space pass writes T over G): a step touches the state and its
-  // spectrum only, half the arrays, which keeps more of them in the
-  // Infinity Cache.  The three-transform form reads T and G together and
-  // keeps G in the scratch arrays.
-  const bool inplace = hat && g->step_inplace;
-  void** G = inplace ? g->state : g->scratch;
+  // The stepping form can run every pass in place on the state arrays
+  // (each workgroup reads its tile or lines whole before writing them; the
+  // k-space pass writes T over G): a step then touches the state and its
+  // spectrum only, which keeps more of them in the Infinity Cache.  Or G
+  // goes to the scratch arrays and the k-space pass writes T over it, and
+  // the two arrays swap roles.  The three-transform form reads T and G
+  // together and keeps G in the scratch arrays.
+  const int arr = hat ? g->step_arr : 0;
+  void** G = arr == 1 ? g->state : g->scratch;
   if (g->ndim == 2) {
     SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], G[0], G[1], nullptr, nullptr,
                            1.0, pt));
@@ -441,7 +446,9 @@ ss_status step_once(ss_grid g, PassTimer* pt, bool hat = true) {
     SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, G[0], G[1], G[0], G[1], nullptr, nullptr, 1.0, pt));
     for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, -1, G[f], G[f], 1.0, pt));
   }
-  SS_TRY(launch_kpass<T>(g, pt, hat ? 1 : 0, inplace));
+  SS_TRY(launch_kpass<T>(g, pt, hat ? 1 : 0, arr));
+  if (arr == 2)
+    for (int f = 0; f < g->nf; ++f) std::swap(g->state[f], g->scratch[f]);
   if (!hat) g->shat_valid = false;
   g->log_count++;
   return SS_OK;
@@ -851,15 +858,20 @@ ss_status autotune_t(ss_grid g, int reps) {
   g->tile_k = bk;
   g->tile_y = by;
   if (free_layout) {
-    // whether the passes run in place on the state: fewer arrays in the
-    // caches, against the in-place x pass's access pattern (slower for
-    // FP32 in 2D)
-    float t_in, t_out;
-    g->step_inplace = true;
-    SS_TRY(tune_steps<T>(g, reps, &t_in));
-    g->step_inplace = false;
-    SS_TRY(tune_steps<T>(g, reps, &t_out));
-    g->step_inplace = t_in <= t_out;
+    // the arrays of a step (see step_once): fewer arrays in the caches
+    // against the in-place x pass's access pattern (slower for FP32 in 2D)
+    float best_arr = 1e30f;
+    int barr = 1;
+    for (int arr : {1, 0, 2}) {
+      g->step_arr = arr;
+      float ms;
+      SS_TRY(tune_steps<T>(g, reps, &ms));
+      if (ms < best_arr) {
+        best_arr = ms;
+        barr = arr;
+      }
+    }
+    g->step_arr = barr;
     // the dominant pass's tiling, settled by whole steps as well: single
     // launches repeated on the same arrays can rank tilings differently
     // from steps once the arrays outgrow the Infinity Cache
@@ -900,7 +912,7 @@ ss_status autotune_t(ss_grid g, int reps) {
   }
   std::lock_guard<std::mutex> lk(g_tile_mu);
   g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k, g->tile_x_ppb, g->lb,
-                                     g->step_inplace ? 1 : 0};
+                                     g->step_arr};
   return SS_OK;
 }
 
@@ -1519,6 +1531,19 @@ ss_status ss_workspace_size(ss_grid g, size_t* bytes) {
   if (!g || !bytes) return fail(SS_ERR_ARG, "ss_workspace_size: null argument");
   if (!g->has_model) return fail(SS_ERR_STATE, "ss_workspace_size: call ss_set_model first");
   *bytes = align_up(g->field_bytes()) * (size_t)(g->solver == 1 ? 2 * g->nf + 3 : 3 * g->nf + 1);
+  return SS_OK;
+}
+
+ss_status ss_get_step_arrangement(ss_grid g, int* arr) {
+  if (!g || !arr) return fail(SS_ERR_ARG, "ss_get_step_arrangement: null argument");
+  *arr = g->step_arr;
+  return SS_OK;
+}
+
+ss_status ss_set_step_arrangement(ss_grid g, int arr) {
+  if (!g) return fail(SS_ERR_ARG, "ss_set_step_arrangement: null grid");
+  if (arr < 0 || arr > 2) return fail(SS_ERR_ARG, "ss_set_step_arrangement: arrangement %d is not 0, 1 or 2", arr);
+  g->step_arr = arr;
   return SS_OK;
 }
 

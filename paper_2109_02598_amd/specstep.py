@@ -66,6 +66,8 @@ def lib():
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
         "ss_structure_factor_nbins": [vp, ctypes.POINTER(cint)],
         "ss_set_solver": [vp, cint, cint],
+        "ss_get_step_arrangement": [vp, ctypes.POINTER(cint)],
+        "ss_set_step_arrangement": [vp, cint],
         "ss_set_equations": [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl), cint,
                              dbl, cint],
         "ss_split_equations": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl), cint,
@@ -207,6 +209,16 @@ def ss_structure_factor_nbins(h):
 
 def ss_structure_factor(h, field, s_ptr, n_ptr, nbins):
     _check(lib().ss_structure_factor(h, int(field), s_ptr, n_ptr, int(nbins)))
+
+
+def ss_get_step_arrangement(h):
+    v = ctypes.c_int()
+    _check(lib().ss_get_step_arrangement(h, ctypes.byref(v)))
+    return v.value
+
+
+def ss_set_step_arrangement(h, arr):
+    _check(lib().ss_set_step_arrangement(h, int(arr)))
 
 
 SOLVERS = {"spectral": 0, "euler": 1}

@@ -134,3 +134,38 @@ def test_tilings_are_bitwise_identical(n, model, dtype):
         assert np.array_equal(g.get_field(i).cpu().numpy(), b), tiles
     say("tilings tried", tried, "autotuned", tiles)
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,model", [((256, 64), "cahn_hilliard"), ((64, 128), "gray_scott"),
+                                     ((32, 16, 64), "pfc"), ((16, 16, 32), "model_c")])
+def test_step_arrangements_are_bitwise_identical(n, model, dtype):
+    """The three arrays arrangements of a step (in place on the state; G in
+    scratch; G in scratch with T over it and the arrays swapping roles) give
+    the same bits, across calls of odd length and a reload of the fields."""
+    from tests._common import need_gpu
+    torch, specstep = need_gpu()
+    dx = (1.0,) * len(n)
+    f0 = as_input(synth_fields(model, n, dx, 5), dtype)
+    f1 = as_input(synth_fields(model, n, dx, 6), dtype)
+    outs = {}
+    for arr in (1, 0, 2):
+        g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model], dt=0.05)
+        specstep.ss_set_step_arrangement(g.h, arr)
+        assert specstep.ss_get_step_arrangement(g.h) == arr
+        for i, f in enumerate(f0):
+            g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
+        g.step(3)
+        g.step(4)
+        mid = [g.get_field(i).cpu().numpy() for i in range(len(f0))]
+        for i, f in enumerate(f1):
+            g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
+        g.step(5)
+        outs[arr] = mid + [g.get_field(i).cpu().numpy() for i in range(len(f1))]
+        g.close()
+    for arr in (0, 2):
+        for a, b in zip(outs[arr], outs[1]):
+            assert np.array_equal(a, b), arr
+    with pytest.raises(specstep.SpecStepError):
+        specstep.ss_set_step_arrangement(specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model],
+                                                       dt=0.05).h, 3)
