@@ -42,6 +42,9 @@ def workloads():
         "ac128": lambda: inputs.allen_cahn_2d(n=128, seed=1, steps=100),
         "pfc256": lambda: inputs.pfc_3d(n=256, seed=3, steps=500),
         "gs512": lambda: inputs.gray_scott_2d(n=512),
+        # the shapes of the paper's own timing table (Sec. 3.1): context
+        "ac512": lambda: inputs.allen_cahn_2d(n=512, seed=1, steps=100),
+        "mc512": lambda: inputs.model_c_2d(n=512),
     }
 
 
@@ -303,10 +306,11 @@ def run_equations(w, dtype, steps=300):
 
 def run_others(skip, steps=200):
     """The other workloads of the benchmark set (PFC 256^3, GS 512^2, AC
-    128^2), both precisions, 200 timed steps each: cell-updates/s and the
-    roofline of each one's dominant kernel."""
+    128^2) and two shapes of the paper's timing table (Allen-Cahn and
+    Model C at 512^2), both precisions, 200 timed steps each:
+    cell-updates/s and the roofline of each one's dominant kernel."""
     out = {}
-    for name in ("pfc256", "gs512", "ac128"):
+    for name in ("pfc256", "gs512", "ac128", "ac512", "mc512"):
         if name == skip:
             continue
         w = workloads()[name]()

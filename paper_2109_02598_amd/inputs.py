@@ -97,6 +97,15 @@ def allen_cahn_2d(n=128, seed=1, steps=100) -> Workload:
                     [uniform_field(seed, shape, -0.1, 0.1)])
 
 
+def model_c_2d(n=512, seed=8, steps=100) -> Workload:
+    """2D Model C (psi non-conserved, m conserved), dx=1, dt=0.05,
+    c1..c5 = 1, both fields ~ U[-0.1, 0.1) (field 1 from seed + 1)."""
+    shape = (n, n)
+    return Workload("model_c_%dx%d" % (n, n), "model_c", (n, n), (1.0, 1.0), 0.05,
+                    (1.0, 1.0, 1.0, 1.0, 1.0), steps,
+                    [uniform_field(seed, shape, -0.1, 0.1), uniform_field(seed + 1, shape, -0.1, 0.1)])
+
+
 def cahn_hilliard_2d(n=2048, seed=2, steps=1000) -> Workload:
     """2D Cahn-Hilliard, dx=1, dt=0.1, M=kappa=c1=c2=1, phi ~ U[-0.05, 0.05).
 
