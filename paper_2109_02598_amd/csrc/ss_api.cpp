@@ -496,8 +496,14 @@ ss_status fd_step_once(ss_grid g) {
       SS_TRY(fd_launch(g, ss::FD_GS, S[0], S[1], N[0], N[1], 0.0));
       break;
     case SS_CAHN_HILLIARD:
-      SS_TRY(fd_launch(g, ss::FD_MU_CH, S[0], nullptr, T[0], nullptr, 0.0));
-      SS_TRY(fd_launch(g, ss::FD_UPD, S[0], T[0], N[0], nullptr, c[0]));
+      // 2D axis-wise stencil: mu recomputed at the stencil points, one launch
+      // and two arrays (the wider stencils recompute too much: 9 x 9 loads)
+      if (g->ndim == 2 && (g->stencil == 0 || g->stencil == 5)) {
+        SS_TRY(fd_launch(g, ss::FD_CH, S[0], nullptr, N[0], nullptr, 0.0));
+      } else {
+        SS_TRY(fd_launch(g, ss::FD_MU_CH, S[0], nullptr, T[0], nullptr, 0.0));
+        SS_TRY(fd_launch(g, ss::FD_UPD, S[0], T[0], N[0], nullptr, c[0]));
+      }
       break;
     case SS_PFC:
       SS_TRY(fd_launch(g, ss::FD_LAP, S[0], nullptr, T[0], nullptr, 0.0));

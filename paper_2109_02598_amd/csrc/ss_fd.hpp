@@ -26,6 +26,10 @@
 //   FD_MU_PFC mu = (r + q0^4) psi + 2 q0^2 a + L a + g2 psi^2 + g3 psi^3
 //   FD_MC     psi' = psi + dt (L psi + c1 psi - c2 psi^3 + 2 c5 psi m),
 //             b = -L m - c3 m + c4 m^3 - c5 psi^2     (then m' = m + dt L b)
+//   FD_CH     psi' = psi + dt M L mu with mu recomputed at every stencil
+//             point from psi (FD_MU_CH and FD_UPD in one launch: the
+//             neighbours' psi come from the caches, and the step moves two
+//             arrays instead of five; same arithmetic, same bits)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,7 +37,7 @@
 
 namespace ss {
 
-enum { FD_AC = 0, FD_GS = 1, FD_MU_CH = 2, FD_UPD = 3, FD_LAP = 4, FD_MU_PFC = 5, FD_MC = 6 };
+enum { FD_AC = 0, FD_GS = 1, FD_MU_CH = 2, FD_UPD = 3, FD_LAP = 4, FD_MU_PFC = 5, FD_MC = 6, FD_CH = 7 };
 
 struct FDArgs {
   const void* in[2];
@@ -48,12 +52,9 @@ struct FDArgs {
   int op;
 };
 
-template <typename T, int DIM, int ST>
-__device__ __forceinline__ T fd_lap(const T* __restrict__ f, int64_t x, int64_t y, int64_t z, const FDArgs& a) {
-  const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
-  auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-    return f[((((z + dz) & mz) * a.ny + ((y + dy) & my)) << a.lx) + ((x + dx) & mx)];
-  };
+// The stencil applied to at(dx, dy, dz), the value at offset (dx, dy, dz).
+template <typename T, int DIM, int ST, typename AT>
+__device__ __forceinline__ T fd_stencil(AT&& at, const FDArgs& a) {
   const T c = at(0, 0, 0);
   if constexpr (ST == 0) {
     T s = (at(-1, 0, 0) + at(1, 0, 0) - (T)2 * c) * (T)a.ih2[0] +
@@ -83,6 +84,26 @@ __device__ __forceinline__ T fd_lap(const T* __restrict__ f, int64_t x, int64_t 
       return ((T)14 * face + (T)3 * edge + corner - (T)128 * c) * (T)a.i30h2;
     }
   }
+}
+
+// The stencil applied to array f around cell (x, y, z) (periodic wrap;
+// x, y, z may lie one or two cells outside the grid).
+template <typename T, int DIM, int ST>
+__device__ __forceinline__ T fd_lap(const T* __restrict__ f, int64_t x, int64_t y, int64_t z, const FDArgs& a) {
+  const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
+  auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+    return f[((((z + dz) & mz) * a.ny + ((y + dy) & my)) << a.lx) + ((x + dx) & mx)];
+  };
+  return fd_stencil<T, DIM, ST>(at, a);
+}
+
+// Cahn-Hilliard chemical potential at one cell (the FD_MU_CH expression).
+template <typename T, int DIM, int ST>
+__device__ __forceinline__ T fd_mu_ch(const T* __restrict__ f, int64_t x, int64_t y, int64_t z, const FDArgs& a) {
+  const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+  const int64_t i = ((((z & (a.nz - 1)) * a.ny + (y & (a.ny - 1))) << a.lx) + (x & (a.nx - 1)));
+  const T q = f[i];
+  return c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(f, x, y, z, a);
 }
 
 template <typename T, int DIM, int ST>
@@ -132,6 +153,14 @@ __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
       const T q02 = q0 * q0;
       out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + fd_lap<T, DIM, ST>(in1, x, y, z, a) + g2 * q * q +
                 g3 * q * q * q;
+      break;
+    }
+    case FD_CH: {
+      const T M = (T)a.p[0];
+      auto mu_at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+        return fd_mu_ch<T, DIM, ST>(in0, x + dx, y + dy, z + dz, a);
+      };
+      out0[i] = in0[i] + dt * (M * fd_stencil<T, DIM, ST>(mu_at, a));
       break;
     }
     default: {  // FD_MC
