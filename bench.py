@@ -395,6 +395,8 @@ def main():
     ap.add_argument("--no-euler", action="store_true", help="skip the finite-difference solver timing")
     ap.add_argument("--no-equations", action="store_true", help="skip the run-time equations timing")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads (PFC 256^3, GS, AC)")
+    ap.add_argument("--only", choices=["equations", "euler", "batch", "adjoint"],
+                    help="run only this leg on the workload and print its JSON object (for profiling)")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (for scaling "
@@ -426,6 +428,11 @@ def main():
         sys.exit(1)
 
     w = workloads()[args.workload]()
+    if args.only:
+        leg = {"equations": lambda: run_equations(w, args.dtype), "euler": lambda: run_euler(w, args.dtype),
+               "batch": run_batch, "adjoint": run_adjoint}[args.only]
+        print(json.dumps({args.only: leg()}), flush=True)
+        return
     print("bench: workload %s cells %d dtype %s steps %d warmup %d" %
           (w.name, w.cells, args.dtype, args.steps, args.warmup), file=sys.stderr, flush=True)
     ms, wall, prof, mass = run_gpu(w, args.dtype, args.steps, args.warmup, args.profile_steps,
