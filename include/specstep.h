@@ -259,7 +259,9 @@ ss_status ss_set_tiles(ss_grid g, const int tiles[6]);
  * nonlinear term in the scratch arrays and the new state back to the
  * state arrays, 2 the nonlinear term in the scratch arrays with the new
  * state written over it, after which the two arrays swap roles.  Results
- * are bitwise the same; only the memory traffic pattern differs.
+ * are bitwise the same; only the memory traffic pattern differs.  A value
+ * set here stays until changed here or by ss_autotune (tilings remembered
+ * for the grid's shape do not replace it).
  * Errors: SS_ERR_ARG (null, arrangement outside 0..2). */
 ss_status ss_get_step_arrangement(ss_grid g, int* arr);
 ss_status ss_set_step_arrangement(ss_grid g, int arr);

@@ -98,6 +98,7 @@ struct ss_grid_s {
   // state; 0 G in the scratch arrays, T back to the state; 2 G in the
   // scratch arrays and T over it, then state and scratch swap roles
   int step_arr = 1;
+  bool step_arr_set = false;   // chosen by ss_set_step_arrangement: the tile cache leaves it alone
   int lb = -1;          // log2 of the row block B of the spectral layout (-1: not chosen)
 
   // reverse mode: caller-owned workspace with checkpoints and segment
@@ -317,7 +318,7 @@ void ensure_tiles(ss_grid g) {
   }
   if (!g->tile_k) g->tile_k = t.k ? t.k : ss::k_tile_default(esz, nlast(g), nlines_k(g), g->ndim == 3);
   if (g->ndim == 3 && !g->tile_y) g->tile_y = t.y ? t.y : ss::y_tile_default(esz, (int)g->n[1], g->n[2]);
-  if (t.arr >= 0) g->step_arr = t.arr;
+  if (t.arr >= 0 && !g->step_arr_set) g->step_arr = t.arr;
 }
 
 // Coefficients of the x pass's pointwise terms (fixed models) or their
@@ -1550,6 +1551,7 @@ ss_status ss_set_step_arrangement(ss_grid g, int arr) {
   if (!g) return fail(SS_ERR_ARG, "ss_set_step_arrangement: null grid");
   if (arr < 0 || arr > 2) return fail(SS_ERR_ARG, "ss_set_step_arrangement: arrangement %d is not 0, 1 or 2", arr);
   g->step_arr = arr;
+  g->step_arr_set = true;
   return SS_OK;
 }
 

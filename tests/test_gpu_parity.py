@@ -157,6 +157,7 @@ def test_step_arrangements_are_bitwise_identical(n, model, dtype):
             g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
         g.step(3)
         g.step(4)
+        assert specstep.ss_get_step_arrangement(g.h) == arr   # not replaced by tuned tiles of the shape
         mid = [g.get_field(i).cpu().numpy() for i in range(len(f0))]
         for i, f in enumerate(f1):
             g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
