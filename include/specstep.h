@@ -146,7 +146,7 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
  * solver 0 (default): the semi-implicit spectral scheme (Sec. 2.4.2).
  * solver 1: explicit forward Euler with finite differences (Sec. 2.4.1):
  *   q <- q + dt * rhs(q) on the real-space fields, the right-hand sides of
- *   the models above with the Laplacian replaced by a second-order stencil
+ *   the models above with the Laplacian replaced by a finite-difference stencil
  *   (Sec. 2.2.2; periodic wrap; higher powers by composition):
  *   stencil 0 (or 5 in 2D, 7 in 3D): axis-wise central differences,
  *   sum_a (f[-1] - 2 f + f[+1]) / dx_a^2;  stencil 9 (2D) or 19 (3D): the
@@ -167,11 +167,13 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
  * SS_ERR_UNSUPPORTED (isotropic stencil with unequal spacings). */
 ss_status ss_set_solver(ss_grid g, int solver, int stencil);
 
-/* Bytes of device workspace the grid needs (after ss_set_model):
- * for the spectral solver (3 nfields + 1) arrays of nx*ny*nz reals -- per field the partly
- * transformed state, its full spectrum (carried between steps so that a
- * step transforms the state only once, inversely) and the transformed
- * nonlinear term, plus one staging array. */
+/* Bytes of device workspace the grid needs (after ss_set_model or
+ * ss_set_equations): for the spectral solver (3 nfields + 1) arrays of
+ * nx*ny*nz reals -- per field the partly transformed state, its full
+ * spectrum (carried between steps so that a step transforms the state only
+ * once, inversely) and a scratch array (the transformed nonlinear term
+ * unless the step runs in place, see ss_set_step_arrangement), plus one
+ * staging array; for the finite-difference solver (2 nfields + 3). */
 ss_status ss_workspace_size(ss_grid g, size_t* bytes);
 
 /* Bind caller-owned device memory of at least ss_workspace_size bytes,
