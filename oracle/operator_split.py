@@ -327,3 +327,32 @@ def step_n(fields, split, dt, dx, nsteps, scheme="etd1"):
             new.append(np.ascontiguousarray(np.fft.ifftn(acc).real))
         q = new
     return q
+
+
+def euler_n(fields, split, dt, dx, nsteps, stencil=0):
+    """``nsteps`` forward-Euler steps (Sec. 2.4.1) of the split equations
+    with finite-difference Laplacians (Sec. 2.2.2, the stencils of
+    ``fd_euler.laplacian``): psi_j' = psi_j + dt (sum_p c_p lap^p psi_j +
+    sum_i lap^p_i (E_i^0 + E_i^1)), every term from the fields of the
+    current step."""
+    from oracle.fd_euler import laplacian
+
+    def lap_pow(f, p):
+        for _ in range(p):
+            f = laplacian(f, dx, stencil)
+        return f
+
+    q = [np.array(f, dtype=np.float64, copy=True) for f in fields]
+    if len(q) != len(split.fields):
+        raise SplitError("%d fields given, the equations have %d" % (len(q), len(split.fields)))
+    for _ in range(int(nsteps)):
+        new = []
+        for j in range(len(q)):
+            rhs = np.zeros_like(q[j])
+            for p, c in split.L[j].items():
+                rhs = rhs + c * lap_pow(q[j], p)
+            for p, e0, e1 in split.channels[j]:
+                rhs = rhs + lap_pow(pointwise(e0, q) + pointwise(e1, q), p)
+            new.append(q[j] + dt * rhs)
+        q = new
+    return q

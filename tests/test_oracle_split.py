@@ -211,3 +211,49 @@ def test_implicit_scheme_needs_a_positive_denominator():
     sp = osp.parse("psi' = 5*psi", {})
     with pytest.raises(osp.SplitError):
         osp.step_n([np.zeros((8, 8))], sp, 0.5, (1.0, 1.0), 1, "implicit")
+
+
+# --- the forward-Euler form of the split ------------------------------------
+
+from oracle import fd_euler  # noqa: E402
+
+
+@pytest.mark.parametrize("model,stencil,shape", [
+    ("allen_cahn", 0, (16, 32)), ("cahn_hilliard", 9, (32, 32)), ("pfc", 0, (16, 16)),
+    ("gray_scott", 4, (16, 32)), ("model_c", 0, (16, 16)), ("cahn_hilliard", 19, (8, 8, 8)),
+])
+def test_euler_form_reduces_to_the_fixed_model_euler_oracle(model, stencil, shape):
+    coef = COEF[model] if model != "pfc" else (-0.25, 1.0, 0.3, 1.0)
+    text, coefs = eqs.fixed(model, coef)
+    nf = spectral.NFIELDS[model]
+    q0 = rand_fields(nf, shape, 13)
+    if model == "gray_scott":
+        q0 = [1.0 + q0[0], 0.25 + q0[1]]
+    dx = (1.0,) * len(shape)
+    dt = {"pfc": 5e-4}.get(model, 0.01)
+    got = osp.euler_n(q0, osp.parse(text, coefs), dt, dx, 10, stencil)
+    want = fd_euler.euler_n(q0, model, coef, dt, dx, 10, stencil)
+    for a, b in zip(got, want):
+        assert rel(a, b) < 1e-12
+
+
+@pytest.mark.parametrize("case", range(len(CONSISTENCY)))
+@pytest.mark.parametrize("stencil", [0, 9])
+def test_euler_increment_is_the_directly_evaluated_right_hand_side(case, stencil):
+    """One Euler step's increment over dt is the right-hand side itself,
+    evaluated by Python's parser with the same finite-difference Laplacian
+    (equal up to rounding)."""
+    text, coefs = CONSISTENCY[case]
+    sp = osp.parse(text, coefs)
+    shape, dx = (16, 32), (1.0, 1.0)
+    q0 = smooth_fields(len(sp.fields), shape, 9 + case)
+    dt = 1e-3
+    q1 = osp.euler_n(q0, sp, dt, dx, 1, stencil)
+    env = dict(coefs)
+    lap = lambda f: fd_euler.laplacian(np.broadcast_to(np.asarray(f, dtype=float), shape), dx, stencil)
+    env.update(lap=lap, bilap=lambda f: lap(lap(f)))
+    lines = [s for s in text.replace(";", "\n").split("\n") if s.strip()]
+    env.update(zip([s.split("'")[0].strip() for s in lines], q0))
+    for a, b, s in zip(q1, q0, lines):
+        r = np.broadcast_to(eval(s.split("=", 1)[1].replace("^", "**"), {"__builtins__": {}}, env), shape)
+        assert rel((a - b) / dt, r) < 1e-11
