@@ -119,14 +119,17 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
  *   k^2 up to the grid's largest, sum_a (pi/dx_a)^2.
  * Afterwards the grid behaves as with ss_set_model (model SS_EQUATIONS):
  * ss_step_n, fields, mass log, structure factor, autotune and timing work;
- * the finite-difference solver, the adjoint and batches are
- * SS_ERR_UNSUPPORTED.  Replacing equations with the same number of fields
+ * the adjoint and batches are SS_ERR_UNSUPPORTED.  With the
+ * finite-difference solver (ss_set_solver, before or after) the same split
+ * is stepped by forward Euler (Sec. 2.4.1): psi_j += dt (sum_p c_p lap^p
+ * psi_j + lap^p_j E_j), every Laplacian the chosen stencil; scheme must
+ * be 0 there.  Replacing equations with the same number of fields
  * keeps the workspace and fields (like changing coefficients); otherwise
  * they are dropped.
  * Errors: SS_ERR_ARG (unreadable text, unknown or duplicate names,
  * non-finite values, dt <= 0, unknown scheme, 1 - L dt <= 0),
- * SS_ERR_UNSUPPORTED (a valid equation outside the limits above, or the
- * finite-difference solver selected). */
+ * SS_ERR_UNSUPPORTED (a valid equation outside the limits above, or
+ * scheme 1 with the finite-difference solver). */
 ss_status ss_set_equations(ss_grid g, const char* equations, const char* const names[],
                            const double values[], int nvalues, double dt, int scheme);
 
@@ -146,7 +149,8 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
  * solver 0 (default): the semi-implicit spectral scheme (Sec. 2.4.2).
  * solver 1: explicit forward Euler with finite differences (Sec. 2.4.1):
  *   q <- q + dt * rhs(q) on the real-space fields, the right-hand sides of
- *   the models above with the Laplacian replaced by a finite-difference stencil
+ *   the models above, or of the equations of ss_set_equations, with the
+ *   Laplacian replaced by a finite-difference stencil
  *   (Sec. 2.2.2; periodic wrap; higher powers by composition):
  *   stencil 0 (or 5 in 2D, 7 in 3D): axis-wise central differences,
  *   sum_a (f[-1] - 2 f + f[+1]) / dx_a^2;  stencil 9 (2D) or 19 (3D): the
@@ -164,7 +168,8 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
  * Changing the solver drops the bound workspace and fields (its size
  * differs: (2 nfields + 3) arrays for solver 1).
  * Errors: SS_ERR_ARG (unknown solver or stencil for the dimension),
- * SS_ERR_UNSUPPORTED (isotropic stencil with unequal spacings). */
+ * SS_ERR_UNSUPPORTED (isotropic stencil with unequal spacings; solver 1
+ * for equations set with scheme 1). */
 ss_status ss_set_solver(ss_grid g, int solver, int stencil);
 
 /* Bytes of device workspace the grid needs (after ss_set_model or

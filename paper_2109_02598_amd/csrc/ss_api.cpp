@@ -71,6 +71,7 @@ struct ss_grid_s {
   double p[5] = {0};
   ss::NTab tab = {};   // explicit terms of equations read at run time (NLIN_TABLE)
   int scheme = 0;      // 0: ETD1 factors; 1: linearly implicit (ss_set_equations)
+  ss::EqSplit eq = {};  // the split of ss_set_equations (finite-difference solver)
 
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -484,7 +485,105 @@ ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* o
   return hip_check(e, "finite-difference launch");
 }
 
+// Equations read at run time: field j's right-hand side as nested levels
+// v_k = (-1)^k L[j][k] psi_j (+ E_j if p_j = k) + lap v_{k+1}, k = D_j .. 0
+// (L is the symbol in k^2, and lap -> -k^2), a
+// launch evaluating up to `most` levels; a field's launches alternate
+// between the two intermediate arrays; two fields with the same single
+// launch share it.
+ss_status fd_eq_launch(ss_grid g, const ss::FDEq& q, int depth) {
+  ss::FDArgs a;
+  memset(&a, 0, sizeof(a));
+  a.in[0] = g->state[0];
+  a.in[1] = g->nf > 1 ? g->state[1] : nullptr;
+  a.nx = g->n[0];
+  a.ny = g->n[1];
+  a.nz = g->n[2];
+  a.lx = ilog2i(g->n[0]);
+  a.lxy = ilog2i(g->n[0] * g->n[1]);
+  for (int d = 0; d < 3; ++d) a.ih2[d] = d < g->ndim ? 1.0 / (g->dx[d] * g->dx[d]) : 0.0;
+  a.i6h2 = 1.0 / (6.0 * g->dx[0] * g->dx[0]);
+  a.i30h2 = 1.0 / (30.0 * g->dx[0] * g->dx[0]);
+  a.dt = g->dt;
+  const int st = (g->stencil == 9 || g->stencil == 19 || g->stencil == 27 || g->stencil == 4) ? g->stencil : 0;
+  hipError_t e = g->dtype == SS_F64 ? ss::run_fd_eq<double>(g->ndim, st, depth, a, q, g->stream)
+                                    : ss::run_fd_eq<float>(g->ndim, st, depth, a, q, g->stream);
+  return hip_check(e, "finite-difference launch");
+}
+
+int fd_eq_top(const ss::EqSplit& sp, int j) {
+  int D = sp.p[j] > 0 ? sp.p[j] : 0;
+  for (int k = 1; k < 4; ++k)
+    if (sp.L[j][k] != 0.0) D = std::max(D, k);
+  return D;
+}
+
+ss_status fd_eq_step(ss_grid g) {
+  const ss::EqSplit& sp = g->eq;
+  const int most = (g->ndim == 2 && (g->stencil == 0 || g->stencil == 5)) ? 2 : 1;
+  const int st = (g->stencil == 9 || g->stencil == 19 || g->stencil == 27 || g->stencil == 4) ? g->stencil : 0;
+  ss::FDEq q;
+  memset(&q, 0, sizeof(q));
+  for (int j = 0; j < sp.nf; ++j) {
+    q.dv[j] = 0;
+    for (int m = 0; m < sp.nterm[j]; ++m) {
+      const int e0 = sp.e[j][m][0], e1 = sp.e[j][m][1];
+      q.a[j][e1][e0] += sp.c[j][m];
+      q.du[j][e1] = std::max(q.du[j][e1], e0);
+      q.dv[j] = std::max(q.dv[j], e1);
+    }
+    for (int k = 0; k < 8; ++k)
+      for (int i = 0; i < 8; ++i) q.af[j][k][i] = (float)q.a[j][k][i];
+  }
+  // levels [lo, hi] of field j into slot s: v_lo computed, v_hi the deepest
+  auto fill = [&](int s, int j, int lo, int hi, const void* w, void* out) {
+    q.j[s] = j;
+    for (int d = 0; d <= hi - lo; ++d) {
+      q.cl[s][d] = (lo + d) % 2 ? -sp.L[j][lo + d] : sp.L[j][lo + d];   // k^2 -> -lap
+      q.el[s][d] = sp.p[j] == lo + d;
+    }
+    q.w[s] = w;
+    q.out[s] = out;
+  };
+  const int D0 = fd_eq_top(sp, 0), D1 = sp.nf > 1 ? fd_eq_top(sp, 1) : -1;
+  auto own = [&](int j, int D) { return st != 0 && sp.p[j] == D && D > 0; };
+  if (sp.nf == 2 && D0 == D1 && D0 <= most && !own(0, D0) && !own(1, D1)) {
+    q.nj = 2;
+    q.fin = 1;
+    fill(0, 0, 0, D0, nullptr, g->fd_next[0]);
+    fill(1, 1, 0, D1, nullptr, g->fd_next[1]);
+    SS_TRY(fd_eq_launch(g, q, D0));
+  } else {
+    for (int j = 0; j < sp.nf; ++j) {
+      const int D = fd_eq_top(sp, j);
+      // segments from the top: [D - r, D] first (r = D mod most, or most),
+      // then `most` levels a launch down to level 0
+      int hi = D, t = 0;
+      const void* w = nullptr;
+      // wider stencils: E at the top level gets a launch of its own
+      bool alone = own(j, D);
+      while (true) {
+        const int r = alone ? 0 : hi % most ? hi % most : std::min(most, hi);
+        alone = false;
+        const int lo = hi - r;
+        q.nj = 1;
+        q.fin = lo == 0;
+        void* out = lo == 0 ? g->fd_next[j] : g->fd_tmp[t];
+        fill(0, j, lo, hi, w, out);
+        SS_TRY(fd_eq_launch(g, q, hi - lo));
+        if (lo == 0) break;
+        w = out;
+        t ^= 1;
+        hi = lo;
+      }
+    }
+  }
+  for (int f = 0; f < g->nf; ++f) std::swap(g->state[f], g->fd_next[f]);
+  return SS_OK;
+}
+
 ss_status fd_step_once(ss_grid g) {
+  if (g->model == SS_EQUATIONS) return fd_eq_step(g);
   void** S = g->state;
   void** N = g->fd_next;
   void** T = g->fd_tmp;
@@ -1484,8 +1583,8 @@ ss_status ss_set_equations(ss_grid g, const char* equations, const char* const n
   if (!g) return fail(SS_ERR_ARG, "ss_set_equations: null grid");
   if (!(std::isfinite(dt) && dt > 0.0)) return fail(SS_ERR_ARG, "ss_set_equations: dt must be finite and > 0");
   if (scheme != 0 && scheme != 1) return fail(SS_ERR_ARG, "ss_set_equations: unknown scheme %d", scheme);
-  if (g->solver != 0)
-    return fail(SS_ERR_UNSUPPORTED, "ss_set_equations: the finite-difference solver takes the fixed models");
+  if (g->solver == 1 && scheme != 0)
+    return fail(SS_ERR_UNSUPPORTED, "ss_set_equations: the finite-difference solver is explicit (scheme 0)");
   ss::EqSplit sp;
   char msg[256];
   const int rc = ss::eq_split(equations, names, values, nvalues, &sp, msg, sizeof(msg));
@@ -1529,6 +1628,7 @@ ss_status ss_set_equations(ss_grid g, const char* equations, const char* const n
   g->kf[0] = kf[0];
   g->kf[1] = kf[1];
   g->tab = tab;
+  g->eq = sp;
   g->nlm = ss::NLIN_TABLE;
   g->has_model = true;
   return SS_OK;
@@ -1558,8 +1658,8 @@ ss_status ss_set_step_arrangement(ss_grid g, int arr) {
 ss_status ss_set_solver(ss_grid g, int solver, int stencil) {
   if (!g) return fail(SS_ERR_ARG, "ss_set_solver: null grid");
   if (solver != 0 && solver != 1) return fail(SS_ERR_ARG, "ss_set_solver: unknown solver %d", solver);
-  if (solver == 1 && g->has_model && g->model == SS_EQUATIONS)
-    return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the finite-difference solver takes the fixed models");
+  if (solver == 1 && g->has_model && g->model == SS_EQUATIONS && g->scheme != 0)
+    return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the finite-difference solver is explicit (scheme 0)");
   if (solver == 1) {
     const bool ok = stencil == 0 || stencil == 4 ||
                     (g->ndim == 2 ? (stencil == 5 || stencil == 9) : (stencil == 7 || stencil == 19 || stencil == 27));

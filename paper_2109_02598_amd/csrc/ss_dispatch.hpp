@@ -144,6 +144,8 @@ template <typename T>
 hipError_t run_sfreduce(SFArgs a, hipStream_t s);
 template <typename T>
 hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s);
+template <typename T>
+hipError_t run_fd_eq(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s);
 
 #ifdef SS_DISPATCH_IMPL
 
@@ -297,6 +299,24 @@ hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// depth 0: no Laplacian (the stencil is unused); depth 2 only with the 2D
+// axis-wise stencil (25 points of the field per cell)
+template <typename T>
+hipError_t run_fd_eq(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s) {
+  const int64_t n = a.nx * a.ny * a.nz;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define SS_FDEQ(D, S, P) \
+  if (dim == D && stencil == S && depth == P) return launch_with(fd_eq_kernel<T, D, S, P>, grid, block, 0, s, LaunchEvents(), a, q);
+  if (depth == 0) {
+    if (dim == 2) return launch_with(fd_eq_kernel<T, 2, 0, 0>, grid, block, 0, s, LaunchEvents(), a, q);
+    return launch_with(fd_eq_kernel<T, 3, 0, 0>, grid, block, 0, s, LaunchEvents(), a, q);
+  }
+  SS_FDEQ(2, 0, 1) SS_FDEQ(2, 0, 2) SS_FDEQ(2, 9, 1) SS_FDEQ(2, 4, 1)
+  SS_FDEQ(3, 0, 1) SS_FDEQ(3, 19, 1) SS_FDEQ(3, 27, 1) SS_FDEQ(3, 4, 1)
+#undef SS_FDEQ
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev) {
   return launch_with(xpass_grouped<T>, dim3(blocks), dim3(threads), lds, s, ev, b);
@@ -358,7 +378,8 @@ hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
   template hipError_t run_kpass<T>(int, KArgs, int, hipStream_t, LaunchEvents);           \
   template hipError_t run_sfpass<T>(int, SFArgs, hipStream_t);                            \
   template hipError_t run_sfreduce<T>(SFArgs, hipStream_t);                                \
-  template hipError_t run_fd<T>(int, int, FDArgs, hipStream_t);
+  template hipError_t run_fd<T>(int, int, FDArgs, hipStream_t);                           \
+  template hipError_t run_fd_eq<T>(int, int, int, FDArgs, const FDEq&, hipStream_t);
 
 #endif  // SS_DISPATCH_IMPL
 

@@ -30,6 +30,15 @@
 //             point from psi (FD_MU_CH and FD_UPD in one launch: the
 //             neighbours' psi come from the caches, and the step moves two
 //             arrays instead of five; same arithmetic, same bits)
+//
+// Equations read at run time (Sec. 2.4.2 split, stepped with Sec. 2.4.1)
+// take fd_eq_kernel instead: field j's right-hand side
+//   sum_p c_p L^p psi_j + L^p_j E_j(psi)
+// is written as nested levels, v_D = c_D psi_j (+ E_j) and
+//   v_k = c_k psi_j (+ E_j if p_j = k) + L v_{k+1},
+// so that v_0 is the right-hand side.  One launch evaluates DEPTH nested
+// levels, the deepest read from an array written by the launch before it,
+// or evaluated pointwise from the fields when it is the top level.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -104,6 +113,112 @@ __device__ __forceinline__ T fd_mu_ch(const T* __restrict__ f, int64_t x, int64_
   const int64_t i = ((((z & (a.nz - 1)) * a.ny + (y & (a.ny - 1))) << a.lx) + (x & (a.nx - 1)));
   const T q = f[i];
   return c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(f, x, y, z, a);
+}
+
+// The explicit terms of one field, E = sum_k f1^k sum_i a[k][i] f0^i,
+// i <= du[k], k <= dv (Horner in f0 inside Horner in f1).
+struct FDEq {
+  int nj;               // fields this launch computes (1 or 2)
+  int j[2];             // which fields
+  int fin;              // 1: out = psi_j + dt v_0; 0: out = v_0
+  double cl[2][3];      // coefficient of psi_j at nested level d (0: the output)
+  int el[2][3];         // 1: E_j is added at nested level d
+  const void* w[2];     // deepest level from this array, or null: pointwise
+  void* out[2];
+  int dv[2];
+  int du[2][8];
+  double a[2][8][8];
+  float af[2][8][8];
+};
+
+// The table of the explicit terms, staged in LDS (read with uniform
+// addresses), and one slot's coefficients, held in registers.
+template <typename T>
+struct FDEqTab {
+  T a[2][8][8];
+  int du[2][8];
+  int dv[2];
+};
+
+template <typename T>
+struct FDEqSlot {
+  const T* f[2];        // the fields
+  const T* w;
+  T cl[3];
+  int el[3];
+  int j;
+};
+
+template <typename T>
+__device__ __forceinline__ T fd_eq_E(const FDEqTab<T>* tb, int j, T u, T v) {
+  T acc = (T)0;
+  for (int k = tb->dv[j]; k >= 0; --k) {
+    const int dk = tb->du[j][k];
+    T h = (T)0;
+#pragma unroll
+    for (int i = 7; i >= 0; --i)
+      if (i <= dk) h = h * u + tb->a[j][k][i];
+    acc = acc * v + h;
+  }
+  return acc;
+}
+
+// Nested level D at cell (x, y, z) (coordinates may lie outside the grid:
+// they wrap).
+template <typename T, int DIM, int ST, int D, int DEPTH>
+__device__ __forceinline__ T fd_eq_level(const FDArgs& a, const FDEqTab<T>* tb, const FDEqSlot<T>& sl,
+                                         int64_t x, int64_t y, int64_t z) {
+  const int64_t i = ((((z & (a.nz - 1)) * a.ny + (y & (a.ny - 1))) << a.lx) + (x & (a.nx - 1)));
+  if constexpr (D == DEPTH) {
+    if (sl.w) return sl.w[i];
+  }
+  T v = (T)0;
+  if (sl.cl[D] != (T)0) v = sl.cl[D] * sl.f[sl.j][i];
+  // E away from the centre only with the axis-wise stencil (the launches of
+  // the wider stencils put E at a level of its own)
+  if constexpr (D == 0 || ST == 0)
+    if (sl.el[D]) v += fd_eq_E<T>(tb, sl.j, sl.f[0][i], sl.f[1] ? sl.f[1][i] : (T)0);
+  if constexpr (D < DEPTH) {
+    auto next = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+      return fd_eq_level<T, DIM, ST, D + 1, DEPTH>(a, tb, sl, x + dx, y + dy, z + dz);
+    };
+    v += fd_stencil<T, DIM, ST>(next, a);
+  }
+  return v;
+}
+
+template <typename T, int DIM, int ST, int DEPTH>
+__global__ void __launch_bounds__(256) fd_eq_kernel(FDArgs a, FDEq q) {
+  __shared__ FDEqTab<T> tb;
+  const int t = threadIdx.x;
+  if (t < 128) {
+    const int j = t >> 6, k = (t >> 3) & 7, m = t & 7;
+    tb.a[j][k][m] = sizeof(T) == 8 ? (T)q.a[j][k][m] : (T)q.af[j][k][m];
+  } else if (t < 144) {
+    tb.du[(t - 128) >> 3][t & 7] = q.du[(t - 128) >> 3][t & 7];
+  } else if (t < 146) {
+    tb.dv[t - 144] = q.dv[t - 144];
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + t;
+  if (i >= (a.nx * a.ny * a.nz)) return;
+  const int64_t x = i & (a.nx - 1);
+  const int64_t y = (i >> a.lx) & (a.ny - 1);
+  const int64_t z = i >> a.lxy;
+  for (int s = 0; s < q.nj; ++s) {
+    FDEqSlot<T> sl;
+    sl.f[0] = (const T*)a.in[0];
+    sl.f[1] = (const T*)a.in[1];
+    sl.w = (const T*)q.w[s];
+    sl.j = q.j[s];
+    for (int d = 0; d < 3; ++d) {
+      sl.cl[d] = (T)q.cl[s][d];
+      sl.el[d] = q.el[s][d];
+    }
+    T v = fd_eq_level<T, DIM, ST, 0, DEPTH>(a, &tb, sl, x, y, z);
+    if (q.fin) v = sl.f[sl.j][i] + (T)a.dt * v;
+    ((T*)q.out[s])[i] = v;
+  }
 }
 
 template <typename T, int DIM, int ST>

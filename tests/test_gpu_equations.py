@@ -127,8 +127,9 @@ def test_replacing_equations_and_errors():
         specstep.ss_set_equations(g.h, "psi' = -psi + 0.1*bilap(psi)", {}, 0.5, "implicit")
     with pytest.raises(E):
         specstep.ss_set_equations(g.h, "psi' = -psi", {}, 0.0)
+    specstep.ss_set_equations(g.h, "psi' = lap(psi) - psi^3", {}, 0.1, "implicit")
     with pytest.raises(E):
-        specstep.ss_set_solver(g.h, 1, 0)                    # no finite differences for equations
+        specstep.ss_set_solver(g.h, 1, 0)                    # the implicit factors are spectral
     with pytest.raises(E):
         specstep.ss_set_model(g.h, specstep.SS_EQUATIONS, [1.0], 0.1)
     with pytest.raises(E):
