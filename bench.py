@@ -223,7 +223,8 @@ def run_adjoint(steps=200, K=20, dtype="f32"):
 
 def run_euler(w, dtype, steps=500):
     """The forward-Euler finite-difference solver on the same grid and
-    fields (axis-wise, isotropic and fourth-order Laplacians).  With the 2D
+    fields (axis-wise, isotropic and fourth-order Laplacians), with the
+    fixed-model kernels and with the model's equation read at run time.  With the 2D
     axis-wise stencil a Cahn-Hilliard step is one launch that recomputes mu
     at the stencil points from psi (one array read, one written); the
     other stencils take two launches, mu from psi, then psi + dt M L mu
@@ -233,9 +234,12 @@ def run_euler(w, dtype, steps=500):
     out = {"workload": "%s, forward Euler, %s, %d steps (dt 0.01)" % (w.name, dtype, steps)}
     esz = 8 if dtype == "f64" else 4
     nfa = {"allen_cahn": 2, "cahn_hilliard": 5, "pfc": 8, "gray_scott": 4, "model_c": 6}[w.model]
-    for st in ((0, 9, 4) if len(w.n) == 2 else (0, 19, 27, 4)):
-        g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=0.01,
-                          solver="euler", stencil=st)
+    text, names = MODEL_TEXT.get(w.model, (None, ()))
+    variants = [(st, eq) for st in ((0, 9, 4) if len(w.n) == 2 else (0, 19, 27, 4))
+                for eq in ((False, True) if text else (False,))]
+    for st, eq in variants:
+        kw = (dict(equations=text, coefs=dict(zip(names, w.coef))) if eq else dict(model=w.model, coef=w.coef))
+        g = specstep.Grid(w.n, w.dx, dtype=dtype, dt=0.01, solver="euler", stencil=st, **kw)
         for i, f in enumerate(w.fields):
             g.set_field(i, torch.from_numpy(f).to("cuda:0"))
         g.step(20)
@@ -250,7 +254,10 @@ def run_euler(w, dtype, steps=500):
         ms = e0.elapsed_time(e1)
         g.close()
         name = {0: "axis-wise", 4: "fourth-order axis-wise"}.get(st, "isotropic %d-point" % st)
-        arrays = 2 if (w.model == "cahn_hilliard" and st == 0 and len(w.n) == 2) else nfa
+        name += ", equation text" if eq else ""
+        # arrays moved per step: the fused Cahn-Hilliard launch moves 2; the
+        # equation text takes one launch per Laplacian (the fixed kernels' count)
+        arrays = 2 if (w.model == "cahn_hilliard" and st == 0 and len(w.n) == 2 and not eq) else nfa
         out[name] = {"value": round(w.cells * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
                      "us_per_step": round(ms * 1e3 / steps, 2),
                      "achieved_GBs": round(arrays * w.cells * esz * steps / (ms * 1e-3) / 1e9, 1)}

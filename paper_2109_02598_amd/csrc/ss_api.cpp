@@ -487,10 +487,10 @@ ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* o
 
 // Equations read at run time: field j's right-hand side as nested levels
 // v_k = (-1)^k L[j][k] psi_j (+ E_j if p_j = k) + lap v_{k+1}, k = D_j .. 0
-// (L is the symbol in k^2, and lap -> -k^2), a
-// launch evaluating up to `most` levels; a field's launches alternate
-// between the two intermediate arrays; two fields with the same single
-// launch share it.
+// (L is the symbol in k^2, and lap -> -k^2), one Laplacian a launch, from
+// the top level down, alternating between the two intermediate arrays (a
+// launch nesting two Laplacians recomputes too much to pay: its registers
+// halve the occupancy); two fields with a single launch each share it.
 ss_status fd_eq_launch(ss_grid g, const ss::FDEq& q, int depth) {
   ss::FDArgs a;
   memset(&a, 0, sizeof(a));
@@ -520,34 +520,36 @@ int fd_eq_top(const ss::EqSplit& sp, int j) {
 
 ss_status fd_eq_step(ss_grid g) {
   const ss::EqSplit& sp = g->eq;
-  const int most = (g->ndim == 2 && (g->stencil == 0 || g->stencil == 5)) ? 2 : 1;
   const int st = (g->stencil == 9 || g->stencil == 19 || g->stencil == 27 || g->stencil == 4) ? g->stencil : 0;
   ss::FDEq q;
   memset(&q, 0, sizeof(q));
   for (int j = 0; j < sp.nf; ++j) {
-    q.dv[j] = 0;
+    q.tab.dv[j] = 0;
     for (int m = 0; m < sp.nterm[j]; ++m) {
       const int e0 = sp.e[j][m][0], e1 = sp.e[j][m][1];
-      q.a[j][e1][e0] += sp.c[j][m];
-      q.du[j][e1] = std::max(q.du[j][e1], e0);
-      q.dv[j] = std::max(q.dv[j], e1);
+      q.tab.a[j][e1][e0] += sp.c[j][m];
+      q.tab.du[j][e1] = std::max(q.tab.du[j][e1], e0);
+      q.tab.dv[j] = std::max(q.tab.dv[j], e1);
     }
     for (int k = 0; k < 8; ++k)
-      for (int i = 0; i < 8; ++i) q.af[j][k][i] = (float)q.a[j][k][i];
+      for (int i = 0; i < 8; ++i) q.tab.af[j][k][i] = (float)q.tab.a[j][k][i];
   }
-  // levels [lo, hi] of field j into slot s: v_lo computed, v_hi the deepest
-  auto fill = [&](int s, int j, int lo, int hi, const void* w, void* out) {
+  // levels lo and hi = lo + depth of field j into slot s: v_lo computed,
+  // v_hi from w (or pointwise when w is null)
+  auto fill = [&](int s, int j, int lo, int depth, const void* w, void* out) {
     q.j[s] = j;
-    for (int d = 0; d <= hi - lo; ++d) {
+    for (int d = 0; d <= depth; ++d) {
       q.cl[s][d] = (lo + d) % 2 ? -sp.L[j][lo + d] : sp.L[j][lo + d];   // k^2 -> -lap
       q.el[s][d] = sp.p[j] == lo + d;
     }
     q.w[s] = w;
     q.out[s] = out;
   };
-  const int D0 = fd_eq_top(sp, 0), D1 = sp.nf > 1 ? fd_eq_top(sp, 1) : -1;
+  // the wider stencils take E at the centre only: E at the top level then
+  // gets a launch of its own
   auto own = [&](int j, int D) { return st != 0 && sp.p[j] == D && D > 0; };
-  if (sp.nf == 2 && D0 == D1 && D0 <= most && !own(0, D0) && !own(1, D1)) {
+  const int D0 = fd_eq_top(sp, 0), D1 = sp.nf > 1 ? fd_eq_top(sp, 1) : -1;
+  if (sp.nf == 2 && D0 == D1 && D0 <= 1 && !own(0, D0) && !own(1, D1)) {
     q.nj = 2;
     q.fin = 1;
     fill(0, 0, 0, D0, nullptr, g->fd_next[0]);
@@ -556,21 +558,18 @@ ss_status fd_eq_step(ss_grid g) {
   } else {
     for (int j = 0; j < sp.nf; ++j) {
       const int D = fd_eq_top(sp, j);
-      // segments from the top: [D - r, D] first (r = D mod most, or most),
-      // then `most` levels a launch down to level 0
       int hi = D, t = 0;
       const void* w = nullptr;
-      // wider stencils: E at the top level gets a launch of its own
       bool alone = own(j, D);
       while (true) {
-        const int r = alone ? 0 : hi % most ? hi % most : std::min(most, hi);
+        const int depth = (alone || hi == 0) ? 0 : 1;
+        const int lo = hi - depth;
         alone = false;
-        const int lo = hi - r;
         q.nj = 1;
         q.fin = lo == 0;
         void* out = lo == 0 ? g->fd_next[j] : g->fd_tmp[t];
-        fill(0, j, lo, hi, w, out);
-        SS_TRY(fd_eq_launch(g, q, hi - lo));
+        fill(0, j, lo, depth, w, out);
+        SS_TRY(fd_eq_launch(g, q, depth));
         if (lo == 0) break;
         w = out;
         t ^= 1;

@@ -299,22 +299,30 @@ hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-// depth 0: no Laplacian (the stencil is unused); depth 2 only with the 2D
-// axis-wise stencil (25 points of the field per cell)
-template <typename T>
-hipError_t run_fd_eq(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s) {
+// depth 0: no Laplacian (the stencil is unused); depth 1: one; the deeper
+// level from an array (q.w) or from the fields; one or two fields
+template <typename T, int NF>
+hipError_t run_fd_eq_nf(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s) {
   const int64_t n = a.nx * a.ny * a.nz;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-#define SS_FDEQ(D, S, P) \
-  if (dim == D && stencil == S && depth == P) return launch_with(fd_eq_kernel<T, D, S, P>, grid, block, 0, s, LaunchEvents(), a, q);
+  const bool lw = q.w[0] != nullptr;
+#define SS_FDEQ(D, S, P)                                                                                 \
+  if (dim == D && stencil == S && depth == P)                                                            \
+    return lw ? launch_with(fd_eq_kernel<T, D, S, P, true, NF>, grid, block, 0, s, LaunchEvents(), a, q) \
+              : launch_with(fd_eq_kernel<T, D, S, P, false, NF>, grid, block, 0, s, LaunchEvents(), a, q);
   if (depth == 0) {
-    if (dim == 2) return launch_with(fd_eq_kernel<T, 2, 0, 0>, grid, block, 0, s, LaunchEvents(), a, q);
-    return launch_with(fd_eq_kernel<T, 3, 0, 0>, grid, block, 0, s, LaunchEvents(), a, q);
+    if (dim == 2) return launch_with(fd_eq_kernel<T, 2, 0, 0, false, NF>, grid, block, 0, s, LaunchEvents(), a, q);
+    return launch_with(fd_eq_kernel<T, 3, 0, 0, false, NF>, grid, block, 0, s, LaunchEvents(), a, q);
   }
-  SS_FDEQ(2, 0, 1) SS_FDEQ(2, 0, 2) SS_FDEQ(2, 9, 1) SS_FDEQ(2, 4, 1)
+  SS_FDEQ(2, 0, 1) SS_FDEQ(2, 9, 1) SS_FDEQ(2, 4, 1)
   SS_FDEQ(3, 0, 1) SS_FDEQ(3, 19, 1) SS_FDEQ(3, 27, 1) SS_FDEQ(3, 4, 1)
 #undef SS_FDEQ
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t run_fd_eq(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s) {
+  return a.in[1] ? run_fd_eq_nf<T, 2>(dim, stencil, depth, a, q, s) : run_fd_eq_nf<T, 1>(dim, stencil, depth, a, q, s);
 }
 
 template <typename T>

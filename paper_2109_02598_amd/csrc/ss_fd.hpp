@@ -36,9 +36,10 @@
 //   sum_p c_p L^p psi_j + L^p_j E_j(psi)
 // is written as nested levels, v_D = c_D psi_j (+ E_j) and
 //   v_k = c_k psi_j (+ E_j if p_j = k) + L v_{k+1},
-// so that v_0 is the right-hand side.  One launch evaluates DEPTH nested
-// levels, the deepest read from an array written by the launch before it,
-// or evaluated pointwise from the fields when it is the top level.
+// so that v_0 is the right-hand side.  One launch evaluates one level from
+// the next (DEPTH = 1), which is read from the array the launch before it
+// wrote, or evaluated pointwise from the fields when it is the top level;
+// a level with no Laplacian below it is DEPTH = 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -115,108 +116,152 @@ __device__ __forceinline__ T fd_mu_ch(const T* __restrict__ f, int64_t x, int64_
   return c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(f, x, y, z, a);
 }
 
-// The explicit terms of one field, E = sum_k f1^k sum_i a[k][i] f0^i,
-// i <= du[k], k <= dv (Horner in f0 inside Horner in f1).
-struct FDEq {
-  int nj;               // fields this launch computes (1 or 2)
-  int j[2];             // which fields
-  int fin;              // 1: out = psi_j + dt v_0; 0: out = v_0
-  double cl[2][3];      // coefficient of psi_j at nested level d (0: the output)
-  int el[2][3];         // 1: E_j is added at nested level d
-  const void* w[2];     // deepest level from this array, or null: pointwise
-  void* out[2];
+// The explicit terms of field j, E = sum_k f1^k sum_i a[j][k][i] f0^i,
+// i <= du[j][k], k <= dv[j] (Horner in f0 inside Horner in f1), read from
+// the kernel arguments by every lane at the same addresses (scalar loads:
+// the loop bounds and guards are uniform branches).
+struct FDEqTab {
   int dv[2];
   int du[2][8];
   double a[2][8][8];
   float af[2][8][8];
 };
 
-// The table of the explicit terms, staged in LDS (read with uniform
-// addresses), and one slot's coefficients, held in registers.
-template <typename T>
-struct FDEqTab {
-  T a[2][8][8];
-  int du[2][8];
-  int dv[2];
+struct FDEq {
+  int nj;               // fields this launch computes (1 or 2)
+  int j[2];             // which fields
+  int fin;              // 1: out = psi_j + dt v_0; 0: out = v_0
+  double cl[2][2];      // coefficient of psi_j at nested level d (0: the output)
+  int el[2][2];         // 1: E_j is added at nested level d
+  const void* w[2];     // deepest level from this array, or null: pointwise
+  void* out[2];
+  FDEqTab tab;
 };
 
 template <typename T>
 struct FDEqSlot {
-  const T* f[2];        // the fields
+  const T* f0;          // the fields
+  const T* f1;
+  const T* fj;          // field j
   const T* w;
-  T cl[3];
-  int el[3];
+  T cl[2];
+  int el[2];
   int j;
 };
 
 template <typename T>
-__device__ __forceinline__ T fd_eq_E(const FDEqTab<T>* tb, int j, T u, T v) {
+__device__ __forceinline__ T fd_eq_E(const FDEqTab* tb, int j, T u, T v) {
   T acc = (T)0;
-  for (int k = tb->dv[j]; k >= 0; --k) {
+  const int dv = tb->dv[j];
+#pragma unroll 1
+  for (int k = dv; k >= 0; --k) {
     const int dk = tb->du[j][k];
+    T c[8];   // the row, read whole ahead of the guards
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = sizeof(T) == 8 ? (T)tb->a[j][k][i] : (T)tb->af[j][k][i];
     T h = (T)0;
 #pragma unroll
     for (int i = 7; i >= 0; --i)
-      if (i <= dk) h = h * u + tb->a[j][k][i];
+      if (i <= dk) h = h * u + c[i];
     acc = acc * v + h;
   }
   return acc;
 }
 
-// Nested level D at cell (x, y, z) (coordinates may lie outside the grid:
-// they wrap).
-template <typename T, int DIM, int ST, int D, int DEPTH>
-__device__ __forceinline__ T fd_eq_level(const FDArgs& a, const FDEqTab<T>* tb, const FDEqSlot<T>& sl,
-                                         int64_t x, int64_t y, int64_t z) {
-  const int64_t i = ((((z & (a.nz - 1)) * a.ny + (y & (a.ny - 1))) << a.lx) + (x & (a.nx - 1)));
-  if constexpr (D == DEPTH) {
-    if (sl.w) return sl.w[i];
+// The axis-wise Laplacian of E_j around (x, y, z): E at the 2 DIM + 1
+// points evaluated together (one pass over the table serves every point).
+template <typename T, int DIM, int NF>
+__device__ __forceinline__ T fd_eq_lapE(const FDArgs& a, const FDEqTab* tb, const FDEqSlot<T>& sl,
+                                        int64_t x, int64_t y, int64_t z) {
+  constexpr int P = 2 * DIM + 1;
+  const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
+  T u[P], w[P], acc[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int ax = (p - 1) >> 1;                      // axis of point p (p > 0)
+    const int64_t o = p == 0 ? 0 : ((p & 1) ? -1 : 1);
+    const int64_t xx = x + (ax == 0 ? o : 0), yy = y + (ax == 1 ? o : 0), zz = z + (ax == 2 ? o : 0);
+    const int64_t i = ((((zz & mz) * a.ny + (yy & my)) << a.lx) + (xx & mx));
+    u[p] = sl.f0[i];
+    w[p] = NF == 2 ? sl.f1[i] : (T)0;
+    acc[p] = (T)0;
   }
-  T v = (T)0;
-  if (sl.cl[D] != (T)0) v = sl.cl[D] * sl.f[sl.j][i];
-  // E away from the centre only with the axis-wise stencil (the launches of
-  // the wider stencils put E at a level of its own)
-  if constexpr (D == 0 || ST == 0)
-    if (sl.el[D]) v += fd_eq_E<T>(tb, sl.j, sl.f[0][i], sl.f[1] ? sl.f[1][i] : (T)0);
-  if constexpr (D < DEPTH) {
-    auto next = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-      return fd_eq_level<T, DIM, ST, D + 1, DEPTH>(a, tb, sl, x + dx, y + dy, z + dz);
-    };
-    v += fd_stencil<T, DIM, ST>(next, a);
+  const int j = sl.j;
+  const int dv = tb->dv[j];
+#pragma unroll 1
+  for (int k = dv; k >= 0; --k) {
+    const int dk = tb->du[j][k];
+    T c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = sizeof(T) == 8 ? (T)tb->a[j][k][i] : (T)tb->af[j][k][i];
+    T h[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) h[p] = (T)0;
+#pragma unroll
+    for (int i = 7; i >= 0; --i)
+      if (i <= dk) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) h[p] = h[p] * u[p] + c[i];
+      }
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p] = acc[p] * w[p] + h[p];
   }
-  return v;
+  T s = (acc[1] + acc[2] - (T)2 * acc[0]) * (T)a.ih2[0] + (acc[3] + acc[4] - (T)2 * acc[0]) * (T)a.ih2[1];
+  if constexpr (DIM == 3) s += (acc[5] + acc[6] - (T)2 * acc[0]) * (T)a.ih2[2];
+  return s;
 }
 
-template <typename T, int DIM, int ST, int DEPTH>
-__global__ void __launch_bounds__(256) fd_eq_kernel(FDArgs a, FDEq q) {
-  __shared__ FDEqTab<T> tb;
-  const int t = threadIdx.x;
-  if (t < 128) {
-    const int j = t >> 6, k = (t >> 3) & 7, m = t & 7;
-    tb.a[j][k][m] = sizeof(T) == 8 ? (T)q.a[j][k][m] : (T)q.af[j][k][m];
-  } else if (t < 144) {
-    tb.du[(t - 128) >> 3][t & 7] = q.du[(t - 128) >> 3][t & 7];
-  } else if (t < 146) {
-    tb.dv[t - 144] = q.dv[t - 144];
+// Nested level D at cell (x, y, z) (coordinates may lie outside the grid:
+// they wrap).  LW: the deepest level comes from the array w; NF fields.
+// The loads do not depend on the coefficients, so that a stencil's loads
+// issue together.  E_j enters at the centre (D = 0) directly and, with
+// the axis-wise stencil, one level down as the Laplacian of E evaluated at
+// the stencil's points together (the launches of the wider stencils put E
+// at a level of their own, always the centre).
+template <typename T, int DIM, int ST, int D, int DEPTH, bool LW, int NF>
+__device__ __forceinline__ T fd_eq_level(const FDArgs& a, const FDEqTab* tb, const FDEqSlot<T>& sl,
+                                         int64_t x, int64_t y, int64_t z) {
+  const int64_t i = ((((z & (a.nz - 1)) * a.ny + (y & (a.ny - 1))) << a.lx) + (x & (a.nx - 1)));
+  if constexpr (D == DEPTH && LW) {
+    return sl.w[i];
+  } else {
+    const T u = sl.f0[i], w = NF == 2 ? sl.f1[i] : (T)0;
+    T v = sl.cl[D] * (NF == 1 || sl.j == 0 ? u : w);
+    if constexpr (D == 0)
+      if (sl.el[0]) v += fd_eq_E<T>(tb, sl.j, u, w);
+    if constexpr (D < DEPTH) {
+      auto next = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+        return fd_eq_level<T, DIM, ST, D + 1, DEPTH, LW, NF>(a, tb, sl, x + dx, y + dy, z + dz);
+      };
+      v += fd_stencil<T, DIM, ST>(next, a);
+      if constexpr (ST == 0 && !(LW && D + 1 == DEPTH))
+        if (sl.el[D + 1]) v += fd_eq_lapE<T, DIM, NF>(a, tb, sl, x, y, z);
+    }
+    return v;
   }
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + t;
+}
+
+template <typename T, int DIM, int ST, int DEPTH, bool LW, int NF>
+__global__ void __launch_bounds__(256) fd_eq_kernel(FDArgs a, FDEq q) {
+  const FDEqTab* tb = &q.tab;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (a.nx * a.ny * a.nz)) return;
   const int64_t x = i & (a.nx - 1);
   const int64_t y = (i >> a.lx) & (a.ny - 1);
   const int64_t z = i >> a.lxy;
   for (int s = 0; s < q.nj; ++s) {
     FDEqSlot<T> sl;
-    sl.f[0] = (const T*)a.in[0];
-    sl.f[1] = (const T*)a.in[1];
+    sl.f0 = (const T*)a.in[0];
+    sl.f1 = (const T*)a.in[1];
     sl.w = (const T*)q.w[s];
     sl.j = q.j[s];
-    for (int d = 0; d < 3; ++d) {
+    sl.fj = sl.j == 0 ? sl.f0 : sl.f1;
+    for (int d = 0; d < 2; ++d) {
       sl.cl[d] = (T)q.cl[s][d];
       sl.el[d] = q.el[s][d];
     }
-    T v = fd_eq_level<T, DIM, ST, 0, DEPTH>(a, &tb, sl, x, y, z);
-    if (q.fin) v = sl.f[sl.j][i] + (T)a.dt * v;
+    T v = fd_eq_level<T, DIM, ST, 0, DEPTH, LW, NF>(a, tb, sl, x, y, z);
+    if (q.fin) v = sl.fj[i] + (T)a.dt * v;
     ((T*)q.out[s])[i] = v;
   }
 }
