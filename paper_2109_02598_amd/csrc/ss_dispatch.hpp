@@ -285,17 +285,26 @@ hipError_t run_sfreduce(SFArgs a, hipStream_t s) {
                      LaunchEvents(), a);
 }
 
+// Cells along y per thread, measured per stencil (CH, FP64, 2048^2 and
+// 256^3): one in 2D (two or four were within 3%, and slower for model C);
+// in 3D the wide stencils gain most from the shared loads (27-point 901 ->
+// 650 us per step with four, fourth order 464 -> 366 with two).
+template <typename T, int DIM, int ST, int R>
+hipError_t launch_fd(FDArgs a, hipStream_t s) {
+  const int64_t n = a.nx * a.ny * a.nz / R;
+  if (a.ny % R) return hipErrorInvalidValue;
+  return launch_with(fd_kernel<T, DIM, ST, R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, LaunchEvents(), a);
+}
+
 template <typename T>
 hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
-  const int64_t n = a.nx * a.ny * a.nz;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  if (dim == 2 && stencil == 0) return launch_with(fd_kernel<T, 2, 0>, grid, block, 0, s, LaunchEvents(), a);
-  if (dim == 2 && stencil == 9) return launch_with(fd_kernel<T, 2, 9>, grid, block, 0, s, LaunchEvents(), a);
-  if (dim == 3 && stencil == 0) return launch_with(fd_kernel<T, 3, 0>, grid, block, 0, s, LaunchEvents(), a);
-  if (dim == 3 && stencil == 19) return launch_with(fd_kernel<T, 3, 19>, grid, block, 0, s, LaunchEvents(), a);
-  if (dim == 3 && stencil == 27) return launch_with(fd_kernel<T, 3, 27>, grid, block, 0, s, LaunchEvents(), a);
-  if (dim == 2 && stencil == 4) return launch_with(fd_kernel<T, 2, 4>, grid, block, 0, s, LaunchEvents(), a);
-  if (dim == 3 && stencil == 4) return launch_with(fd_kernel<T, 3, 4>, grid, block, 0, s, LaunchEvents(), a);
+  if (dim == 2 && stencil == 0) return launch_fd<T, 2, 0, 1>(a, s);
+  if (dim == 2 && stencil == 9) return launch_fd<T, 2, 9, 1>(a, s);
+  if (dim == 2 && stencil == 4) return launch_fd<T, 2, 4, 1>(a, s);
+  if (dim == 3 && stencil == 0) return launch_fd<T, 3, 0, 2>(a, s);
+  if (dim == 3 && stencil == 19) return launch_fd<T, 3, 19, 1>(a, s);
+  if (dim == 3 && stencil == 27) return launch_fd<T, 3, 27, 4>(a, s);
+  if (dim == 3 && stencil == 4) return launch_fd<T, 3, 4, 2>(a, s);
   return hipErrorInvalidValue;
 }
 

@@ -14,8 +14,8 @@
 //           (-f[-2] + 16 f[-1] - 30 f + 16 f[+1] - f[+2]) / (12 h_a^2).
 // The leading error of the isotropic stencils depends on |k| only.
 //
-// One launch applies one operation at every cell (thread per cell, x
-// fastest).  A step is one to three launches, by model (the forms of the
+// One launch applies one operation at every cell (a thread per R cells
+// along y, x fastest across threads).  A step is one to three launches, by model (the forms of the
 // right-hand sides are those of the equations of motion of Sec. 3):
 //   FD_AC     psi' = psi + dt M (kappa L psi + c1 psi - c2 psi^3)
 //   FD_GS     u' = u + dt (Du L u - u v^2 + F (1 - u)),
@@ -266,68 +266,93 @@ __global__ void __launch_bounds__(256) fd_eq_kernel(FDArgs a, FDEq q) {
   }
 }
 
-template <typename T, int DIM, int ST>
+// A thread steps R consecutive cells along y (same x, same z): the loads
+// that neighbouring cells share are issued once (R divides ny; ny >= 8).
+template <typename T, int DIM, int ST, int R>
 __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (a.nx * a.ny * a.nz)) return;
-  const int64_t x = i & (a.nx - 1);
-  const int64_t y = (i >> a.lx) & (a.ny - 1);
-  const int64_t z = i >> a.lxy;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t * R >= (a.nx * a.ny * a.nz)) return;
+  constexpr int LR = R == 1 ? 0 : R == 2 ? 1 : R == 4 ? 2 : 3;
+  const int64_t x = t & (a.nx - 1);
+  const int64_t row = t >> a.lx;                          // over (ny / R) * nz
+  const int64_t y0 = (row & ((a.ny >> LR) - 1)) << LR;
+  const int64_t z = row >> (a.lxy - a.lx - LR);
   const T* in0 = (const T*)a.in[0];
   const T* in1 = (const T*)a.in[1];
   T* out0 = (T*)a.out[0];
   T* out1 = (T*)a.out[1];
   const T dt = (T)a.dt;
+  // the operation's body over the thread's R cells, unrolled in one block
+  auto cells = [&](auto&& body) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t y = y0 + r;
+      body((((z * a.ny) + y) << a.lx) + x, y);
+    }
+  };
   switch (a.op) {
     case FD_AC: {
       const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      const T q = in0[i];
-      out0[i] = q + dt * (M * (kap * fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q));
+      cells([&](int64_t i, int64_t y) {
+        const T q = in0[i];
+        out0[i] = q + dt * (M * (kap * fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q));
+      });
       break;
     }
     case FD_GS: {
       const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
-      const T u = in0[i], v = in1[i];
-      const T uvv = u * v * v;
-      out0[i] = u + dt * (du * fd_lap<T, DIM, ST>(in0, x, y, z, a) - uvv + F * ((T)1 - u));
-      out1[i] = v + dt * (dv * fd_lap<T, DIM, ST>(in1, x, y, z, a) + uvv - (F + kk) * v);
+      cells([&](int64_t i, int64_t y) {
+        const T u = in0[i], v = in1[i];
+        const T uvv = u * v * v;
+        out0[i] = u + dt * (du * fd_lap<T, DIM, ST>(in0, x, y, z, a) - uvv + F * ((T)1 - u));
+        out1[i] = v + dt * (dv * fd_lap<T, DIM, ST>(in1, x, y, z, a) + uvv - (F + kk) * v);
+      });
       break;
     }
     case FD_MU_CH: {
       const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      const T q = in0[i];
-      out0[i] = c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(in0, x, y, z, a);
+      cells([&](int64_t i, int64_t y) {
+        const T q = in0[i];
+        out0[i] = c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(in0, x, y, z, a);
+      });
       break;
     }
     case FD_UPD: {
-      out0[i] = in0[i] + dt * ((T)a.p[0] * fd_lap<T, DIM, ST>(in1, x, y, z, a));
+      const T s0 = (T)a.p[0];
+      cells([&](int64_t i, int64_t y) { out0[i] = in0[i] + dt * (s0 * fd_lap<T, DIM, ST>(in1, x, y, z, a)); });
       break;
     }
     case FD_LAP: {
-      out0[i] = fd_lap<T, DIM, ST>(in0, x, y, z, a);
+      cells([&](int64_t i, int64_t y) { out0[i] = fd_lap<T, DIM, ST>(in0, x, y, z, a); });
       break;
     }
     case FD_MU_PFC: {
       const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
-      const T q = in0[i], lq = in1[i];
       const T q02 = q0 * q0;
-      out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + fd_lap<T, DIM, ST>(in1, x, y, z, a) + g2 * q * q +
-                g3 * q * q * q;
+      cells([&](int64_t i, int64_t y) {
+        const T q = in0[i], lq = in1[i];
+        out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + fd_lap<T, DIM, ST>(in1, x, y, z, a) + g2 * q * q +
+                  g3 * q * q * q;
+      });
       break;
     }
     case FD_CH: {
       const T M = (T)a.p[0];
-      auto mu_at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-        return fd_mu_ch<T, DIM, ST>(in0, x + dx, y + dy, z + dz, a);
-      };
-      out0[i] = in0[i] + dt * (M * fd_stencil<T, DIM, ST>(mu_at, a));
+      cells([&](int64_t i, int64_t y) {
+        auto mu_at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+          return fd_mu_ch<T, DIM, ST>(in0, x + dx, y + dy, z + dz, a);
+        };
+        out0[i] = in0[i] + dt * (M * fd_stencil<T, DIM, ST>(mu_at, a));
+      });
       break;
     }
     default: {  // FD_MC
       const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
-      const T q = in0[i], m = in1[i];
-      out0[i] = q + dt * (fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q + (T)2 * c5 * q * m);
-      out1[i] = -fd_lap<T, DIM, ST>(in1, x, y, z, a) - c3 * m + c4 * m * m * m - c5 * q * q;
+      cells([&](int64_t i, int64_t y) {
+        const T q = in0[i], m = in1[i];
+        out0[i] = q + dt * (fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q + (T)2 * c5 * q * m);
+        out1[i] = -fd_lap<T, DIM, ST>(in1, x, y, z, a) - c3 * m + c4 * m * m * m - c5 * q * q;
+      });
       break;
     }
   }
