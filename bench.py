@@ -224,11 +224,21 @@ def run_adjoint(steps=200, K=20, dtype="f32"):
 def run_euler(w, dtype, steps=500):
     """The forward-Euler finite-difference solver on the same grid and
     fields (axis-wise, isotropic and fourth-order Laplacians), with the
-    fixed-model kernels and with the model's equation read at run time.  With the 2D
-    axis-wise stencil a Cahn-Hilliard step is one launch that recomputes mu
-    at the stencil points from psi (one array read, one written); the
-    other stencils take two launches, mu from psi, then psi + dt M L mu
-    (5 arrays)."""
+    fixed-model kernels and with the model's equation read at run time; for
+    a 2D workload also Cahn-Hilliard on 256^3 with the 3D stencils.  With
+    the 2D axis-wise stencil a Cahn-Hilliard step is one launch that
+    recomputes mu at the stencil points from psi (one array read, one
+    written); the other stencils take two launches, mu from psi, then
+    psi + dt M L mu (5 arrays)."""
+    from paper_2109_02598_amd import inputs
+    out = euler_times(w, dtype, steps)
+    if len(w.n) == 2:
+        w3 = inputs.cahn_hilliard_3d(n=256)
+        out["3d"] = euler_times(w3, dtype, 200)
+    return out
+
+
+def euler_times(w, dtype, steps):
     import torch
     from paper_2109_02598_amd import specstep
     out = {"workload": "%s, forward Euler, %s, %d steps (dt 0.01)" % (w.name, dtype, steps)}

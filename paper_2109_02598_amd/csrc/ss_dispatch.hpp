@@ -285,26 +285,43 @@ hipError_t run_sfreduce(SFArgs a, hipStream_t s) {
                      LaunchEvents(), a);
 }
 
-// Cells along y per thread, measured per stencil (CH, FP64, 2048^2 and
-// 256^3): one in 2D (two or four were within 3%, and slower for model C);
-// in 3D the wide stencils gain most from the shared loads (27-point 901 ->
-// 650 us per step with four, fourth order 464 -> 366 with two).
-template <typename T, int DIM, int ST, int R>
+// Cells along y per thread, chosen per stencil by measurement (CH, FP64,
+// 2048^2 and 256^3; 1, 2 and 4 tried): two for the stencils whose loads
+// along y overlap most per register spent (2D 9-point and fourth order,
+// 3D axis-wise and fourth order), one otherwise.
+constexpr int fd_rows(int dim, int st) {
+  return dim == 2 ? (st == 0 ? 1 : 2) : (st == 0 || st == 4) ? 2 : 1;
+}
+
+template <typename T, int DIM, int ST>
 hipError_t launch_fd(FDArgs a, hipStream_t s) {
+  constexpr int R = fd_rows(DIM, ST);
   const int64_t n = a.nx * a.ny * a.nz / R;
   if (a.ny % R) return hipErrorInvalidValue;
-  return launch_with(fd_kernel<T, DIM, ST, R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, LaunchEvents(), a);
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define SS_FDOP(OP) \
+  case OP: return launch_with(fd_kernel<T, DIM, ST, R, OP>, grid, block, 0, s, LaunchEvents(), a);
+  switch (a.op) {
+    SS_FDOP(FD_AC) SS_FDOP(FD_GS) SS_FDOP(FD_MU_CH) SS_FDOP(FD_UPD) SS_FDOP(FD_LAP) SS_FDOP(FD_MU_PFC)
+    SS_FDOP(FD_MC)
+    case FD_CH:   // the fused Cahn-Hilliard step: 2D axis-wise only
+      if constexpr (DIM == 2 && ST == 0)
+        return launch_with(fd_kernel<T, DIM, ST, R, FD_CH>, grid, block, 0, s, LaunchEvents(), a);
+      return hipErrorInvalidValue;
+  }
+#undef SS_FDOP
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
-  if (dim == 2 && stencil == 0) return launch_fd<T, 2, 0, 1>(a, s);
-  if (dim == 2 && stencil == 9) return launch_fd<T, 2, 9, 1>(a, s);
-  if (dim == 2 && stencil == 4) return launch_fd<T, 2, 4, 1>(a, s);
-  if (dim == 3 && stencil == 0) return launch_fd<T, 3, 0, 2>(a, s);
-  if (dim == 3 && stencil == 19) return launch_fd<T, 3, 19, 1>(a, s);
-  if (dim == 3 && stencil == 27) return launch_fd<T, 3, 27, 4>(a, s);
-  if (dim == 3 && stencil == 4) return launch_fd<T, 3, 4, 2>(a, s);
+  if (dim == 2 && stencil == 0) return launch_fd<T, 2, 0>(a, s);
+  if (dim == 2 && stencil == 9) return launch_fd<T, 2, 9>(a, s);
+  if (dim == 2 && stencil == 4) return launch_fd<T, 2, 4>(a, s);
+  if (dim == 3 && stencil == 0) return launch_fd<T, 3, 0>(a, s);
+  if (dim == 3 && stencil == 19) return launch_fd<T, 3, 19>(a, s);
+  if (dim == 3 && stencil == 27) return launch_fd<T, 3, 27>(a, s);
+  if (dim == 3 && stencil == 4) return launch_fd<T, 3, 4>(a, s);
   return hipErrorInvalidValue;
 }
 

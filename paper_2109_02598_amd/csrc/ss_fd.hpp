@@ -268,7 +268,9 @@ __global__ void __launch_bounds__(256) fd_eq_kernel(FDArgs a, FDEq q) {
 
 // A thread steps R consecutive cells along y (same x, same z): the loads
 // that neighbouring cells share are issued once (R divides ny; ny >= 8).
-template <typename T, int DIM, int ST, int R>
+// OP is a template parameter: each kernel holds the registers of its own
+// operation only.
+template <typename T, int DIM, int ST, int R, int OP>
 __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t * R >= (a.nx * a.ny * a.nz)) return;
@@ -290,71 +292,54 @@ __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
       body((((z * a.ny) + y) << a.lx) + x, y);
     }
   };
-  switch (a.op) {
-    case FD_AC: {
-      const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      cells([&](int64_t i, int64_t y) {
-        const T q = in0[i];
-        out0[i] = q + dt * (M * (kap * fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q));
-      });
-      break;
-    }
-    case FD_GS: {
-      const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
-      cells([&](int64_t i, int64_t y) {
-        const T u = in0[i], v = in1[i];
-        const T uvv = u * v * v;
-        out0[i] = u + dt * (du * fd_lap<T, DIM, ST>(in0, x, y, z, a) - uvv + F * ((T)1 - u));
-        out1[i] = v + dt * (dv * fd_lap<T, DIM, ST>(in1, x, y, z, a) + uvv - (F + kk) * v);
-      });
-      break;
-    }
-    case FD_MU_CH: {
-      const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      cells([&](int64_t i, int64_t y) {
-        const T q = in0[i];
-        out0[i] = c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(in0, x, y, z, a);
-      });
-      break;
-    }
-    case FD_UPD: {
-      const T s0 = (T)a.p[0];
-      cells([&](int64_t i, int64_t y) { out0[i] = in0[i] + dt * (s0 * fd_lap<T, DIM, ST>(in1, x, y, z, a)); });
-      break;
-    }
-    case FD_LAP: {
-      cells([&](int64_t i, int64_t y) { out0[i] = fd_lap<T, DIM, ST>(in0, x, y, z, a); });
-      break;
-    }
-    case FD_MU_PFC: {
-      const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
-      const T q02 = q0 * q0;
-      cells([&](int64_t i, int64_t y) {
-        const T q = in0[i], lq = in1[i];
-        out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + fd_lap<T, DIM, ST>(in1, x, y, z, a) + g2 * q * q +
-                  g3 * q * q * q;
-      });
-      break;
-    }
-    case FD_CH: {
-      const T M = (T)a.p[0];
-      cells([&](int64_t i, int64_t y) {
-        auto mu_at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-          return fd_mu_ch<T, DIM, ST>(in0, x + dx, y + dy, z + dz, a);
-        };
-        out0[i] = in0[i] + dt * (M * fd_stencil<T, DIM, ST>(mu_at, a));
-      });
-      break;
-    }
-    default: {  // FD_MC
-      const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
-      cells([&](int64_t i, int64_t y) {
-        const T q = in0[i], m = in1[i];
-        out0[i] = q + dt * (fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q + (T)2 * c5 * q * m);
-        out1[i] = -fd_lap<T, DIM, ST>(in1, x, y, z, a) - c3 * m + c4 * m * m * m - c5 * q * q;
-      });
-      break;
-    }
+  if constexpr (OP == FD_AC) {
+    const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+    cells([&](int64_t i, int64_t y) {
+      const T q = in0[i];
+      out0[i] = q + dt * (M * (kap * fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q));
+    });
+  } else if constexpr (OP == FD_GS) {
+    const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
+    cells([&](int64_t i, int64_t y) {
+      const T u = in0[i], v = in1[i];
+      const T uvv = u * v * v;
+      out0[i] = u + dt * (du * fd_lap<T, DIM, ST>(in0, x, y, z, a) - uvv + F * ((T)1 - u));
+      out1[i] = v + dt * (dv * fd_lap<T, DIM, ST>(in1, x, y, z, a) + uvv - (F + kk) * v);
+    });
+  } else if constexpr (OP == FD_MU_CH) {
+    const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+    cells([&](int64_t i, int64_t y) {
+      const T q = in0[i];
+      out0[i] = c2 * q * q * q - c1 * q - kap * fd_lap<T, DIM, ST>(in0, x, y, z, a);
+    });
+  } else if constexpr (OP == FD_UPD) {
+    const T s0 = (T)a.p[0];
+    cells([&](int64_t i, int64_t y) { out0[i] = in0[i] + dt * (s0 * fd_lap<T, DIM, ST>(in1, x, y, z, a)); });
+  } else if constexpr (OP == FD_LAP) {
+    cells([&](int64_t i, int64_t y) { out0[i] = fd_lap<T, DIM, ST>(in0, x, y, z, a); });
+  } else if constexpr (OP == FD_MU_PFC) {
+    const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
+    const T q02 = q0 * q0;
+    cells([&](int64_t i, int64_t y) {
+      const T q = in0[i], lq = in1[i];
+      out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + fd_lap<T, DIM, ST>(in1, x, y, z, a) + g2 * q * q +
+                g3 * q * q * q;
+    });
+  } else if constexpr (OP == FD_CH) {
+    const T M = (T)a.p[0];
+    cells([&](int64_t i, int64_t y) {
+      auto mu_at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+        return fd_mu_ch<T, DIM, ST>(in0, x + dx, y + dy, z + dz, a);
+      };
+      out0[i] = in0[i] + dt * (M * fd_stencil<T, DIM, ST>(mu_at, a));
+    });
+  } else {  // FD_MC
+    const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
+    cells([&](int64_t i, int64_t y) {
+      const T q = in0[i], m = in1[i];
+      out0[i] = q + dt * (fd_lap<T, DIM, ST>(in0, x, y, z, a) + c1 * q - c2 * q * q * q + (T)2 * c5 * q * m);
+      out1[i] = -fd_lap<T, DIM, ST>(in1, x, y, z, a) - c3 * m + c4 * m * m * m - c5 * q * q;
+    });
   }
 }
 

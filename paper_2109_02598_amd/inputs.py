@@ -118,6 +118,15 @@ def cahn_hilliard_2d(n=2048, seed=2, steps=1000) -> Workload:
                     [uniform_field(seed, shape, -0.05, 0.05)])
 
 
+def cahn_hilliard_3d(n=256, seed=9, steps=500) -> Workload:
+    """3D Cahn-Hilliard, dx=1, dt=0.01, M=kappa=c1=c2=1, phi ~ U[-0.05, 0.05)
+    (the forward-Euler solver's 3D case)."""
+    shape = (n, n, n)
+    return Workload("cahn_hilliard_%d^3" % n, "cahn_hilliard", (n, n, n),
+                    (1.0, 1.0, 1.0), 0.01, (1.0, 1.0, 1.0, 1.0), steps,
+                    [uniform_field(seed, shape, -0.05, 0.05)])
+
+
 def pfc_3d(n=256, seed=3, steps=500) -> Workload:
     """3D phase-field crystal, dx=pi/4, dt=0.5, r=-0.25, q0=1, g2=0, g3=1.
 
