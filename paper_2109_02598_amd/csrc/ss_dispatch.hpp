@@ -329,16 +329,19 @@ hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
 // level from an array (q.w) or from the fields; one or two fields
 template <typename T, int NF>
 hipError_t run_fd_eq_nf(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s) {
-  const int64_t n = a.nx * a.ny * a.nz;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   const bool lw = q.w[0] != nullptr;
-#define SS_FDEQ(D, S, P)                                                                                 \
-  if (dim == D && stencil == S && depth == P)                                                            \
-    return lw ? launch_with(fd_eq_kernel<T, D, S, P, true, NF>, grid, block, 0, s, LaunchEvents(), a, q) \
-              : launch_with(fd_eq_kernel<T, D, S, P, false, NF>, grid, block, 0, s, LaunchEvents(), a, q);
+  const dim3 block(256);
+  auto grid = [&](int R) { return dim3((unsigned)((a.nx * a.ny * a.nz / R + 255) / 256)); };
+#define SS_FDEQ(D, S, P)                                                                                        \
+  if (dim == D && stencil == S && depth == P) {                                                                \
+    constexpr int R = fd_rows(D, S);                                                                           \
+    if (a.ny % R) return hipErrorInvalidValue;                                                                 \
+    return lw ? launch_with(fd_eq_kernel<T, D, S, P, true, NF, R>, grid(R), block, 0, s, LaunchEvents(), a, q)  \
+              : launch_with(fd_eq_kernel<T, D, S, P, false, NF, R>, grid(R), block, 0, s, LaunchEvents(), a, q); \
+  }
   if (depth == 0) {
-    if (dim == 2) return launch_with(fd_eq_kernel<T, 2, 0, 0, false, NF>, grid, block, 0, s, LaunchEvents(), a, q);
-    return launch_with(fd_eq_kernel<T, 3, 0, 0, false, NF>, grid, block, 0, s, LaunchEvents(), a, q);
+    if (dim == 2) return launch_with(fd_eq_kernel<T, 2, 0, 0, false, NF, 1>, grid(1), block, 0, s, LaunchEvents(), a, q);
+    return launch_with(fd_eq_kernel<T, 3, 0, 0, false, NF, 1>, grid(1), block, 0, s, LaunchEvents(), a, q);
   }
   SS_FDEQ(2, 0, 1) SS_FDEQ(2, 9, 1) SS_FDEQ(2, 4, 1)
   SS_FDEQ(3, 0, 1) SS_FDEQ(3, 19, 1) SS_FDEQ(3, 27, 1) SS_FDEQ(3, 4, 1)

@@ -241,14 +241,16 @@ __device__ __forceinline__ T fd_eq_level(const FDArgs& a, const FDEqTab* tb, con
   }
 }
 
-template <typename T, int DIM, int ST, int DEPTH, bool LW, int NF>
+template <typename T, int DIM, int ST, int DEPTH, bool LW, int NF, int R>
 __global__ void __launch_bounds__(256) fd_eq_kernel(FDArgs a, FDEq q) {
   const FDEqTab* tb = &q.tab;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (a.nx * a.ny * a.nz)) return;
-  const int64_t x = i & (a.nx - 1);
-  const int64_t y = (i >> a.lx) & (a.ny - 1);
-  const int64_t z = i >> a.lxy;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t * R >= (a.nx * a.ny * a.nz)) return;
+  constexpr int LR = R == 1 ? 0 : R == 2 ? 1 : R == 4 ? 2 : 3;
+  const int64_t x = t & (a.nx - 1);
+  const int64_t row = t >> a.lx;                          // over (ny / R) * nz
+  const int64_t y0 = (row & ((a.ny >> LR) - 1)) << LR;
+  const int64_t z = row >> (a.lxy - a.lx - LR);
   for (int s = 0; s < q.nj; ++s) {
     FDEqSlot<T> sl;
     sl.f0 = (const T*)a.in[0];
@@ -260,9 +262,15 @@ __global__ void __launch_bounds__(256) fd_eq_kernel(FDArgs a, FDEq q) {
       sl.cl[d] = (T)q.cl[s][d];
       sl.el[d] = q.el[s][d];
     }
-    T v = fd_eq_level<T, DIM, ST, 0, DEPTH, LW, NF>(a, tb, sl, x, y, z);
-    if (q.fin) v = sl.fj[i] + (T)a.dt * v;
-    ((T*)q.out[s])[i] = v;
+    // the thread's R cells along y, unrolled in one block (shared loads once)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t y = y0 + r;
+      const int64_t i = (((z * a.ny) + y) << a.lx) + x;
+      T v = fd_eq_level<T, DIM, ST, 0, DEPTH, LW, NF>(a, tb, sl, x, y, z);
+      if (q.fin) v = sl.fj[i] + (T)a.dt * v;
+      ((T*)q.out[s])[i] = v;
+    }
   }
 }
 
