@@ -122,3 +122,49 @@ def test_gray_scott_512(dtype):
         err = rel_l2(got[i], want[i])
         say("gray_scott 512^2", dtype, steps, "steps field", i, "rel_l2 %.3e" % err)
         assert err <= TOL[dtype]
+
+
+# ---- forward-Euler finite differences at the sizes the benchmark times ------
+
+from oracle import fd_euler  # noqa: E402
+from oracle import operator_split as osp  # noqa: E402
+
+CH_TEXT = "psi' = M*lap(c2*psi^3 - c1*psi - kappa*lap(psi))"
+
+
+def gpu_euler_run(w, stencil, steps, dt, text=None):
+    torch, specstep = need_gpu()
+    kw = (dict(equations=text, coefs=dict(zip(("M", "kappa", "c1", "c2"), w.coef))) if text
+          else dict(model=w.model, coef=w.coef))
+    g = specstep.Grid(w.n, w.dx, dtype="f64", dt=dt, solver="euler", stencil=stencil, **kw)
+    g.set_field(0, torch.from_numpy(w.fields[0]).to("cuda:0"))
+    g.step(steps)
+    out = g.get_field(0).cpu().numpy()
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("stencil", [0, 9, 4])
+def test_euler_cahn_hilliard_2048(stencil):
+    """The forward-Euler leg's 2D workload (dt 0.01), fixed-model kernels and
+    the equation text, 10 steps element by element."""
+    w = inputs.cahn_hilliard_2d(n=2048, seed=2)
+    want = fd_euler.euler_n(w.fields, w.model, w.coef, 0.01, w.dx, 10, stencil)[0]
+    for text in (None, CH_TEXT):
+        got = gpu_euler_run(w, stencil, 10, 0.01, text)
+        err = rel_l2(got, want)
+        say("euler CH 2048^2 stencil", stencil, "text" if text else "fixed", "rel_l2 %.3e" % err)
+        assert err <= TOL["f64"]
+
+
+@pytest.mark.parametrize("stencil", [0, 19, 27, 4])
+def test_euler_cahn_hilliard_256_cubed(stencil):
+    """The forward-Euler leg's 3D workload (256^3, dt 0.01), fixed-model
+    kernels and the equation text, 2 steps element by element."""
+    w = inputs.cahn_hilliard_3d(n=256)
+    want = fd_euler.euler_n(w.fields, w.model, w.coef, 0.01, w.dx, 2, stencil)[0]
+    for text in (None, CH_TEXT):
+        got = gpu_euler_run(w, stencil, 2, 0.01, text)
+        err = rel_l2(got, want)
+        say("euler CH 256^3 stencil", stencil, "text" if text else "fixed", "rel_l2 %.3e" % err)
+        assert err <= TOL["f64"]
