@@ -351,4 +351,74 @@ __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
   }
 }
 
+// 3D stencils with a one-cell reach (7, 19 and 27 points) for the
+// operations with one Laplacian: a 64 x 4 block of threads marches along z
+// over ZC planes,
+// keeping the planes z - 1, z, z + 1 of the Laplacian's input (with a
+// one-cell halo) in LDS, so that a cell's neighbours are read from LDS and
+// the input is read from memory about once.  Needs nx % 64,
+// ny % 4 and nz % ZC to be 0 (the host falls back to fd_kernel otherwise).
+constexpr int FD3_BX = 64, FD3_BY = 4, FD3_ZC = 16;
+
+template <typename T, int ST, int OP>
+__global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
+  constexpr int W = FD3_BX + 2, H = FD3_BY + 2;
+  constexpr bool LAP1 = OP == FD_UPD || OP == FD_MU_PFC;   // the Laplacian of in1
+  __shared__ T pl[3][H][W];
+  const int tid = threadIdx.x, tx = tid & (FD3_BX - 1), ty = tid / FD3_BX;
+  const int64_t nbx = a.nx / FD3_BX, nby = a.ny / FD3_BY;
+  int64_t b = blockIdx.x;
+  const int64_t bx = b % nbx;
+  b /= nbx;
+  const int64_t by = b % nby, bz = b / nby;
+  const int64_t x0 = bx * FD3_BX, y0 = by * FD3_BY, z0 = bz * FD3_ZC;
+  const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
+  const T* in0 = (const T*)a.in[0];
+  const T* in1 = (const T*)a.in[1];
+  const T* src = LAP1 ? in1 : in0;
+  T* out0 = (T*)a.out[0];
+  auto load_plane = [&](int slot, int64_t z) {
+    const int64_t zo = (z & mz) * a.ny;
+    for (int p = tid; p < H * W; p += 256) {
+      const int ly = p / W, lx = p - ly * W;
+      const int64_t gx = (x0 + lx - 1) & mx, gy = (y0 + ly - 1) & my;
+      pl[slot][ly][lx] = src[((zo + gy) << a.lx) + gx];
+    }
+  };
+  load_plane(0, z0 - 1);
+  load_plane(1, z0);
+  const T dt = (T)a.dt;
+  for (int k = 0; k < FD3_ZC; ++k) {
+    const int64_t z = z0 + k;
+    load_plane((k + 2) % 3, z + 1);
+    __syncthreads();
+    const int sm = k % 3, sc = (k + 1) % 3, sp = (k + 2) % 3;   // planes z - 1, z, z + 1
+    auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+      const int sl = dz < 0 ? sm : (dz > 0 ? sp : sc);
+      return pl[sl][ty + 1 + dy][tx + 1 + dx];
+    };
+    const T lap = fd_stencil<T, 3, ST>(at, a);
+    const int64_t i = (((z * a.ny) + y0 + ty) << a.lx) + x0 + tx;
+    if constexpr (OP == FD_AC) {
+      const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+      const T q = in0[i];
+      out0[i] = q + dt * (M * (kap * lap + c1 * q - c2 * q * q * q));
+    } else if constexpr (OP == FD_MU_CH) {
+      const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+      const T q = in0[i];
+      out0[i] = c2 * q * q * q - c1 * q - kap * lap;
+    } else if constexpr (OP == FD_UPD) {
+      out0[i] = in0[i] + dt * ((T)a.p[0] * lap);
+    } else if constexpr (OP == FD_LAP) {
+      out0[i] = lap;
+    } else {   // FD_MU_PFC
+      const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
+      const T q02 = q0 * q0;
+      const T q = in0[i], lq = in1[i];
+      out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
+    }
+    __syncthreads();   // the next iteration overwrites the plane z - 1
+  }
+}
+
 }  // namespace ss
