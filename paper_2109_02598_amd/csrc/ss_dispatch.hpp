@@ -297,21 +297,22 @@ constexpr int fd_rows(int dim, int st) {
 // where the grid tiles into its blocks; false: use fd_kernel.
 template <typename T, int ST>
 bool launch_fd3_march(FDArgs a, hipStream_t s, hipError_t* e) {
+  constexpr int HALO = ST == 4 ? 2 : 1;
   if (a.nx % FD3_BX || a.ny % FD3_BY || a.nz % FD3_ZC) return false;
   const dim3 grid((unsigned)((a.nx / FD3_BX) * (a.ny / FD3_BY) * (a.nz / FD3_ZC))), block(256);
   switch (a.op) {
-    case FD_AC: *e = launch_with(fd3_march_kernel<T, ST, FD_AC>, grid, block, 0, s, LaunchEvents(), a); return true;
-    case FD_MU_CH: *e = launch_with(fd3_march_kernel<T, ST, FD_MU_CH>, grid, block, 0, s, LaunchEvents(), a); return true;
-    case FD_UPD: *e = launch_with(fd3_march_kernel<T, ST, FD_UPD>, grid, block, 0, s, LaunchEvents(), a); return true;
-    case FD_LAP: *e = launch_with(fd3_march_kernel<T, ST, FD_LAP>, grid, block, 0, s, LaunchEvents(), a); return true;
-    case FD_MU_PFC: *e = launch_with(fd3_march_kernel<T, ST, FD_MU_PFC>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_AC: *e = launch_with(fd3_march_kernel<T, ST, FD_AC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_MU_CH: *e = launch_with(fd3_march_kernel<T, ST, FD_MU_CH, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_UPD: *e = launch_with(fd3_march_kernel<T, ST, FD_UPD, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_LAP: *e = launch_with(fd3_march_kernel<T, ST, FD_LAP, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_MU_PFC: *e = launch_with(fd3_march_kernel<T, ST, FD_MU_PFC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     default: return false;
   }
 }
 
 template <typename T, int DIM, int ST>
 hipError_t launch_fd(FDArgs a, hipStream_t s) {
-  if constexpr (DIM == 3 && (ST == 0 || ST == 19 || ST == 27)) {
+  if constexpr (DIM == 3) {
     hipError_t e;
     if (launch_fd3_march<T, ST>(a, s, &e)) return e;
   }

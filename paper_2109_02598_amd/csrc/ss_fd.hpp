@@ -351,20 +351,20 @@ __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
   }
 }
 
-// 3D stencils with a one-cell reach (7, 19 and 27 points) for the
-// operations with one Laplacian: a 64 x 4 block of threads marches along z
-// over ZC planes,
-// keeping the planes z - 1, z, z + 1 of the Laplacian's input (with a
-// one-cell halo) in LDS, so that a cell's neighbours are read from LDS and
-// the input is read from memory about once.  Needs nx % 64,
-// ny % 4 and nz % ZC to be 0 (the host falls back to fd_kernel otherwise).
+// 3D stencils for the operations with one Laplacian: a 64 x 4 block of
+// threads marches along z over ZC planes, keeping the 2 HALO + 1 planes
+// z - HALO .. z + HALO of the Laplacian's input (with a HALO-cell rim) in
+// LDS, so that a cell's neighbours are read from LDS and the input is read
+// from memory about once (HALO = 1: 7, 19 and 27 points; 2: fourth order).
+// Needs nx % 64, ny % 4 and nz % ZC to be 0 (the host falls back to
+// fd_kernel otherwise).
 constexpr int FD3_BX = 64, FD3_BY = 4, FD3_ZC = 16;
 
-template <typename T, int ST, int OP>
+template <typename T, int ST, int OP, int HALO>
 __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
-  constexpr int W = FD3_BX + 2, H = FD3_BY + 2;
+  constexpr int W = FD3_BX + 2 * HALO, H = FD3_BY + 2 * HALO, NP = 2 * HALO + 1;
   constexpr bool LAP1 = OP == FD_UPD || OP == FD_MU_PFC;   // the Laplacian of in1
-  __shared__ T pl[3][H][W];
+  __shared__ T pl[NP][H][W];
   const int tid = threadIdx.x, tx = tid & (FD3_BX - 1), ty = tid / FD3_BX;
   const int64_t nbx = a.nx / FD3_BX, nby = a.ny / FD3_BY;
   int64_t b = blockIdx.x;
@@ -381,21 +381,19 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
     const int64_t zo = (z & mz) * a.ny;
     for (int p = tid; p < H * W; p += 256) {
       const int ly = p / W, lx = p - ly * W;
-      const int64_t gx = (x0 + lx - 1) & mx, gy = (y0 + ly - 1) & my;
+      const int64_t gx = (x0 + lx - HALO) & mx, gy = (y0 + ly - HALO) & my;
       pl[slot][ly][lx] = src[((zo + gy) << a.lx) + gx];
     }
   };
-  load_plane(0, z0 - 1);
-  load_plane(1, z0);
+  // plane z + dz of iteration k sits in slot (k + HALO + dz) % NP
+  for (int j = 0; j < 2 * HALO; ++j) load_plane(j, z0 - HALO + j);
   const T dt = (T)a.dt;
   for (int k = 0; k < FD3_ZC; ++k) {
     const int64_t z = z0 + k;
-    load_plane((k + 2) % 3, z + 1);
+    load_plane((k + 2 * HALO) % NP, z + HALO);
     __syncthreads();
-    const int sm = k % 3, sc = (k + 1) % 3, sp = (k + 2) % 3;   // planes z - 1, z, z + 1
     auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-      const int sl = dz < 0 ? sm : (dz > 0 ? sp : sc);
-      return pl[sl][ty + 1 + dy][tx + 1 + dx];
+      return pl[(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
     };
     const T lap = fd_stencil<T, 3, ST>(at, a);
     const int64_t i = (((z * a.ny) + y0 + ty) << a.lx) + x0 + tx;
@@ -417,7 +415,7 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
       const T q = in0[i], lq = in1[i];
       out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
     }
-    __syncthreads();   // the next iteration overwrites the plane z - 1
+    __syncthreads();   // the next iteration overwrites the plane z - HALO
   }
 }
 
