@@ -377,42 +377,66 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
   const T* in1 = (const T*)a.in[1];
   const T* src = LAP1 ? in1 : in0;
   T* out0 = (T*)a.out[0];
-  auto load_plane = [&](int slot, int64_t z) {
+  // a plane's H x W values, NV per thread: read into registers (the next
+  // plane's read is in flight while the current plane is computed), then
+  // stored to its LDS slot
+  constexpr int NV = (H * W + 255) / 256;
+  T nxt[NV];
+  auto fetch_plane = [&](int64_t z) {
     const int64_t zo = (z & mz) * a.ny;
-    for (int p = tid; p < H * W; p += 256) {
-      const int ly = p / W, lx = p - ly * W;
-      const int64_t gx = (x0 + lx - HALO) & mx, gy = (y0 + ly - HALO) & my;
-      pl[slot][ly][lx] = src[((zo + gy) << a.lx) + gx];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int p = tid + 256 * v;
+      if (p < H * W) {
+        const int ly = p / W, lx = p - ly * W;
+        const int64_t gx = (x0 + lx - HALO) & mx, gy = (y0 + ly - HALO) & my;
+        nxt[v] = src[((zo + gy) << a.lx) + gx];
+      }
+    }
+  };
+  auto store_plane = [&](int slot) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int p = tid + 256 * v;
+      if (p < H * W) {
+        const int ly = p / W, lx = p - ly * W;
+        pl[slot][ly][lx] = nxt[v];
+      }
     }
   };
   // plane z + dz of iteration k sits in slot (k + HALO + dz) % NP
-  for (int j = 0; j < 2 * HALO; ++j) load_plane(j, z0 - HALO + j);
+  for (int j = 0; j < 2 * HALO; ++j) {
+    fetch_plane(z0 - HALO + j);
+    store_plane(j);
+  }
+  fetch_plane(z0 + HALO);
   const T dt = (T)a.dt;
   for (int k = 0; k < FD3_ZC; ++k) {
     const int64_t z = z0 + k;
-    load_plane((k + 2 * HALO) % NP, z + HALO);
+    const int64_t i = (((z * a.ny) + y0 + ty) << a.lx) + x0 + tx;
+    // the centre values, read ahead of the barrier
+    const T q = (OP == FD_LAP) ? (T)0 : in0[i];
+    const T lq = (OP == FD_MU_PFC) ? in1[i] : (T)0;
+    store_plane((k + 2 * HALO) % NP);
+    if (k + 1 < FD3_ZC) fetch_plane(z + HALO + 1);
     __syncthreads();
     auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
       return pl[(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
     };
     const T lap = fd_stencil<T, 3, ST>(at, a);
-    const int64_t i = (((z * a.ny) + y0 + ty) << a.lx) + x0 + tx;
     if constexpr (OP == FD_AC) {
       const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      const T q = in0[i];
       out0[i] = q + dt * (M * (kap * lap + c1 * q - c2 * q * q * q));
     } else if constexpr (OP == FD_MU_CH) {
       const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      const T q = in0[i];
       out0[i] = c2 * q * q * q - c1 * q - kap * lap;
     } else if constexpr (OP == FD_UPD) {
-      out0[i] = in0[i] + dt * ((T)a.p[0] * lap);
+      out0[i] = q + dt * ((T)a.p[0] * lap);
     } else if constexpr (OP == FD_LAP) {
       out0[i] = lap;
     } else {   // FD_MU_PFC
       const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
       const T q02 = q0 * q0;
-      const T q = in0[i], lq = in1[i];
       out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
     }
     __syncthreads();   // the next iteration overwrites the plane z - HALO
