@@ -595,9 +595,12 @@ ss_status fd_step_once(ss_grid g) {
       SS_TRY(fd_launch(g, ss::FD_GS, S[0], S[1], N[0], N[1], 0.0));
       break;
     case SS_CAHN_HILLIARD:
-      // 2D axis-wise stencil: mu recomputed at the stencil points, one launch
-      // and two arrays (the wider stencils recompute too much: 9 x 9 loads)
-      if (g->ndim == 2 && (g->stencil == 0 || g->stencil == 5)) {
+      // 2D axis-wise stencil on grids the row-marching kernel does not tile:
+      // mu recomputed at the stencil points, one launch and two arrays (the
+      // wider stencils recompute too much: 9 x 9 loads); where it tiles, its
+      // two launches (mu, then the update) are faster
+      if (g->ndim == 2 && (g->stencil == 0 || g->stencil == 5) &&
+          (g->n[0] % ss::FD2_BX || g->n[1] % ss::FD2_YC)) {
         SS_TRY(fd_launch(g, ss::FD_CH, S[0], nullptr, N[0], nullptr, 0.0));
       } else {
         SS_TRY(fd_launch(g, ss::FD_MU_CH, S[0], nullptr, T[0], nullptr, 0.0));

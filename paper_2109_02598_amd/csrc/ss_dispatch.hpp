@@ -310,8 +310,27 @@ bool launch_fd3_march(FDArgs a, hipStream_t s, hipError_t* e) {
   }
 }
 
+template <typename T, int ST>
+bool launch_fd2_march(FDArgs a, hipStream_t s, hipError_t* e) {
+  constexpr int HALO = ST == 4 ? 2 : 1;
+  if (a.nx % FD2_BX || a.ny % FD2_YC) return false;
+  const dim3 grid((unsigned)((a.nx / FD2_BX) * (a.ny / FD2_YC))), block(256);
+  switch (a.op) {
+    case FD_AC: *e = launch_with(fd2_march_kernel<T, ST, FD_AC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_MU_CH: *e = launch_with(fd2_march_kernel<T, ST, FD_MU_CH, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_UPD: *e = launch_with(fd2_march_kernel<T, ST, FD_UPD, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_LAP: *e = launch_with(fd2_march_kernel<T, ST, FD_LAP, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_MU_PFC: *e = launch_with(fd2_march_kernel<T, ST, FD_MU_PFC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    default: return false;
+  }
+}
+
 template <typename T, int DIM, int ST>
 hipError_t launch_fd(FDArgs a, hipStream_t s) {
+  if constexpr (DIM == 2) {
+    hipError_t e;
+    if (launch_fd2_march<T, ST>(a, s, &e)) return e;
+  }
   if constexpr (DIM == 3) {
     hipError_t e;
     if (launch_fd3_march<T, ST>(a, s, &e)) return e;

@@ -443,4 +443,79 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
   }
 }
 
+// The 2D form: a block of 256 threads along x marches along y over YC
+// rows, keeping the rows y - HALO .. y + HALO of the Laplacian's input
+// (with a HALO-cell rim) in LDS; the next row is read into registers
+// while the current one is computed.  Needs nx % 256 == 0 and ny % YC == 0.
+constexpr int FD2_BX = 256, FD2_YC = 8;
+
+template <typename T, int ST, int OP, int HALO>
+__global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
+  constexpr int W = FD2_BX + 2 * HALO, NP = 2 * HALO + 1;
+  constexpr bool LAP1 = OP == FD_UPD || OP == FD_MU_PFC;   // the Laplacian of in1
+  __shared__ T pl[NP][W];
+  const int tid = threadIdx.x;
+  const int64_t nbx = a.nx / FD2_BX;
+  const int64_t bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+  const int64_t x0 = bx * FD2_BX, y0 = by * FD2_YC;
+  const int64_t mx = a.nx - 1, my = a.ny - 1;
+  const T* in0 = (const T*)a.in[0];
+  const T* in1 = (const T*)a.in[1];
+  const T* src = LAP1 ? in1 : in0;
+  T* out0 = (T*)a.out[0];
+  constexpr int NV = (W + 255) / 256;
+  T nxt[NV];
+  auto fetch_row = [&](int64_t y) {
+    const int64_t yo = (y & my) << a.lx;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int p = tid + 256 * v;
+      if (p < W) nxt[v] = src[yo + ((x0 + p - HALO) & mx)];
+    }
+  };
+  auto store_row = [&](int slot) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int p = tid + 256 * v;
+      if (p < W) pl[slot][p] = nxt[v];
+    }
+  };
+  // row y + dy of iteration k sits in slot (k + HALO + dy) % NP
+  for (int j = 0; j < 2 * HALO; ++j) {
+    fetch_row(y0 - HALO + j);
+    store_row(j);
+  }
+  fetch_row(y0 + HALO);
+  const T dt = (T)a.dt;
+  for (int k = 0; k < FD2_YC; ++k) {
+    const int64_t y = y0 + k;
+    const int64_t i = (y << a.lx) + x0 + tid;
+    const T q = (OP == FD_LAP) ? (T)0 : in0[i];
+    const T lq = (OP == FD_MU_PFC) ? in1[i] : (T)0;
+    store_row((k + 2 * HALO) % NP);
+    if (k + 1 < FD2_YC) fetch_row(y + HALO + 1);
+    __syncthreads();
+    auto at = [&](int64_t dx, int64_t dy, int64_t) -> T {
+      return pl[(k + HALO + (int)dy) % NP][tid + HALO + dx];
+    };
+    const T lap = fd_stencil<T, 2, ST>(at, a);
+    if constexpr (OP == FD_AC) {
+      const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+      out0[i] = q + dt * (M * (kap * lap + c1 * q - c2 * q * q * q));
+    } else if constexpr (OP == FD_MU_CH) {
+      const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+      out0[i] = c2 * q * q * q - c1 * q - kap * lap;
+    } else if constexpr (OP == FD_UPD) {
+      out0[i] = q + dt * ((T)a.p[0] * lap);
+    } else if constexpr (OP == FD_LAP) {
+      out0[i] = lap;
+    } else {   // FD_MU_PFC
+      const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
+      const T q02 = q0 * q0;
+      out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
+    }
+    __syncthreads();   // the next iteration overwrites the row y - HALO
+  }
+}
+
 }  // namespace ss

@@ -32,7 +32,8 @@ def gpu_euler(model, n, dx, dt, steps, fields, dtype, stencil):
 @pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc", "gray_scott", "model_c"])
 @pytest.mark.parametrize("n,stencil", [((64, 32), 0), ((32, 64), 9), ((16, 8, 32), 0), ((16, 16, 16), 19),
                                        ((16, 16, 16), 27), ((32, 64), 4), ((16, 8, 32), 4),
-                                       ((64, 8, 32), 19), ((128, 8, 16), 27), ((64, 16, 16), 0), ((64, 8, 32), 4)])
+                                       ((64, 8, 32), 19), ((128, 8, 16), 27), ((64, 16, 16), 0), ((64, 8, 32), 4),
+                                       ((256, 16), 9), ((512, 8), 4), ((256, 32), 0)])
 def test_euler_vs_oracle(model, n, stencil, dtype):
     dx = (1.0,) * len(n)
     steps = 20
