@@ -414,9 +414,9 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
   for (int k = 0; k < FD3_ZC; ++k) {
     const int64_t z = z0 + k;
     const int64_t i = (((z * a.ny) + y0 + ty) << a.lx) + x0 + tx;
-    // the centre values, read ahead of the barrier
-    const T q = (OP == FD_LAP) ? (T)0 : in0[i];
-    const T lq = (OP == FD_MU_PFC) ? in1[i] : (T)0;
+    // a centre value of the other array, read ahead of the barrier (the
+    // Laplacian's input is in LDS)
+    const T qg = (OP == FD_UPD || OP == FD_MU_PFC) ? in0[i] : (T)0;
     store_plane((k + 2 * HALO) % NP);
     if (k + 1 < FD3_ZC) fetch_plane(z + HALO + 1);
     __syncthreads();
@@ -424,6 +424,9 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
       return pl[(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
     };
     const T lap = fd_stencil<T, 3, ST>(at, a);
+    const T c = at(0, 0, 0);
+    const T q = (OP == FD_UPD || OP == FD_MU_PFC) ? qg : c;   // psi
+    const T lq = c;                                          // FD_MU_PFC: L psi
     if constexpr (OP == FD_AC) {
       const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
       out0[i] = q + dt * (M * (kap * lap + c1 * q - c2 * q * q * q));
@@ -490,8 +493,7 @@ __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
   for (int k = 0; k < FD2_YC; ++k) {
     const int64_t y = y0 + k;
     const int64_t i = (y << a.lx) + x0 + tid;
-    const T q = (OP == FD_LAP) ? (T)0 : in0[i];
-    const T lq = (OP == FD_MU_PFC) ? in1[i] : (T)0;
+    const T qg = (OP == FD_UPD || OP == FD_MU_PFC) ? in0[i] : (T)0;
     store_row((k + 2 * HALO) % NP);
     if (k + 1 < FD2_YC) fetch_row(y + HALO + 1);
     __syncthreads();
@@ -499,6 +501,9 @@ __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
       return pl[(k + HALO + (int)dy) % NP][tid + HALO + dx];
     };
     const T lap = fd_stencil<T, 2, ST>(at, a);
+    const T c = at(0, 0, 0);
+    const T q = (OP == FD_UPD || OP == FD_MU_PFC) ? qg : c;   // psi
+    const T lq = c;                                          // FD_MU_PFC: L psi
     if constexpr (OP == FD_AC) {
       const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
       out0[i] = q + dt * (M * (kap * lap + c1 * q - c2 * q * q * q));
