@@ -306,6 +306,8 @@ bool launch_fd3_march(FDArgs a, hipStream_t s, hipError_t* e) {
     case FD_UPD: *e = launch_with(fd3_march_kernel<T, ST, FD_UPD, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     case FD_LAP: *e = launch_with(fd3_march_kernel<T, ST, FD_LAP, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     case FD_MU_PFC: *e = launch_with(fd3_march_kernel<T, ST, FD_MU_PFC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_GS: *e = launch_with(fd3_march_kernel<T, ST, FD_GS, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_MC: *e = launch_with(fd3_march_kernel<T, ST, FD_MC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     default: return false;
   }
 }
@@ -321,6 +323,8 @@ bool launch_fd2_march(FDArgs a, hipStream_t s, hipError_t* e) {
     case FD_UPD: *e = launch_with(fd2_march_kernel<T, ST, FD_UPD, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     case FD_LAP: *e = launch_with(fd2_march_kernel<T, ST, FD_LAP, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     case FD_MU_PFC: *e = launch_with(fd2_march_kernel<T, ST, FD_MU_PFC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_GS: *e = launch_with(fd2_march_kernel<T, ST, FD_GS, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
+    case FD_MC: *e = launch_with(fd2_march_kernel<T, ST, FD_MC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     default: return false;
   }
 }

@@ -351,10 +351,10 @@ __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
   }
 }
 
-// 3D stencils for the operations with one Laplacian: a 64 x 4 block of
-// threads marches along z over ZC planes, keeping the 2 HALO + 1 planes
-// z - HALO .. z + HALO of the Laplacian's input (with a HALO-cell rim) in
-// LDS, so that a cell's neighbours are read from LDS and the input is read
+// 3D stencils: a 64 x 4 block of threads marches along z over ZC planes,
+// keeping the 2 HALO + 1 planes z - HALO .. z + HALO of the Laplacian's
+// input (of both fields for Gray-Scott and Model C; with a HALO-cell rim)
+// in LDS, so that a cell's neighbours are read from LDS and the input is read
 // from memory about once (HALO = 1: 7, 19 and 27 points; 2: fourth order).
 // Needs nx % 64, ny % 4 and nz % ZC to be 0 (the host falls back to
 // fd_kernel otherwise).
@@ -364,7 +364,8 @@ template <typename T, int ST, int OP, int HALO>
 __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
   constexpr int W = FD3_BX + 2 * HALO, H = FD3_BY + 2 * HALO, NP = 2 * HALO + 1;
   constexpr bool LAP1 = OP == FD_UPD || OP == FD_MU_PFC;   // the Laplacian of in1
-  __shared__ T pl[NP][H][W];
+  constexpr int NS = (OP == FD_GS || OP == FD_MC) ? 2 : 1;  // arrays in LDS (Laplacians taken)
+  __shared__ T pl[NS][NP][H][W];
   const int tid = threadIdx.x, tx = tid & (FD3_BX - 1), ty = tid / FD3_BX;
   const int64_t nbx = a.nx / FD3_BX, nby = a.ny / FD3_BY;
   int64_t b = blockIdx.x;
@@ -375,13 +376,14 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
   const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
   const T* in0 = (const T*)a.in[0];
   const T* in1 = (const T*)a.in[1];
-  const T* src = LAP1 ? in1 : in0;
+  const T* const srcs[2] = {LAP1 ? in1 : in0, in1};
   T* out0 = (T*)a.out[0];
+  T* out1 = (T*)a.out[1];
   // a plane's H x W values, NV per thread: read into registers (the next
   // plane's read is in flight while the current plane is computed), then
   // stored to its LDS slot
   constexpr int NV = (H * W + 255) / 256;
-  T nxt[NV];
+  T nxt[NS][NV];
   auto fetch_plane = [&](int64_t z) {
     const int64_t zo = (z & mz) * a.ny;
 #pragma unroll
@@ -390,7 +392,8 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
       if (p < H * W) {
         const int ly = p / W, lx = p - ly * W;
         const int64_t gx = (x0 + lx - HALO) & mx, gy = (y0 + ly - HALO) & my;
-        nxt[v] = src[((zo + gy) << a.lx) + gx];
+#pragma unroll
+        for (int n = 0; n < NS; ++n) nxt[n][v] = srcs[n][((zo + gy) << a.lx) + gx];
       }
     }
   };
@@ -400,7 +403,8 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
       const int p = tid + 256 * v;
       if (p < H * W) {
         const int ly = p / W, lx = p - ly * W;
-        pl[slot][ly][lx] = nxt[v];
+#pragma unroll
+        for (int n = 0; n < NS; ++n) pl[n][slot][ly][lx] = nxt[n][v];
       }
     }
   };
@@ -421,7 +425,10 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
     if (k + 1 < FD3_ZC) fetch_plane(z + HALO + 1);
     __syncthreads();
     auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-      return pl[(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
+      return pl[0][(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
+    };
+    auto at1 = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+      return pl[NS - 1][(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
     };
     const T lap = fd_stencil<T, 3, ST>(at, a);
     const T c = at(0, 0, 0);
@@ -437,10 +444,21 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
       out0[i] = q + dt * ((T)a.p[0] * lap);
     } else if constexpr (OP == FD_LAP) {
       out0[i] = lap;
-    } else {   // FD_MU_PFC
+    } else if constexpr (OP == FD_MU_PFC) {
       const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
       const T q02 = q0 * q0;
       out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
+    } else if constexpr (OP == FD_GS) {
+      const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
+      const T u = c, v = at1(0, 0, 0), lap1 = fd_stencil<T, 3, ST>(at1, a);
+      const T uvv = u * v * v;
+      out0[i] = u + dt * (du * lap - uvv + F * ((T)1 - u));
+      out1[i] = v + dt * (dv * lap1 + uvv - (F + kk) * v);
+    } else {   // FD_MC
+      const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
+      const T m = at1(0, 0, 0), lap1 = fd_stencil<T, 3, ST>(at1, a);
+      out0[i] = c + dt * (lap + c1 * c - c2 * c * c * c + (T)2 * c5 * c * m);
+      out1[i] = -lap1 - c3 * m + c4 * m * m * m - c5 * c * c;
     }
     __syncthreads();   // the next iteration overwrites the plane z - HALO
   }
@@ -448,7 +466,7 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
 
 // The 2D form: a block of 256 threads along x marches along y over YC
 // rows, keeping the rows y - HALO .. y + HALO of the Laplacian's input
-// (with a HALO-cell rim) in LDS; the next row is read into registers
+// (of both fields for Gray-Scott and Model C; with a HALO-cell rim) in LDS; the next row is read into registers
 // while the current one is computed.  Needs nx % 256 == 0 and ny % YC == 0.
 constexpr int FD2_BX = 256, FD2_YC = 8;
 
@@ -456,7 +474,8 @@ template <typename T, int ST, int OP, int HALO>
 __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
   constexpr int W = FD2_BX + 2 * HALO, NP = 2 * HALO + 1;
   constexpr bool LAP1 = OP == FD_UPD || OP == FD_MU_PFC;   // the Laplacian of in1
-  __shared__ T pl[NP][W];
+  constexpr int NS = (OP == FD_GS || OP == FD_MC) ? 2 : 1;  // arrays in LDS (Laplacians taken)
+  __shared__ T pl[NS][NP][W];
   const int tid = threadIdx.x;
   const int64_t nbx = a.nx / FD2_BX;
   const int64_t bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
@@ -464,23 +483,30 @@ __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
   const int64_t mx = a.nx - 1, my = a.ny - 1;
   const T* in0 = (const T*)a.in[0];
   const T* in1 = (const T*)a.in[1];
-  const T* src = LAP1 ? in1 : in0;
+  const T* const srcs[2] = {LAP1 ? in1 : in0, in1};
   T* out0 = (T*)a.out[0];
+  T* out1 = (T*)a.out[1];
   constexpr int NV = (W + 255) / 256;
-  T nxt[NV];
+  T nxt[NS][NV];
   auto fetch_row = [&](int64_t y) {
     const int64_t yo = (y & my) << a.lx;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int p = tid + 256 * v;
-      if (p < W) nxt[v] = src[yo + ((x0 + p - HALO) & mx)];
+      if (p < W) {
+#pragma unroll
+        for (int n = 0; n < NS; ++n) nxt[n][v] = srcs[n][yo + ((x0 + p - HALO) & mx)];
+      }
     }
   };
   auto store_row = [&](int slot) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int p = tid + 256 * v;
-      if (p < W) pl[slot][p] = nxt[v];
+      if (p < W) {
+#pragma unroll
+        for (int n = 0; n < NS; ++n) pl[n][slot][p] = nxt[n][v];
+      }
     }
   };
   // row y + dy of iteration k sits in slot (k + HALO + dy) % NP
@@ -498,7 +524,10 @@ __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
     if (k + 1 < FD2_YC) fetch_row(y + HALO + 1);
     __syncthreads();
     auto at = [&](int64_t dx, int64_t dy, int64_t) -> T {
-      return pl[(k + HALO + (int)dy) % NP][tid + HALO + dx];
+      return pl[0][(k + HALO + (int)dy) % NP][tid + HALO + dx];
+    };
+    auto at1 = [&](int64_t dx, int64_t dy, int64_t) -> T {
+      return pl[NS - 1][(k + HALO + (int)dy) % NP][tid + HALO + dx];
     };
     const T lap = fd_stencil<T, 2, ST>(at, a);
     const T c = at(0, 0, 0);
@@ -514,10 +543,21 @@ __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
       out0[i] = q + dt * ((T)a.p[0] * lap);
     } else if constexpr (OP == FD_LAP) {
       out0[i] = lap;
-    } else {   // FD_MU_PFC
+    } else if constexpr (OP == FD_MU_PFC) {
       const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
       const T q02 = q0 * q0;
       out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
+    } else if constexpr (OP == FD_GS) {
+      const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
+      const T u = c, v = at1(0, 0, 0), lap1 = fd_stencil<T, 2, ST>(at1, a);
+      const T uvv = u * v * v;
+      out0[i] = u + dt * (du * lap - uvv + F * ((T)1 - u));
+      out1[i] = v + dt * (dv * lap1 + uvv - (F + kk) * v);
+    } else {   // FD_MC
+      const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
+      const T m = at1(0, 0, 0), lap1 = fd_stencil<T, 2, ST>(at1, a);
+      out0[i] = c + dt * (lap + c1 * c - c2 * c * c * c + (T)2 * c5 * c * m);
+      out1[i] = -lap1 - c3 * m + c4 * m * m * m - c5 * c * c;
     }
     __syncthreads();   // the next iteration overwrites the row y - HALO
   }
