@@ -14,9 +14,12 @@
 //           (-f[-2] + 16 f[-1] - 30 f + 16 f[+1] - f[+2]) / (12 h_a^2).
 // The leading error of the isotropic stencils depends on |k| only.
 //
-// One launch applies one operation at every cell (a thread per R cells
-// along y, x fastest across threads).  A step is one to three launches, by model (the forms of the
-// right-hand sides are those of the equations of motion of Sec. 3):
+// One launch applies one operation at every cell: where the grid tiles,
+// a marching kernel (fd2_march_kernel, fd3_march_kernel: the rows or
+// planes of the Laplacian's input held in LDS), else fd_kernel (a thread
+// per R cells along y, x fastest across threads).  A step is one to three
+// launches, by model (the forms of the right-hand sides are those of the
+// equations of motion of Sec. 3):
 //   FD_AC     psi' = psi + dt M (kappa L psi + c1 psi - c2 psi^3)
 //   FD_GS     u' = u + dt (Du L u - u v^2 + F (1 - u)),
 //             v' = v + dt (Dv L v + u v^2 - (F + k) v)
