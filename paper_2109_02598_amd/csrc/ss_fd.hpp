@@ -566,4 +566,100 @@ __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
   }
 }
 
+// One level of an equation read at run time, v_0 = c_0 psi_j (+ E_j) +
+// L v_1, with the marching scheme of the kernels above (2D: 256 threads
+// along x march along y; 3D: 64 x 4 threads march along z): the rows or
+// planes of v_1 sit in LDS, staged from the array w (LW) or evaluated
+// from the fields once per staged point (c_1 psi_j (+ E_j)).  One slot
+// (field); the two-slot launches and the launches without a Laplacian
+// take fd_eq_kernel.
+template <typename T, int DIM, int ST, bool LW, int NF, int HALO>
+__global__ void __launch_bounds__(256) fd_eq_march_kernel(FDArgs a, FDEq q) {
+  constexpr int BX = DIM == 2 ? FD2_BX : FD3_BX, BY = DIM == 2 ? 1 : FD3_BY;
+  constexpr int NZ = DIM == 2 ? FD2_YC : FD3_ZC;            // planes a block marches
+  constexpr int W = BX + 2 * HALO, H = DIM == 2 ? 1 : BY + 2 * HALO, NP = 2 * HALO + 1;
+  constexpr int NV = (H * W + 255) / 256;
+  __shared__ T pl[NP][H][W];
+  const FDEqTab* tb = &q.tab;
+  const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
+  const int64_t nbx = a.nx / BX, nby = DIM == 2 ? 1 : a.ny / BY;
+  int64_t b = blockIdx.x;
+  const int64_t bx = b % nbx;
+  b /= nbx;
+  const int64_t by = DIM == 2 ? 0 : b % nby, bm = DIM == 2 ? b : b / nby;
+  const int64_t x0 = bx * BX, y0 = by * BY, m0 = bm * NZ;    // m: y in 2D, z in 3D
+  const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
+  const T* f0 = (const T*)a.in[0];
+  const T* f1 = NF == 2 ? (const T*)a.in[1] : f0;
+  const int j = q.j[0];
+  const T* fj = j == 0 ? f0 : f1;
+  const T* w = (const T*)q.w[0];
+  T* out = (T*)q.out[0];
+  const T cl0 = (T)q.cl[0][0], cl1 = (T)q.cl[0][1];
+  const int el0 = q.el[0][0], el1 = q.el[0][1];
+  auto addr = [&](int p, int64_t m) -> int64_t {
+    const int ly = p / W, lx = p - ly * W;
+    const int64_t gx = (x0 + lx - HALO) & mx;
+    if constexpr (DIM == 2) return ((m & my) << a.lx) + gx;
+    else return (((m & mz) * a.ny + ((y0 + ly - HALO) & my)) << a.lx) + gx;
+  };
+  T n0[NV], n1[NV];
+  auto fetch = [&](int64_t m) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int p = tid + 256 * v;
+      if (p < H * W) {
+        const int64_t g = addr(p, m);
+        if constexpr (LW) {
+          n0[v] = w[g];
+        } else {
+          n0[v] = f0[g];
+          n1[v] = NF == 2 ? f1[g] : (T)0;
+        }
+      }
+    }
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int p = tid + 256 * v;
+      if (p < H * W) {
+        const int ly = p / W, lx = p - ly * W;
+        T val;
+        if constexpr (LW) {
+          val = n0[v];
+        } else {
+          val = cl1 * (NF == 1 || j == 0 ? n0[v] : n1[v]);
+          if (el1) val += fd_eq_E<T>(tb, j, n0[v], n1[v]);
+        }
+        pl[slot][ly][lx] = val;
+      }
+    }
+  };
+  // plane m + d of iteration k sits in slot (k + HALO + d) % NP
+  for (int jj = 0; jj < 2 * HALO; ++jj) {
+    fetch(m0 - HALO + jj);
+    store(jj);
+  }
+  fetch(m0 + HALO);
+  for (int k = 0; k < NZ; ++k) {
+    const int64_t m = m0 + k;
+    const int64_t i = DIM == 2 ? ((m << a.lx) + x0 + tid) : ((((m * a.ny) + y0 + ty) << a.lx) + x0 + tx);
+    const T u = f0[i], uv = NF == 2 ? f1[i] : (T)0;
+    store((k + 2 * HALO) % NP);
+    if (k + 1 < NZ) fetch(m + HALO + 1);
+    __syncthreads();
+    auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+      if constexpr (DIM == 2) return pl[(k + HALO + (int)dy) % NP][0][tid + HALO + dx];
+      else return pl[(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
+    };
+    const T self = NF == 1 || j == 0 ? u : uv;
+    T v = cl0 * self + fd_stencil<T, DIM, ST>(at, a);
+    if (el0) v += fd_eq_E<T>(tb, j, u, uv);
+    if (q.fin) v = self + (T)a.dt * v;
+    out[i] = v;
+    __syncthreads();   // the next iteration overwrites the plane m - HALO
+  }
+}
+
 }  // namespace ss

@@ -17,7 +17,9 @@ COEF_FD["pfc"] = (-0.25, 1.0, 0.3, 1.0)
 # explicit time steps inside each fixed model's stability limit at dx = 1
 DT_FIXED = {"allen_cahn": 0.05, "cahn_hilliard": 0.01, "pfc": 0.0005, "gray_scott": 0.1, "model_c": 0.01}
 CASES = [((64, 32), 0), ((32, 64), 9), ((32, 64), 4), ((16, 8, 32), 0), ((16, 16, 16), 19),
-         ((16, 16, 16), 27), ((16, 8, 32), 4)]
+         ((16, 16, 16), 27), ((16, 8, 32), 4),
+         # grids the marching kernels tile (rows of 256, tiles of 64 x 4 x 8)
+         ((256, 16), 9), ((512, 8), 4), ((64, 8, 16), 27), ((64, 8, 16), 0)]
 
 
 def gpu_euler_eq(text, coefs, n, dx, dt, steps, fields, dtype, stencil):
