@@ -298,8 +298,9 @@ constexpr int fd_rows(int dim, int st) {
 template <typename T, int ST>
 bool launch_fd3_march(FDArgs a, hipStream_t s, hipError_t* e) {
   constexpr int HALO = ST == 4 ? 2 : 1;
-  if (a.nx % FD3_BX || a.ny % FD3_BY || a.nz % FD3_ZC) return false;
-  const dim3 grid((unsigned)((a.nx / FD3_BX) * (a.ny / FD3_BY) * (a.nz / FD3_ZC))), block(256);
+  constexpr int TY = FD3_BY * fd3_rows(ST);
+  if (a.nx % FD3_BX || a.ny % TY || a.nz % FD3_ZC) return false;
+  const dim3 grid((unsigned)((a.nx / FD3_BX) * (a.ny / TY) * (a.nz / FD3_ZC))), block(256);
   switch (a.op) {
     case FD_AC: *e = launch_with(fd3_march_kernel<T, ST, FD_AC, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;
     case FD_MU_CH: *e = launch_with(fd3_march_kernel<T, ST, FD_MU_CH, HALO>, grid, block, 0, s, LaunchEvents(), a); return true;

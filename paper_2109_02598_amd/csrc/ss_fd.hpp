@@ -362,20 +362,25 @@ __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
 // Needs nx % 64, ny % 4 and nz % ZC to be 0 (the host falls back to
 // fd_kernel otherwise).
 constexpr int FD3_BX = 64, FD3_BY = 4, FD3_ZC = 8;   // 8 planes a block: measured faster than 16 or 32 (more blocks in flight)
+// rows per thread: two (tiles of 64 x 8, a thinner rim) for the axis-wise
+// and fourth-order stencils, one for the 19- and 27-point ones (measured:
+// CH 256^3 axis-wise 162 -> 148 us per step, 19-point 165 -> 170)
+constexpr int fd3_rows(int st) { return (st == 0 || st == 4) ? 2 : 1; }
 
 template <typename T, int ST, int OP, int HALO>
 __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
-  constexpr int W = FD3_BX + 2 * HALO, H = FD3_BY + 2 * HALO, NP = 2 * HALO + 1;
+  constexpr int RY = fd3_rows(ST), TY = FD3_BY * RY;   // a thread's rows ty + FD3_BY r, r < RY
+  constexpr int W = FD3_BX + 2 * HALO, H = TY + 2 * HALO, NP = 2 * HALO + 1;
   constexpr bool LAP1 = OP == FD_UPD || OP == FD_MU_PFC;   // the Laplacian of in1
   constexpr int NS = (OP == FD_GS || OP == FD_MC) ? 2 : 1;  // arrays in LDS (Laplacians taken)
   __shared__ T pl[NS][NP][H][W];
   const int tid = threadIdx.x, tx = tid & (FD3_BX - 1), ty = tid / FD3_BX;
-  const int64_t nbx = a.nx / FD3_BX, nby = a.ny / FD3_BY;
+  const int64_t nbx = a.nx / FD3_BX, nby = a.ny / TY;
   int64_t b = blockIdx.x;
   const int64_t bx = b % nbx;
   b /= nbx;
   const int64_t by = b % nby, bz = b / nby;
-  const int64_t x0 = bx * FD3_BX, y0 = by * FD3_BY, z0 = bz * FD3_ZC;
+  const int64_t x0 = bx * FD3_BX, y0 = by * TY, z0 = bz * FD3_ZC;
   const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
   const T* in0 = (const T*)a.in[0];
   const T* in1 = (const T*)a.in[1];
@@ -420,48 +425,58 @@ __global__ void __launch_bounds__(256) fd3_march_kernel(FDArgs a) {
   const T dt = (T)a.dt;
   for (int k = 0; k < FD3_ZC; ++k) {
     const int64_t z = z0 + k;
-    const int64_t i = (((z * a.ny) + y0 + ty) << a.lx) + x0 + tx;
-    // a centre value of the other array, read ahead of the barrier (the
-    // Laplacian's input is in LDS)
-    const T qg = (OP == FD_UPD || OP == FD_MU_PFC) ? in0[i] : (T)0;
+    int64_t i[RY];
+    T qg[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      i[r] = (((z * a.ny) + y0 + ty + FD3_BY * r) << a.lx) + x0 + tx;
+      // a centre value of the other array, read ahead of the barrier (the
+      // Laplacian's input is in LDS)
+      qg[r] = (OP == FD_UPD || OP == FD_MU_PFC) ? in0[i[r]] : (T)0;
+    }
     store_plane((k + 2 * HALO) % NP);
     if (k + 1 < FD3_ZC) fetch_plane(z + HALO + 1);
     __syncthreads();
-    auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-      return pl[0][(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
-    };
-    auto at1 = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-      return pl[NS - 1][(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
-    };
-    const T lap = fd_stencil<T, 3, ST>(at, a);
-    const T c = at(0, 0, 0);
-    const T q = (OP == FD_UPD || OP == FD_MU_PFC) ? qg : c;   // psi
-    const T lq = c;                                          // FD_MU_PFC: L psi
-    if constexpr (OP == FD_AC) {
-      const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      out0[i] = q + dt * (M * (kap * lap + c1 * q - c2 * q * q * q));
-    } else if constexpr (OP == FD_MU_CH) {
-      const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
-      out0[i] = c2 * q * q * q - c1 * q - kap * lap;
-    } else if constexpr (OP == FD_UPD) {
-      out0[i] = q + dt * ((T)a.p[0] * lap);
-    } else if constexpr (OP == FD_LAP) {
-      out0[i] = lap;
-    } else if constexpr (OP == FD_MU_PFC) {
-      const T r = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
-      const T q02 = q0 * q0;
-      out0[i] = (r + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
-    } else if constexpr (OP == FD_GS) {
-      const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
-      const T u = c, v = at1(0, 0, 0), lap1 = fd_stencil<T, 3, ST>(at1, a);
-      const T uvv = u * v * v;
-      out0[i] = u + dt * (du * lap - uvv + F * ((T)1 - u));
-      out1[i] = v + dt * (dv * lap1 + uvv - (F + kk) * v);
-    } else {   // FD_MC
-      const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
-      const T m = at1(0, 0, 0), lap1 = fd_stencil<T, 3, ST>(at1, a);
-      out0[i] = c + dt * (lap + c1 * c - c2 * c * c * c + (T)2 * c5 * c * m);
-      out1[i] = -lap1 - c3 * m + c4 * m * m * m - c5 * c * c;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int yl = ty + FD3_BY * r + HALO;
+      auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+        return pl[0][(k + HALO + (int)dz) % NP][yl + dy][tx + HALO + dx];
+      };
+      auto at1 = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+        return pl[NS - 1][(k + HALO + (int)dz) % NP][yl + dy][tx + HALO + dx];
+      };
+      const T lap = fd_stencil<T, 3, ST>(at, a);
+      const T c = at(0, 0, 0);
+      const T q = (OP == FD_UPD || OP == FD_MU_PFC) ? qg[r] : c;   // psi
+      const T lq = c;                                             // FD_MU_PFC: L psi
+      const int64_t ii = i[r];
+      if constexpr (OP == FD_AC) {
+        const T M = (T)a.p[0], kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+        out0[ii] = q + dt * (M * (kap * lap + c1 * q - c2 * q * q * q));
+      } else if constexpr (OP == FD_MU_CH) {
+        const T kap = (T)a.p[1], c1 = (T)a.p[2], c2 = (T)a.p[3];
+        out0[ii] = c2 * q * q * q - c1 * q - kap * lap;
+      } else if constexpr (OP == FD_UPD) {
+        out0[ii] = q + dt * ((T)a.p[0] * lap);
+      } else if constexpr (OP == FD_LAP) {
+        out0[ii] = lap;
+      } else if constexpr (OP == FD_MU_PFC) {
+        const T r0 = (T)a.p[0], q0 = (T)a.p[1], g2 = (T)a.p[2], g3 = (T)a.p[3];
+        const T q02 = q0 * q0;
+        out0[ii] = (r0 + q02 * q02) * q + (T)2 * q02 * lq + lap + g2 * q * q + g3 * q * q * q;
+      } else if constexpr (OP == FD_GS) {
+        const T du = (T)a.p[0], dv = (T)a.p[1], F = (T)a.p[2], kk = (T)a.p[3];
+        const T u = c, v = at1(0, 0, 0), lap1 = fd_stencil<T, 3, ST>(at1, a);
+        const T uvv = u * v * v;
+        out0[ii] = u + dt * (du * lap - uvv + F * ((T)1 - u));
+        out1[ii] = v + dt * (dv * lap1 + uvv - (F + kk) * v);
+      } else {   // FD_MC
+        const T c1 = (T)a.p[0], c2 = (T)a.p[1], c3 = (T)a.p[2], c4 = (T)a.p[3], c5 = (T)a.p[4];
+        const T m = at1(0, 0, 0), lap1 = fd_stencil<T, 3, ST>(at1, a);
+        out0[ii] = c + dt * (lap + c1 * c - c2 * c * c * c + (T)2 * c5 * c * m);
+        out1[ii] = -lap1 - c3 * m + c4 * m * m * m - c5 * c * c;
+      }
     }
     __syncthreads();   // the next iteration overwrites the plane z - HALO
   }
