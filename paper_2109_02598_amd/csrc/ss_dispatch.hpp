@@ -389,14 +389,15 @@ hipError_t run_fd_eq_nf(int dim, int stencil, int depth, FDArgs a, const FDEq& q
     return launch_with(fd_eq_kernel<T, 3, 0, 0, false, NF, 1>, grid(1), block, 0, s, LaunchEvents(), a, q);
   }
   // one slot, one Laplacian, a grid the marching scheme tiles
+  const int ty3 = FD3_BY * fd3_rows(stencil);
   const bool march = depth == 1 && q.nj == 1 &&
                      (dim == 2 ? (a.nx % FD2_BX == 0 && a.ny % FD2_YC == 0)
-                               : (a.nx % FD3_BX == 0 && a.ny % FD3_BY == 0 && a.nz % FD3_ZC == 0));
+                               : (a.nx % FD3_BX == 0 && a.ny % ty3 == 0 && a.nz % FD3_ZC == 0));
 #define SS_FDEQM(D, S)                                                                                        \
   if (march && dim == D && stencil == S) {                                                                    \
     constexpr int HALO = S == 4 ? 2 : 1;                                                                      \
     const dim3 g((unsigned)(D == 2 ? (a.nx / FD2_BX) * (a.ny / FD2_YC)                                       \
-                                   : (a.nx / FD3_BX) * (a.ny / FD3_BY) * (a.nz / FD3_ZC)));                   \
+                                   : (a.nx / FD3_BX) * (a.ny / ty3) * (a.nz / FD3_ZC)));                      \
     return lw ? launch_with(fd_eq_march_kernel<T, D, S, true, NF, HALO>, g, block, 0, s, LaunchEvents(), a, q)  \
               : launch_with(fd_eq_march_kernel<T, D, S, false, NF, HALO>, g, block, 0, s, LaunchEvents(), a, q); \
   }

@@ -591,18 +591,19 @@ __global__ void __launch_bounds__(256) fd2_march_kernel(FDArgs a) {
 template <typename T, int DIM, int ST, bool LW, int NF, int HALO>
 __global__ void __launch_bounds__(256) fd_eq_march_kernel(FDArgs a, FDEq q) {
   constexpr int BX = DIM == 2 ? FD2_BX : FD3_BX, BY = DIM == 2 ? 1 : FD3_BY;
+  constexpr int RY = DIM == 2 ? 1 : fd3_rows(ST), TY = BY * RY;   // a thread's rows ty + BY r
   constexpr int NZ = DIM == 2 ? FD2_YC : FD3_ZC;            // planes a block marches
-  constexpr int W = BX + 2 * HALO, H = DIM == 2 ? 1 : BY + 2 * HALO, NP = 2 * HALO + 1;
+  constexpr int W = BX + 2 * HALO, H = DIM == 2 ? 1 : TY + 2 * HALO, NP = 2 * HALO + 1;
   constexpr int NV = (H * W + 255) / 256;
   __shared__ T pl[NP][H][W];
   const FDEqTab* tb = &q.tab;
   const int tid = threadIdx.x, tx = tid % BX, ty = tid / BX;
-  const int64_t nbx = a.nx / BX, nby = DIM == 2 ? 1 : a.ny / BY;
+  const int64_t nbx = a.nx / BX, nby = DIM == 2 ? 1 : a.ny / TY;
   int64_t b = blockIdx.x;
   const int64_t bx = b % nbx;
   b /= nbx;
   const int64_t by = DIM == 2 ? 0 : b % nby, bm = DIM == 2 ? b : b / nby;
-  const int64_t x0 = bx * BX, y0 = by * BY, m0 = bm * NZ;    // m: y in 2D, z in 3D
+  const int64_t x0 = bx * BX, y0 = by * TY, m0 = bm * NZ;    // m: y in 2D, z in 3D
   const int64_t mx = a.nx - 1, my = a.ny - 1, mz = a.nz - 1;
   const T* f0 = (const T*)a.in[0];
   const T* f1 = NF == 2 ? (const T*)a.in[1] : f0;
@@ -659,20 +660,30 @@ __global__ void __launch_bounds__(256) fd_eq_march_kernel(FDArgs a, FDEq q) {
   fetch(m0 + HALO);
   for (int k = 0; k < NZ; ++k) {
     const int64_t m = m0 + k;
-    const int64_t i = DIM == 2 ? ((m << a.lx) + x0 + tid) : ((((m * a.ny) + y0 + ty) << a.lx) + x0 + tx);
-    const T u = f0[i], uv = NF == 2 ? f1[i] : (T)0;
+    int64_t i[RY];
+    T u[RY], uv[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      i[r] = DIM == 2 ? ((m << a.lx) + x0 + tid) : ((((m * a.ny) + y0 + ty + BY * r) << a.lx) + x0 + tx);
+      u[r] = f0[i[r]];
+      uv[r] = NF == 2 ? f1[i[r]] : (T)0;
+    }
     store((k + 2 * HALO) % NP);
     if (k + 1 < NZ) fetch(m + HALO + 1);
     __syncthreads();
-    auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
-      if constexpr (DIM == 2) return pl[(k + HALO + (int)dy) % NP][0][tid + HALO + dx];
-      else return pl[(k + HALO + (int)dz) % NP][ty + HALO + dy][tx + HALO + dx];
-    };
-    const T self = NF == 1 || j == 0 ? u : uv;
-    T v = cl0 * self + fd_stencil<T, DIM, ST>(at, a);
-    if (el0) v += fd_eq_E<T>(tb, j, u, uv);
-    if (q.fin) v = self + (T)a.dt * v;
-    out[i] = v;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int yl = ty + BY * r + HALO;
+      auto at = [&](int64_t dx, int64_t dy, int64_t dz) -> T {
+        if constexpr (DIM == 2) return pl[(k + HALO + (int)dy) % NP][0][tid + HALO + dx];
+        else return pl[(k + HALO + (int)dz) % NP][yl + dy][tx + HALO + dx];
+      };
+      const T self = NF == 1 || j == 0 ? u[r] : uv[r];
+      T v = cl0 * self + fd_stencil<T, DIM, ST>(at, a);
+      if (el0) v += fd_eq_E<T>(tb, j, u[r], uv[r]);
+      if (q.fin) v = self + (T)a.dt * v;
+      out[i[r]] = v;
+    }
     __syncthreads();   // the next iteration overwrites the plane m - HALO
   }
 }
