@@ -78,6 +78,12 @@ def algorithmic_bytes(pass_name, w, esz):
 PASSES = {2: ("xpass", "kpass"), 3: ("xpass", "kpass", "ypass_inv", "ypass_fwd")}
 
 
+def step_bytes(w, esz):
+    """Byte model of one whole step (every pass): 6 F N s in 2D (x pass 2,
+    k-space pass 4 arrays per field), 10 F N s in 3D (y passes 2 + 2 more)."""
+    return (6 if len(w.n) == 2 else 10) * len(w.fields) * w.cells * esz
+
+
 def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
     import torch
     from paper_2109_02598_amd import specstep
@@ -168,8 +174,15 @@ def run_batch(steps=500, reps=3):
     b.close()
     for g in gs:
         g.close()
+    # the byte model of one step of every member (6 arrays of N_i floats each)
+    bpass = sum(6 * w.cells * 4 for w in ws)
+    agg = bpass * steps / (ms_graph * 1e-3) / 1e9
     return {"workload": "cahn_hilliard batch of 64 (sizes %s, M, kappa ~ U[0.5, 2)), f32, %d steps"
                         % (sorted(set(w.n[0] for w in ws)), steps),
+            "roofline": {"bound": "hbm", "what": "aggregate: sum over members of 6 N_i s bytes per step "
+                                                 "over the graph launch time per step",
+                         "bytes_per_step": bpass, "achieved": round(agg, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(agg / HBM_PEAK_GBS, 4)},
             "cells": cells, "value": round(cells * steps / (ms_graph * 1e-3), 1),
             "unit": "cell-updates/s", "ms_graph_launch": round(ms_graph, 3),
             "ms_eager_grouped": round(ms_eager, 3), "ms_sequential_plain": round(ms_plain, 3),
@@ -341,16 +354,16 @@ def run_others(skip, steps=200):
         for dt in ("f64", "f32"):
             ms, _, prof, _ = run_gpu(w, dt, steps, 20, 50)
             prof.pop("structure_factor", None)
-            r = roofline(w, dt, prof, load_traffic(name, dt))
+            r = roofline(w, dt, prof, load_traffic(name, dt), ms / steps)
             res[dt] = {"value": round(w.cells * steps / (ms * 1e-3), 1), "unit": "cell-updates/s",
                        "ms_per_step": round(ms / steps, 5),
                        "roofline": {k: r[k] for k in ("kernel", "achieved", "frac", "traffic", "mean_launch_us",
-                                                      "tiles")}}
+                                                      "whole_step", "tiles")}}
         out[name] = res
     return out
 
 
-def roofline(w, dtype, prof, traffic_rec):
+def roofline(w, dtype, prof, traffic_rec, ms_per_step=None):
     """Roofline of the dominant kernel: algorithmic bytes per launch over its
     mean launch duration inside steps (HIP events around every launch of
     the profiled steps, on the library's stream).  The back-to-back means
@@ -366,9 +379,14 @@ def roofline(w, dtype, prof, traffic_rec):
     traffic = None
     if traffic_rec:
         traffic = traffic_rec.get("bytes_per_launch", {}).get(dom)
+    step = None
+    if ms_per_step:
+        sb = step_bytes(w, esz)
+        sg = sb / (ms_per_step * 1e-3) / 1e9
+        step = {"bytes_per_step": sb, "achieved": round(sg, 1), "frac": round(sg / HBM_PEAK_GBS, 4)}
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": algo,
+            "algorithmic_bytes_per_launch": algo, "whole_step": step,
             "mean_launch_us": {k: round(v * 1e3, 2) for k, v in evt.items()},
             "mean_launch_us_back_to_back": {k: round(v * 1e3, 2) for k, v in b2b.items()},
             "tiles": tiles}
@@ -385,20 +403,57 @@ def load_traffic(workload, dtype):
     return rec
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """FP64 oracle on the host over a bounded number of steps."""
+def host_cpu():
+    """CPU model name, logical CPUs and the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model or platform.processor() or platform.machine(),
+            "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_rate(w, fft, budget_s):
+    """Cell-updates/s of the FP64 oracle over about budget_s seconds of steps."""
     from oracle import spectral
     t = time.perf_counter()
-    q = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, 1)
+    q = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, 1, fft=fft)
     one = time.perf_counter() - t
     nsteps = int(max(1, min(200, budget_s // max(one, 1e-6))))
     t = time.perf_counter()
-    spectral.step_n(q, w.model, w.coef, w.dt, w.dx, nsteps)
+    spectral.step_n(q, w.model, w.coef, w.dt, w.dx, nsteps, fft=fft)
     dt = time.perf_counter() - t
-    return {"value": round(w.cells * nsteps / dt, 1), "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d steps of the %s workload (after 1 untimed step), numpy FP64, "
-                      "single-threaded pocketfft on %s" % (nsteps, w.name, platform.processor() or platform.machine())}
+    return w.cells * nsteps / dt, nsteps
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The FP64 oracle on the host: its transforms on every usable core (at
+    most 16, the host share of one GPU), and on one thread."""
+    host = host_cpu()
+    threads = max(1, min(16, host["usable_cpus"]))
+    fft = None
+    try:
+        import scipy.fft as sfft
+        fft = (lambda a: sfft.fftn(a, workers=threads), lambda a: sfft.ifftn(a, workers=threads))
+    except ImportError:
+        threads = 1
+    v, n = oracle_rate(w, fft, budget_s)
+    v1, n1 = oracle_rate(w, None, budget_s)
+    return {"value": round(v, 1), "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d steps of the %s workload (after 1 untimed step), numpy FP64 oracle with its "
+                      "FFTs in scipy's pocketfft on %d threads (pointwise work on one)" % (n, w.name, threads),
+            "single_thread": {"value": round(v1, 1), "cores": 1, "steps": n1,
+                              "sample": "numpy's pocketfft, one thread"},
+            "host": host}
 
 
 def main():
@@ -459,14 +514,14 @@ def main():
                                    not args.no_autotune)
     value = w.cells * args.steps / (ms * 1e-3)
     sf1 = prof.pop("structure_factor", None)
-    roof = roofline(w, args.dtype, prof, load_traffic(args.workload, args.dtype))
+    roof = roofline(w, args.dtype, prof, load_traffic(args.workload, args.dtype), ms / args.steps)
     other = "f32" if args.dtype == "f64" else "f64"
     print("bench: %s done, %.3f ms/step; running %s" % (args.dtype, ms / args.steps, other),
           file=sys.stderr, flush=True)
     ms2, _, prof2, _ = run_gpu(w, other, args.steps, args.warmup, args.profile_steps,
                                not args.no_autotune)
     sf2 = prof2.pop("structure_factor", None)
-    roof2 = roofline(w, other, prof2, load_traffic(args.workload, other))
+    roof2 = roofline(w, other, prof2, load_traffic(args.workload, other), ms2 / args.steps)
     drift = float(abs(mass[-1][0] - mass[0][0])) if len(mass) else None
     adj = None
     if not args.no_adjoint:
@@ -488,6 +543,16 @@ def main():
     if not args.no_batch:
         print("bench: batched 64-grid workload", file=sys.stderr, flush=True)
         batch = run_batch()
+    summary = {"%s_%s" % (args.workload, args.dtype): {"kernel_frac": roof["frac"],
+                                                        "step_frac": roof["whole_step"]["frac"]},
+               "%s_%s" % (args.workload, other): {"kernel_frac": roof2["frac"],
+                                                  "step_frac": roof2["whole_step"]["frac"]}}
+    for name, res in (others or {}).items():
+        for dt in ("f64", "f32"):
+            r = res[dt]["roofline"]
+            summary["%s_%s" % (name, dt)] = {"kernel_frac": r["frac"], "step_frac": r["whole_step"]["frac"]}
+    if batch:
+        summary["batch64_f32"] = {"step_frac": batch["roofline"]["frac"]}
     out = {
         "metric": "grid cell-updates/sec per spectral step + % peak HBM BW",
         "value": round(value, 1),
@@ -504,6 +569,7 @@ def main():
         "config": {"workload": w.name, "equation": w.model, "grid": list(w.n), "dx": list(w.dx),
                    "dt": w.dt, "coef": list(w.coef), "mass_log": True, "parallelism": "1 GPU"},
         "roofline": roof,
+        "rooflines": summary,
         "other_dtype": {"dtype": other, "value": round(w.cells * args.steps / (ms2 * 1e-3), 1),
                         "ms_per_step": round(ms2 / args.steps, 5), "roofline": roof2},
         "mass_drift_over_run": drift,

@@ -46,7 +46,7 @@ typedef enum {
   SS_ERR_UNSUPPORTED = 2,  /* valid but not implemented (e.g. axis not 2^k) */
   SS_ERR_STATE = 3,        /* call out of order (no model, workspace, field) */
   SS_ERR_DEVICE = 4,       /* HIP runtime error */
-  SS_ERR_NONFINITE = 5     /* a checked value is NaN or infinite */
+  SS_ERR_NONFINITE = 5     /* ss_check_finite found a NaN or an infinity */
 } ss_status;
 
 typedef enum { SS_F32 = 4, SS_F64 = 8 } ss_dtype;
@@ -204,6 +204,18 @@ ss_status ss_get_field(ss_grid g, int field, void* dst, int dst_on_device);
  * Errors: SS_ERR_STATE (model, workspace or a field missing), SS_ERR_ARG,
  * SS_ERR_DEVICE. */
 ss_status ss_step_n(ss_grid g, int64_t nsteps);
+
+/* Optional finite check of the fields (failure detection): scans the
+ * stored state of every field (the spectral state, where a NaN or an
+ * infinity of any cell reaches every mode of its row, or the real fields
+ * of the finite-difference solver) on the grid's stream and synchronises.
+ * *nonfinite_fields = bit f set when field f holds a NaN or an infinity.
+ * Returns SS_ERR_NONFINITE when any bit is set, SS_OK otherwise.  Uses
+ * the first bytes of the grid's staging array.  Not called by ss_step_n,
+ * which stays asynchronous: callers check between runs of steps.
+ * Errors: SS_ERR_ARG (null), SS_ERR_STATE (no model, workspace or field),
+ * SS_ERR_DEVICE. */
+ss_status ss_check_finite(ss_grid g, int* nonfinite_fields);
 
 /* Same as ss_step_n, and times every kernel launch with HIP events
  * recorded on the grid's stream between consecutive launches.  On return

@@ -1759,6 +1759,31 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps) {
   return SS_OK;
 }
 
+ss_status ss_check_finite(ss_grid g, int* nonfinite_fields) {
+  if (!g || !nonfinite_fields) return fail(SS_ERR_ARG, "ss_check_finite: null argument");
+  if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_check_finite: model and workspace must be set first");
+  for (int f = 0; f < g->nf; ++f)
+    if (!g->field_set[f]) return fail(SS_ERR_STATE, "ss_check_finite: field %d was never set", f);
+  ss::FiniteArgs a;
+  memset(&a, 0, sizeof(a));
+  for (int f = 0; f < g->nf; ++f) a.arr[f] = g->state[f];
+  a.narr = g->nf;
+  a.n = g->cells();
+  a.flag = (unsigned*)g->staging;
+  SS_TRY(hip_check(g->dtype == SS_F64 ? ss::run_finite<double>(a, g->stream) : ss::run_finite<float>(a, g->stream),
+                   "ss_check_finite: launch"));
+  unsigned flag[2] = {0u, 0u};
+  SS_TRY(hip_check(hipMemcpyAsync(flag, g->staging, sizeof(flag), hipMemcpyDeviceToHost, g->stream),
+                   "ss_check_finite: copy"));
+  SS_TRY(hip_check(hipStreamSynchronize(g->stream), "ss_check_finite: synchronise"));
+  int mask = 0;
+  for (int f = 0; f < g->nf; ++f)
+    if (flag[f]) mask |= 1 << f;
+  *nonfinite_fields = mask;
+  if (mask) return fail(SS_ERR_NONFINITE, "ss_check_finite: non-finite values in field mask %d", mask);
+  return SS_OK;
+}
+
 ss_status ss_structure_factor_nbins(ss_grid g, int* nbins) {
   if (!g || !nbins) return fail(SS_ERR_ARG, "ss_structure_factor_nbins: null argument");
   *nbins = sf_nbins(g);

@@ -145,6 +145,8 @@ hipError_t run_sfreduce(SFArgs a, hipStream_t s);
 template <typename T>
 hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s);
 template <typename T>
+hipError_t run_finite(FiniteArgs a, hipStream_t s);
+template <typename T>
 hipError_t run_fd_eq(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s);
 
 #ifdef SS_DISPATCH_IMPL
@@ -465,7 +467,18 @@ hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <typename T>
+hipError_t run_finite(FiniteArgs a, hipStream_t s) {
+  if (a.narr < 1 || a.narr > 2 || a.n < 1 || !a.flag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finite_clear_kernel<T>, dim3(1), dim3(64), 0, s, a);
+  int64_t blocks = (a.n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(finite_kernel<T>, dim3((unsigned)blocks, (unsigned)a.narr), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 #define SS_INSTANTIATE(T)                                                                  \
+  template hipError_t run_finite<T>(FiniteArgs, hipStream_t);                             \
   template hipError_t run_kadj<T>(int, KAdjArgs, hipStream_t);                          \
   template hipError_t run_xadj<T>(int, XAdjArgs, hipStream_t);                          \
   template hipError_t run_batch_x<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \

@@ -1161,4 +1161,29 @@ __global__ void __launch_bounds__(256) sf_reduce_kernel(SFArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Finite check: flag[0] counts the arrays (of narr, n values each) holding
+// a NaN or an infinity; one atomic per offending block.
+// ---------------------------------------------------------------------------
+struct FiniteArgs {
+  const void* arr[2];
+  int narr;
+  int64_t n;
+  unsigned* flag;   // flag[a] != 0: array a is not finite
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64) finite_clear_kernel(FiniteArgs a) {
+  if (threadIdx.x < 2) a.flag[threadIdx.x] = 0u;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) finite_kernel(FiniteArgs a) {
+  const T* v = (const T*)a.arr[blockIdx.y];
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !__builtin_isfinite(v[i]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&a.flag[blockIdx.y], 1u);
+}
+
 }  // namespace ss

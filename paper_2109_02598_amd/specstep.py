@@ -88,6 +88,7 @@ def lib():
         "ss_batch_launch": [vp],
         "ss_batch_info": [vp, ctypes.POINTER(cint)],
         "ss_batch_destroy": [vp],
+        "ss_check_finite": [vp, ctypes.POINTER(cint)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -154,6 +155,15 @@ def ss_get_field(h, field, dst_ptr, on_device):
 
 def ss_step_n(h, nsteps):
     _check(lib().ss_step_n(h, int(nsteps)))
+
+
+def ss_check_finite(h):
+    """Bit mask of the fields holding a NaN or an infinity (0: all finite)."""
+    m = ctypes.c_int()
+    st = lib().ss_check_finite(h, ctypes.byref(m))
+    if st not in (SS_OK, SS_ERR_NONFINITE):
+        _check(st)
+    return m.value
 
 
 SS_NPASS = 4
@@ -419,8 +429,16 @@ class Grid:
             t = data.to(device=self.device, dtype=self.tdtype).contiguous()
             if tuple(t.shape) != self.shape:
                 raise ValueError("field shape %s != grid shape %s" % (tuple(t.shape), self.shape))
+            self._after_current_stream()
             ss_set_field(self.h, field, t.data_ptr(), True)
             torch.cuda.synchronize(self.device)   # t must outlive the copy
+
+    def _after_current_stream(self):
+        """Tensors just made on torch's current stream are read by the
+        library on the grid's stream: wait for the former first."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if self.stream != cur.cuda_stream:
+            cur.synchronize()
 
     def get_field(self, field, out=None):
         torch = self.torch
@@ -471,8 +489,13 @@ class Grid:
         torch = self.torch
         dqT = [t.to(device=self.device, dtype=self.tdtype).contiguous() for t in dqT]
         out = [torch.empty(self.shape, dtype=self.tdtype, device=self.device) for _ in dqT]
+        self._after_current_stream()
         dc = ss_adjoint_n(self.h, [t.data_ptr() for t in dqT], [t.data_ptr() for t in out])
         return out, dc
+
+    def check_finite(self):
+        """Bit mask of the fields holding a NaN or an infinity (0: all finite)."""
+        return ss_check_finite(self.h)
 
     def enable_mass_log(self, capacity):
         self.mass_buf = self.torch.zeros(capacity * self.nfields, dtype=self.torch.float64,

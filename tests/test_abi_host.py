@@ -130,3 +130,21 @@ def test_batch_validation(L):
     finally:
         for h in hs:
             ss.ss_destroy_grid(h)
+
+
+def test_finite_check_validation(L):
+    """Argument and state checks of ss_check_finite (refused before any
+    device work)."""
+    fake = 1 << 40
+    m = ctypes.c_int()
+    assert L.ss_check_finite(None, ctypes.byref(m)) == ss.SS_ERR_ARG
+    h = ss.ss_create_grid((64, 32), (1, 1), ss.SS_F64)
+    try:
+        assert L.ss_check_finite(h, None) == ss.SS_ERR_ARG
+        assert L.ss_check_finite(h, ctypes.byref(m)) == ss.SS_ERR_STATE       # no model
+        ss.ss_set_model(h, 2, (1, 1, 1, 1), 0.1)
+        assert L.ss_check_finite(h, ctypes.byref(m)) == ss.SS_ERR_STATE       # no workspace
+        ss.ss_bind_workspace(h, fake, ss.ss_workspace_size(h))
+        assert L.ss_check_finite(h, ctypes.byref(m)) == ss.SS_ERR_STATE       # no field
+    finally:
+        ss.ss_destroy_grid(h)

@@ -56,3 +56,28 @@ def test_roofline_object():
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
     assert r["traffic"] == 134480000.0
     assert r["mean_launch_us_back_to_back"]["kpass"] == pytest.approx(24.6)
+
+
+def test_whole_step_fraction():
+    w = W((2048, 2048), 1)
+    prof = {"xpass": (200 * 0.0214, 200), "kpass": (200 * 0.0245, 200),
+            "mean_b2b": {"xpass": 0.0212, "kpass": 0.0246}, "tiles": None}
+    r = bench.roofline(w, "f32", dict(prof), None, 0.050)
+    ws = r["whole_step"]
+    assert ws["bytes_per_step"] == 6 * 2048 * 2048 * 4
+    assert ws["achieved"] == pytest.approx(6 * 2048 * 2048 * 4 / 50e-6 / 1e9, rel=1e-3)
+    assert ws["frac"] == pytest.approx(ws["achieved"] / 8000.0, rel=1e-3)
+    assert bench.step_bytes(W((256, 256, 256), 1), 8) == 10 * 256 ** 3 * 8
+    assert bench.step_bytes(W((512, 512), 2), 4) == 12 * 512 * 512 * 4
+
+
+def test_cpu_baseline_uses_the_host_cores():
+    """The oracle leg on a tiny workload: the threaded and the one-thread
+    figures, the core count and the CPU model are reported."""
+    from paper_2109_02598_amd import inputs
+    w = inputs.allen_cahn_2d(n=32, seed=1, steps=2)
+    r = bench.cpu_baseline(w, budget_s=0.2)
+    assert r["kind"] == "oracle" and r["value"] > 0
+    assert r["cores"] == max(1, min(16, r["host"]["usable_cpus"]))
+    assert r["single_thread"]["cores"] == 1 and r["single_thread"]["value"] > 0
+    assert r["host"]["cpu_model"] and r["host"]["nproc"] >= 1

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import operator_split as osp
 from tests import _equations as eqs
-from tests._common import COEF, TOL, as_input, need_gpu, rel_l2, run_gpu, say, synth_fields
+from tests._common import COEF, TOL, as_input, assert_parity, need_gpu, rel_l2, run_gpu, say, synth_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -36,10 +36,7 @@ def gpu_equations(text, coefs, n, dx, dt, steps, fields, dtype, scheme="etd1", m
 
 
 def check(got, want, dtype, what):
-    for i, (a, b) in enumerate(zip(got, want)):
-        e = rel_l2(a, b)
-        say(what, "field", i, dtype, "rel_l2 %.3e" % e)
-        assert e <= TOL[dtype], (what, i, e)
+    assert_parity(got, want, dtype, what)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

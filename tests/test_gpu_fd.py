@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import fd_euler
-from tests._common import COEF, TOL, as_input, need_gpu, rel_l2, say, synth_fields
+from tests._common import COEF, TOL, as_input, assert_parity, need_gpu, rel_l2, say, synth_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -43,10 +43,7 @@ def test_euler_vs_oracle(model, n, stencil, dtype):
     got = gpu_euler(model, n, dx, dt, steps, [f.astype(np.float32) if dtype == "f32" else f for f in fields],
                     dtype, stencil)
     ref = fd_euler.euler_n(as_input(fields, dtype), model, COEF_FD[model], dt, dx, steps, stencil)
-    for a, b in zip(got, ref):
-        e = rel_l2(a, b)
-        say(model, n, stencil, dtype, "rel_l2 %.3e" % e)
-        assert e <= TOL[dtype]
+    assert_parity(list(got), list(ref), dtype, (model, n, stencil))
 
 
 @pytest.mark.parametrize("stencil,n", [(0, (128, 64)), (9, (64, 64)), (19, (32, 32, 32)), (27, (32, 32, 32)),

@@ -8,7 +8,7 @@ import pytest
 from oracle import fd_euler
 from oracle import operator_split as osp
 from tests import _equations as eqs
-from tests._common import COEF, TOL, as_input, need_gpu, rel_l2, say, synth_fields
+from tests._common import COEF, TOL, as_input, assert_parity, need_gpu, rel_l2, say, synth_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +19,10 @@ DT_FIXED = {"allen_cahn": 0.05, "cahn_hilliard": 0.01, "pfc": 0.0005, "gray_scot
 CASES = [((64, 32), 0), ((32, 64), 9), ((32, 64), 4), ((16, 8, 32), 0), ((16, 16, 16), 19),
          ((16, 16, 16), 27), ((16, 8, 32), 4),
          # grids the marching kernels tile (rows of 256, tiles of 64 x 4 x 8)
-         ((256, 16), 9), ((512, 8), 4), ((64, 8, 16), 27), ((64, 8, 16), 0)]
+         ((256, 16), 9), ((512, 8), 4), ((64, 8, 16), 27), ((64, 8, 16), 0),
+         # the 2D axis-wise and the 3D fourth-order marching tiles (two rows a
+         # thread, a two-cell rim), in both precisions
+         ((256, 32), 0), ((64, 8, 32), 4)]
 
 
 def gpu_euler_eq(text, coefs, n, dx, dt, steps, fields, dtype, stencil):
@@ -49,10 +52,7 @@ def stable_dt(split, ndim, stencil, h=1.0, frac=0.4):
 
 
 def check(got, want, dtype, what):
-    for i, (a, b) in enumerate(zip(got, want)):
-        e = rel_l2(a, b)
-        say(what, "field", i, dtype, "rel_l2 %.3e" % e)
-        assert e <= TOL[dtype], (what, i, e)
+    assert_parity(got, want, dtype, what)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
