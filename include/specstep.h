@@ -107,11 +107,15 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
  * fields).  Terms linear in the field itself form L (symbol lap -> -|k|^2,
  * at most lap^3, so L(k^2) is at most cubic in k^2).  All other terms --
  * constants, terms in the other field, nonlinear terms -- are explicit and
- * are evaluated pointwise from the fields of the current step.  Limits of
- * the GPU step: the explicit terms of a field all sit under the same
- * derivative, 1 or lap (one B_i per field), in at most 8 monomials with
- * exponents at most 7.  A derivative multiplied by a field (psi lap psi)
- * has no operator form and is refused.
+ * are evaluated pointwise from the fields of the current step; the explicit
+ * terms under the same derivative lap^p form one channel i with operator
+ * B_i = B (-k^2)^p (Sec. 2.4.2, the pairing of L_* and N terms by
+ * derivative).  Limits of the GPU step: at most two channels per field,
+ * p <= 3, each with at most 8 monomials with exponents at most 7 (a
+ * second channel costs one more forward transform and one more array per
+ * field: the workspace grows by nfields arrays); the finite-difference
+ * solver takes one channel per field.  A derivative multiplied by a field
+ * (psi lap psi) has no operator form and is refused.
  *
  * scheme 0: ETD1 factors A = exp(L dt), B = (exp(L dt) - 1)/L (Eq. 4).
  * scheme 1: linearly implicit factors A = 1/(1 - L dt), B = dt/(1 - L dt),
@@ -135,13 +139,17 @@ ss_status ss_set_equations(ss_grid g, const char* equations, const char* const n
 
 /* Host-only: the split ss_set_equations performs, without a grid or a
  * device.  out (at least SS_SPLIT_OUT_LEN doubles) receives out[0] = the
- * number of fields and, for field j at o = out + 1 + 30 j: o[0..3] = the
- * coefficients of L in 1, k^2, k^4, k^6; o[4] = p, the derivative lap^p
- * of the explicit terms (-1: none); o[5] = m, their number of monomials;
- * then for i < m: o[6 + 3i] = coefficient, o[7 + 3i], o[8 + 3i] = the
- * exponents of fields 0 and 1.  Unused entries are 0.
+ * number of fields and, for field j at o = out + 1 + SS_SPLIT_FIELD_LEN j:
+ * o[0..3] = the coefficients of L in 1, k^2, k^4, k^6; o[4] = the number
+ * of explicit channels (0, 1 or 2, in ascending derivative order); channel
+ * c at q = o + 5 + SS_SPLIT_CHANNEL_LEN c: q[0] = p, its derivative lap^p;
+ * q[1] = m, its number of monomials; then for i < m: q[2 + 3i] =
+ * coefficient, q[3 + 3i], q[4 + 3i] = the exponents of fields 0 and 1.
+ * Unused entries are 0.
  * Errors: as ss_set_equations (no grid checks). */
-#define SS_SPLIT_OUT_LEN 61
+#define SS_SPLIT_CHANNEL_LEN 26
+#define SS_SPLIT_FIELD_LEN (5 + 2 * SS_SPLIT_CHANNEL_LEN)
+#define SS_SPLIT_OUT_LEN (1 + 2 * SS_SPLIT_FIELD_LEN)
 ss_status ss_split_equations(const char* equations, const char* const names[], const double values[],
                              int nvalues, double* out, int nout);
 

@@ -69,7 +69,9 @@ struct ss_grid_s {
   ss::KField kf[2];
   int nlm = ss::NLIN_POLY;
   double p[5] = {0};
-  ss::NTab tab = {};   // explicit terms of equations read at run time (NLIN_TABLE)
+  ss::NTab tab = {};   // explicit terms of equations read at run time (NLIN_TABLE), channel 0
+  ss::NTab tab2 = {};  // the second explicit channel of each field (nsets = 2)
+  int nsets = 1;       // x passes per step: 2 when a field has two explicit channels
   int scheme = 0;      // 0: ETD1 factors; 1: linearly implicit (ss_set_equations)
   ss::EqSplit eq = {};  // the split of ss_set_equations (finite-difference solver)
 
@@ -79,6 +81,7 @@ struct ss_grid_s {
   void* scratch[2] = {nullptr, nullptr};
   void* staging = nullptr;
   void* shat[2] = {nullptr, nullptr};   // full spectrum of each field (stepping form)
+  void* scratch2[2] = {nullptr, nullptr};   // second channel's nonlinear term (nsets = 2)
   // forward-Euler finite-difference solver (solver 1): real-space fields in
   // state[], the next step's in fd_next[], intermediates in fd_tmp[]
   int solver = 0;
@@ -229,6 +232,8 @@ void carve_workspace(ss_grid g) {
   }
   g->staging = b + (size_t)(2 * g->nf) * fb;
   for (int f = 0; f < 2; ++f) g->shat[f] = f < g->nf ? b + (size_t)(2 * g->nf + 1 + f) * fb : nullptr;
+  for (int f = 0; f < 2; ++f)
+    g->scratch2[f] = (g->nsets == 2 && f < g->nf) ? b + (size_t)(3 * g->nf + 1 + f) * fb : nullptr;
   g->shat_valid = false;
 }
 
@@ -324,15 +329,15 @@ void ensure_tiles(ss_grid g) {
 
 // Coefficients of the x pass's pointwise terms (fixed models) or their
 // monomial table (equations read at run time).
-void fill_nonlinear(ss_grid g, ss::XArgs& a) {
+void fill_nonlinear(ss_grid g, ss::XArgs& a, int set = 0) {
   for (int i = 0; i < 5; ++i) a.p[i] = g->p[i];
-  a.tab = g->tab;
+  a.tab = set == 0 ? g->tab : g->tab2;
 }
 
 template <typename T>
 ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void* in1, void* out0,
                        void* out1, const void* real_in, void* real_out, double scale,
-                       PassTimer* pt = nullptr, int nlm = -1) {
+                       PassTimer* pt = nullptr, int nlm = -1, int set = 0) {
   ss::XArgs a;
   memset(&a, 0, sizeof(a));
   a.spec_in[0] = in0;
@@ -350,7 +355,7 @@ ss_status launch_xpass(ss_grid g, int mode, int nf, const void* in0, const void*
   a.rows_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_step : g->tile_x_io;
   a.tiles_per_block = (mode == ss::XMODE_STEP) ? g->tile_x_ppb : 0;
   a.lb = g->lb;
-  fill_nonlinear(g, a);
+  fill_nonlinear(g, a, set);
   return hip_check(ss::run_xpass<T>((int)g->n[0], nf, mode, nlm >= 0 ? nlm : g->nlm, a, g->stream,
                                     take_events(pt, PASS_X)),
                    "x pass launch");
@@ -389,6 +394,7 @@ ss_status launch_kpass(ss_grid g, PassTimer* pt = nullptr, int mode = 1, int arr
     a.fld[f].nonlin = arr == 1 ? g->state[f] : g->scratch[f];   // G
     a.fld[f].out = arr == 2 ? g->scratch[f] : nullptr;           // T: over G, else to the state
     a.fld[f].shat = g->shat[f];
+    a.fld[f].nonlin2 = (mode == 1 && g->nsets == 2) ? g->scratch2[f] : nullptr;
   }
   a.J = three ? (int)g->n[1] : 1;
   a.nlines = (int)(g->n[0] / 2) * a.J;
@@ -438,6 +444,32 @@ ss_status step_once(ss_grid g, PassTimer* pt, bool hat = true) {
   // goes to the scratch arrays and the k-space pass writes T over it, and
   // the two arrays swap roles.  The three-transform form reads T and G
   // together and keeps G in the scratch arrays.
+  if (g->nsets == 2) {
+    // two explicit channels: channel 1's terms go to scratch2 first, then
+    // channel 0's over the state (2D) or into scratch (3D); the k-space
+    // pass transforms both and writes T over channel 0's array
+    if (!hat) return fail(SS_ERR_UNSUPPORTED, "two explicit channels: stepping form only");
+    if (g->ndim == 2) {
+      SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], g->scratch2[0], g->scratch2[1],
+                             nullptr, nullptr, 1.0, pt, -1, 1));
+      SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->state[0], g->state[1], g->state[0], g->state[1],
+                             nullptr, nullptr, 1.0, pt, -1, 0));
+      SS_TRY(launch_kpass<T>(g, pt, 1, 1));
+    } else {
+      for (int f = 0; f < g->nf; ++f) SS_TRY(launch_ypass<T>(g, +1, g->state[f], g->scratch[f], 1.0, pt));
+      SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->scratch[0], g->scratch[1], g->scratch2[0], g->scratch2[1],
+                             nullptr, nullptr, 1.0, pt, -1, 1));
+      SS_TRY(launch_xpass<T>(g, ss::XMODE_STEP, g->nf, g->scratch[0], g->scratch[1], g->scratch[0], g->scratch[1],
+                             nullptr, nullptr, 1.0, pt, -1, 0));
+      for (int f = 0; f < g->nf; ++f) {
+        SS_TRY(launch_ypass<T>(g, -1, g->scratch2[f], g->scratch2[f], 1.0, pt));
+        SS_TRY(launch_ypass<T>(g, -1, g->scratch[f], g->scratch[f], 1.0, pt));
+      }
+      SS_TRY(launch_kpass<T>(g, pt, 1, 0));
+    }
+    g->log_count++;
+    return SS_OK;
+  }
   const int arr = hat ? g->step_arr : 0;
   void** G = arr == 1 ? g->state : g->scratch;
   if (g->ndim == 2) {
@@ -511,8 +543,12 @@ ss_status fd_eq_launch(ss_grid g, const ss::FDEq& q, int depth) {
   return hip_check(e, "finite-difference launch");
 }
 
+// derivative of field j's explicit channel (-1: none; the finite-difference
+// solver takes one channel per field)
+int fd_eq_p(const ss::EqSplit& sp, int j) { return sp.nch[j] > 0 ? sp.ch[j][0].p : -1; }
+
 int fd_eq_top(const ss::EqSplit& sp, int j) {
-  int D = sp.p[j] > 0 ? sp.p[j] : 0;
+  int D = fd_eq_p(sp, j) > 0 ? fd_eq_p(sp, j) : 0;
   for (int k = 1; k < 4; ++k)
     if (sp.L[j][k] != 0.0) D = std::max(D, k);
   return D;
@@ -525,9 +561,10 @@ ss_status fd_eq_step(ss_grid g) {
   memset(&q, 0, sizeof(q));
   for (int j = 0; j < sp.nf; ++j) {
     q.tab.dv[j] = 0;
-    for (int m = 0; m < sp.nterm[j]; ++m) {
-      const int e0 = sp.e[j][m][0], e1 = sp.e[j][m][1];
-      q.tab.a[j][e1][e0] += sp.c[j][m];
+    const int nterm = sp.nch[j] > 0 ? sp.ch[j][0].nterm : 0;
+    for (int m = 0; m < nterm; ++m) {
+      const int e0 = sp.ch[j][0].e[m][0], e1 = sp.ch[j][0].e[m][1];
+      q.tab.a[j][e1][e0] += sp.ch[j][0].c[m];
       q.tab.du[j][e1] = std::max(q.tab.du[j][e1], e0);
       q.tab.dv[j] = std::max(q.tab.dv[j], e1);
     }
@@ -540,14 +577,14 @@ ss_status fd_eq_step(ss_grid g) {
     q.j[s] = j;
     for (int d = 0; d <= depth; ++d) {
       q.cl[s][d] = (lo + d) % 2 ? -sp.L[j][lo + d] : sp.L[j][lo + d];   // k^2 -> -lap
-      q.el[s][d] = sp.p[j] == lo + d;
+      q.el[s][d] = fd_eq_p(sp, j) == lo + d;
     }
     q.w[s] = w;
     q.out[s] = out;
   };
   // the wider stencils take E at the centre only: E at the top level then
   // gets a launch of its own
-  auto own = [&](int j, int D) { return st != 0 && sp.p[j] == D && D > 0; };
+  auto own = [&](int j, int D) { return st != 0 && fd_eq_p(sp, j) == D && D > 0; };
   const int D0 = fd_eq_top(sp, 0), D1 = sp.nf > 1 ? fd_eq_top(sp, 1) : -1;
   if (sp.nf == 2 && D0 == D1 && D0 <= 1 && !own(0, D0) && !own(1, D1)) {
     q.nj = 2;
@@ -1526,6 +1563,7 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
   g->dt = dt;
   g->has_model = true;
   g->scheme = 0;
+  g->nsets = 1;
   build_operators(g);
   return SS_OK;
 }
@@ -1567,14 +1605,19 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
   for (int i = 0; i < SS_SPLIT_OUT_LEN; ++i) out[i] = 0.0;
   out[0] = sp.nf;
   for (int j = 0; j < sp.nf; ++j) {
-    double* o = out + 1 + 30 * j;
+    double* o = out + 1 + SS_SPLIT_FIELD_LEN * j;
     for (int i = 0; i < 4; ++i) o[i] = sp.L[j][i];
-    o[4] = sp.p[j];
-    o[5] = sp.nterm[j];
-    for (int m = 0; m < sp.nterm[j]; ++m) {
-      o[6 + 3 * m] = sp.c[j][m];
-      o[7 + 3 * m] = sp.e[j][m][0];
-      o[8 + 3 * m] = sp.e[j][m][1];
+    o[4] = sp.nch[j];
+    for (int c = 0; c < sp.nch[j]; ++c) {
+      const ss::EqChannel& ch = sp.ch[j][c];
+      double* q = o + 5 + SS_SPLIT_CHANNEL_LEN * c;
+      q[0] = ch.p;
+      q[1] = ch.nterm;
+      for (int m = 0; m < ch.nterm; ++m) {
+        q[2 + 3 * m] = ch.c[m];
+        q[3 + 3 * m] = ch.e[m][0];
+        q[4 + 3 * m] = ch.e[m][1];
+      }
     }
   }
   return SS_OK;
@@ -1597,23 +1640,36 @@ ss_status ss_set_equations(ss_grid g, const char* equations, const char* const n
   memset(&tab, 0, sizeof(tab));
   double kmax2 = 0.0;
   for (int d = 0; d < g->ndim; ++d) kmax2 += (M_PI / g->dx[d]) * (M_PI / g->dx[d]);
+  ss::NTab tab2;
+  memset(&tab2, 0, sizeof(tab2));
+  int nsets = 1;
+  for (int j = 0; j < sp.nf; ++j) nsets = std::max(nsets, sp.nch[j]);
+  if (nsets == 2 && g->solver == 1)
+    return fail(SS_ERR_UNSUPPORTED, "ss_set_equations: the finite-difference solver takes one explicit channel per field");
   for (int j = 0; j < sp.nf; ++j) {
     for (int i = 0; i < 4; ++i) kf[j].l[i] = sp.L[j][i];
-    if (sp.p[j] == 0) kf[j].n[0] = 1.0;
-    if (sp.p[j] == 1) kf[j].n[1] = -1.0;   // lap -> -k^2
-    // monomials -> dense table: a[j][power of field 1][power of field 0]
-    for (int m = 0; m < sp.nterm[j]; ++m) {
-      const int e0 = sp.e[j][m][0], e1 = sp.e[j][m][1];
-      tab.a[j][e1][e0] += sp.c[j][m];
-      tab.du[j][e1] = std::max(tab.du[j][e1], e0);
-      tab.dv[j] = std::max(tab.dv[j], e1);
+    for (int c = 0; c < sp.nch[j]; ++c) {
+      const ss::EqChannel& ch = sp.ch[j][c];
+      double* n = c == 0 ? kf[j].n : kf[j].n2;
+      n[ch.p] = (ch.p & 1) ? -1.0 : 1.0;   // lap^p -> (-k^2)^p
+      // monomials -> dense table: a[j][power of field 1][power of field 0]
+      ss::NTab& t = c == 0 ? tab : tab2;
+      for (int m = 0; m < ch.nterm; ++m) {
+        const int e0 = ch.e[m][0], e1 = ch.e[m][1];
+        t.a[j][e1][e0] += ch.c[m];
+        t.du[j][e1] = std::max(t.du[j][e1], e0);
+        t.dv[j] = std::max(t.dv[j], e1);
+      }
     }
     for (int k = 0; k < 8; ++k)
-      for (int i = 0; i < 8; ++i) tab.af[j][k][i] = (float)tab.a[j][k][i];
+      for (int i = 0; i < 8; ++i) {
+        tab.af[j][k][i] = (float)tab.a[j][k][i];
+        tab2.af[j][k][i] = (float)tab2.a[j][k][i];
+      }
     if (scheme == 1 && !(max_symbol(kf[j].l, kmax2) * dt < 1.0))
       return fail(SS_ERR_ARG, "ss_set_equations: 1 - L dt is not positive for every mode of field %d", j);
   }
-  const bool same = g->has_model && g->model == SS_EQUATIONS && g->nf == sp.nf;
+  const bool same = g->has_model && g->model == SS_EQUATIONS && g->nf == sp.nf && g->nsets == nsets;
   if (g->has_model && !same) {
     g->ws = nullptr;
     g->ws_bytes = 0;
@@ -1630,6 +1686,8 @@ ss_status ss_set_equations(ss_grid g, const char* equations, const char* const n
   g->kf[0] = kf[0];
   g->kf[1] = kf[1];
   g->tab = tab;
+  g->tab2 = tab2;
+  g->nsets = nsets;
   g->eq = sp;
   g->nlm = ss::NLIN_TABLE;
   g->has_model = true;
@@ -1639,7 +1697,8 @@ ss_status ss_set_equations(ss_grid g, const char* equations, const char* const n
 ss_status ss_workspace_size(ss_grid g, size_t* bytes) {
   if (!g || !bytes) return fail(SS_ERR_ARG, "ss_workspace_size: null argument");
   if (!g->has_model) return fail(SS_ERR_STATE, "ss_workspace_size: call ss_set_model first");
-  *bytes = align_up(g->field_bytes()) * (size_t)(g->solver == 1 ? 2 * g->nf + 3 : 3 * g->nf + 1);
+  *bytes = align_up(g->field_bytes()) *
+           (size_t)(g->solver == 1 ? 2 * g->nf + 3 : 3 * g->nf + 1 + (g->nsets == 2 ? g->nf : 0));
   return SS_OK;
 }
 
@@ -1662,6 +1721,8 @@ ss_status ss_set_solver(ss_grid g, int solver, int stencil) {
   if (solver != 0 && solver != 1) return fail(SS_ERR_ARG, "ss_set_solver: unknown solver %d", solver);
   if (solver == 1 && g->has_model && g->model == SS_EQUATIONS && g->scheme != 0)
     return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the finite-difference solver is explicit (scheme 0)");
+  if (solver == 1 && g->has_model && g->model == SS_EQUATIONS && g->nsets != 1)
+    return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the finite-difference solver takes one explicit channel per field");
   if (solver == 1) {
     const bool ok = stencil == 0 || stencil == 4 ||
                     (g->ndim == 2 ? (stencil == 5 || stencil == 9) : (stencil == 7 || stencil == 19 || stencil == 27));

@@ -240,6 +240,13 @@ hipError_t launch_k(KArgs a, int mode, hipStream_t s, LaunchEvents ev) {
   dim3 grid((unsigned)(a.nlines / L), (unsigned)a.nf), block((unsigned)(L * (NL / 8)));
   dim3 block_hat((unsigned)(L * (NL / k_pts(ESZ, NL))));
   if (mode == 2) return launch_with(kfwd_kernel<T, NL>, grid, block, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  const bool ch2 = a.fld[0].nonlin2 != nullptr;
+  if (mode == 1 && ch2) {
+    if (a.nf == 2 && !a.fld[1].nonlin2) return hipErrorInvalidValue;
+    return a.scheme == 1
+               ? launch_with(kpass_kernel<T, NL, true, 1, true>, grid, block_hat, (uint32_t)k_lds(ESZ, NL, L), s, ev, a)
+               : launch_with(kpass_kernel<T, NL, true, 0, true>, grid, block_hat, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
+  }
   if (mode == 1 && a.scheme == 1)
     return launch_with(kpass_kernel<T, NL, true, 1>, grid, block_hat, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);
   if (mode == 1) return launch_with(kpass_kernel<T, NL, true>, grid, block_hat, (uint32_t)k_lds(ESZ, NL, L), s, ev, a);

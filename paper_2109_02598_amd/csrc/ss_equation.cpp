@@ -11,8 +11,8 @@
 //     the procedure; nonlinear terms, the N) is explicit; explicit terms
 //     under the same derivative d are paired into one channel d applied to
 //     E, with B d as its operator.
-// The GPU step evaluates E pointwise from a table of monomials and carries
-// one channel per field, with d = 1 or lap.
+// The GPU step evaluates each channel's E pointwise from a table of
+// monomials; a field carries up to two channels, d = lap^p with p <= 3.
 //
 // Text: one equation per field, separated by ';' or newlines, each
 // "name' = expression"; numbers, coefficient names, field names, + - * /,
@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace ss {
@@ -360,7 +361,6 @@ void split_all(const char* text, const char* const names[], const double values[
     Poly e = r.sum();
     if (r.kind() != T_END) fail(1, "trailing '%s' in the equation of '%s'", r.text().c_str(), fields[j].c_str());
     // L_psi: terms linear in field j itself; the symbol of lap^p is (-k^2)^p
-    int chan_p = -1;
     for (const Term& x : e.t) {
       if (!std::isfinite(x.c)) fail(1, "a coefficient of '%s' overflows", fields[j].c_str());
       const bool self = x.e[j] == 1 && x.e[1 - j] == 0;
@@ -369,22 +369,29 @@ void split_all(const char* text, const char* const names[], const double values[
         out->L[j][x.p] += (x.p & 1) ? -x.c : x.c;
         continue;
       }
-      // explicit (L_* or N): one derivative per field on the GPU
-      if (chan_p >= 0 && x.p != chan_p)
-        fail(2, "'%s': explicit terms under lap^%d and lap^%d; one derivative per field", fields[j].c_str(),
-             chan_p, x.p);
-      if (x.p > 1) fail(2, "'%s': explicit terms under lap^%d; lap is the highest", fields[j].c_str(), x.p);
+      // explicit (L_* or N): terms under the same derivative form one channel
+      if (x.p > EQ_MAX_LAP)
+        fail(2, "'%s': explicit terms under lap^%d; lap^%d is the highest", fields[j].c_str(), x.p, EQ_MAX_LAP);
       if (x.e[0] > EQ_MAX_EXP || x.e[1] > EQ_MAX_EXP)
         fail(2, "'%s': exponent above %d in an explicit term", fields[j].c_str(), EQ_MAX_EXP);
-      const int m = out->nterm[j];
-      if (m >= EQ_MAX_TERMS) fail(2, "'%s': more than %d explicit monomials", fields[j].c_str(), EQ_MAX_TERMS);
-      chan_p = x.p;
-      out->c[j][m] = x.c;
-      out->e[j][m][0] = x.e[0];
-      out->e[j][m][1] = x.e[1];
-      out->nterm[j] = m + 1;
+      int c = 0;
+      while (c < out->nch[j] && out->ch[j][c].p != x.p) ++c;
+      if (c == out->nch[j]) {
+        if (c >= EQ_MAX_CH)
+          fail(2, "'%s': explicit terms under more than %d derivatives", fields[j].c_str(), EQ_MAX_CH);
+        out->ch[j][c].p = x.p;
+        out->nch[j] = c + 1;
+      }
+      EqChannel& ch = out->ch[j][c];
+      if (ch.nterm >= EQ_MAX_TERMS)
+        fail(2, "'%s': more than %d explicit monomials under lap^%d", fields[j].c_str(), EQ_MAX_TERMS, x.p);
+      ch.c[ch.nterm] = x.c;
+      ch.e[ch.nterm][0] = x.e[0];
+      ch.e[ch.nterm][1] = x.e[1];
+      ch.nterm++;
     }
-    out->p[j] = chan_p;
+    // ascending derivative order
+    if (out->nch[j] == 2 && out->ch[j][0].p > out->ch[j][1].p) std::swap(out->ch[j][0], out->ch[j][1]);
   }
 }
 

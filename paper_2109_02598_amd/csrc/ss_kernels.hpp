@@ -665,10 +665,12 @@ __global__ void __launch_bounds__(1024) ypass_kernel(YArgs a) {
 struct KField {
   void* state;              // T (read; written too unless `out` is set)
   const void* nonlin;       // G
+  const void* nonlin2;      // a second explicit channel's G (stepping form; null: none)
   void* out;                // where the new T goes (null: in place)
   void* shat;               // stepping form: the state's full spectrum S^, read and rewritten
   double l[4];              // L(k^2) = l0 + l1 k^2 + l2 k^4 + l3 k^6
-  double n[2];              // N(k^2) = n0 + n1 k^2
+  double n[4];              // N(k^2) = n0 + n1 k^2 + n2 k^4 + n3 k^6 (the channel's derivative)
+  double n2[4];             // the second channel's N(k^2)
 };
 
 struct KArgs {
@@ -724,10 +726,15 @@ __device__ __forceinline__ void etd1_aphi(T z, T& A, T& phi, T& em) {
 // A = 1/(1 - L dt), B = dt A N (the host has checked 1 - L dt > 0).
 // The scheme is a compile-time choice: a run-time branch here costs the
 // FP64 k-space kernels registers they do not have.
+template <typename T>
+__device__ __forceinline__ T kpoly3(const double (&c)[4], T k2) {
+  return (T)c[0] + k2 * ((T)c[1] + k2 * ((T)c[2] + k2 * (T)c[3]));
+}
+
 template <typename T, int SCH = 0>
 __device__ __forceinline__ void etd1_coeffs(const KField& f, T k2, double dt, double as, double bs,
                                             T& ao, T& bo) {
-  const T L = (T)f.l[0] + k2 * ((T)f.l[1] + k2 * ((T)f.l[2] + k2 * (T)f.l[3]));
+  const T L = kpoly3<T>(f.l, k2);
   const T z = L * (T)dt;
   T A, phi, em;
   if constexpr (SCH == 1) {
@@ -737,7 +744,27 @@ __device__ __forceinline__ void etd1_coeffs(const KField& f, T k2, double dt, do
     etd1_aphi<T>(z, A, phi, em);
   }
   ao = A * (T)as;
-  bo = (T)dt * phi * ((T)f.n[0] + (T)f.n[1] * k2) * (T)bs;
+  bo = (T)dt * phi * kpoly3<T>(f.n, k2) * (T)bs;
+}
+
+// The same with two explicit channels: B N_1 and B N_2 (Eq. 8, a sum over
+// the channels i of B_i = B d_i).
+template <typename T, int SCH = 0>
+__device__ __forceinline__ void etd1_coeffs2(const KField& f, T k2, double dt, double as, double bs,
+                                             T& ao, T& bo, T& bo2) {
+  const T L = kpoly3<T>(f.l, k2);
+  const T z = L * (T)dt;
+  T A, phi, em;
+  if constexpr (SCH == 1) {
+    A = (T)1 / ((T)1 - z);
+    phi = A;
+  } else {
+    etd1_aphi<T>(z, A, phi, em);
+  }
+  ao = A * (T)as;
+  const T b = (T)dt * phi * (T)bs;
+  bo = b * kpoly3<T>(f.n, k2);
+  bo2 = b * kpoly3<T>(f.n2, k2);
 }
 
 // Offset of element u (0 <= u < N_last) of a k-space line from the line's
@@ -810,8 +837,11 @@ struct KCfg {
 // nonlinear term is transformed; U = A S^ + B N G^ is written back as the
 // new S^ and, inverse transformed, as the new T (two transforms per line;
 // the host passes a_scale = 1).
-template <typename T, int NL, bool HAT = false, int SCH = 0, int P = 8>
+// CH2 (stepping form only): the field has a second explicit channel whose
+// term G2 (F.nonlin2) is transformed too: U = A S^ + B (N_1 G^ + N_2 G2^).
+template <typename T, int NL, bool HAT = false, int SCH = 0, int P = 8, bool CH2 = false>
 __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>* lds) {
+  static_assert(!CH2 || HAT, "a second channel needs the stepping form");
   typedef KCfg<T, NL, P> K;
   constexpr int S = K::S, REG = K::REG;
   const int tid = threadIdx.x;
@@ -833,7 +863,7 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
   const C<T>* gn = (const C<T>*)F.nonlin + lbase;
   C<T>* so = (C<T>*)(F.out ? F.out : F.state) + lbase;
 
-  C<T> ct[1][P], cg[1][P];
+  C<T> ct[1][P], cg[1][P], cg2[1][CH2 ? P : 1];
   // the three-transform form transforms the state first; the stepping
   // form reads S^ only for the update, after the nonlinear term's
   // transform (fewer live registers during it)
@@ -856,6 +886,12 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
     for (int i = 0; i < Twiddles<T, NL, P>::NW; ++i) twl[i * twstride] = tw.w[i];
   }
   if constexpr (!HAT) fft_lines<T, NL, -1, 1, P>(ct, x, t, ktw<T, NL, P>(tw, twl, twstride));
+  if constexpr (CH2) {
+    const C<T>* gn2 = (const C<T>*)F.nonlin2 + lbase;
+#pragma unroll
+    for (int e = 0; e < P; ++e) cg2[0][e] = *kline_at(gn2, kline_off(e * S, hx, lb), tb);
+    fft_lines<T, NL, -1, 1, P>(cg2, x, t, ktw<T, NL, P>(tw, twl, twstride));
+  }
 #pragma unroll
   for (int e = 0; e < P; ++e) cg[0][e] = *kline_at(gn, kline_off(e * S, hx, lb), tb);
   fft_lines<T, NL, -1, 1, P>(cg, x, t, ktw<T, NL, P>(tw, twl, twstride));
@@ -921,11 +957,41 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
         const T bp = (T)0.5 * (b0 + bn), bmn = (T)0.5 * (b0 - bn);
         ct[0][e] = mk<T>(ct[0][e].x + bp * cg[0][e].x + bmn * dm.x,
                          ct[0][e].y + bp * cg[0][e].y + bmn * dm.y);
+      } else if constexpr (CH2) {
+        const T k2 = kxv * kxv + kmid2 + kl * kl;
+        T av, bv, bv2;
+        etd1_coeffs2<T, SCH>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv, bv2);
+        ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x + bv2 * cg2[0][e].x,
+                         av * ct[0][e].y + bv * cg[0][e].y + bv2 * cg2[0][e].y);
       } else {
         const T k2 = kxv * kxv + kmid2 + kl * kl;
         T av, bv;
         etd1_coeffs<T, SCH>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
         ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
+      }
+    }
+    if constexpr (CH2) {
+      // the second channel's two packed halves, through the same region
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < P; ++e) x[0][pidx<T>(t + e * S)] = cg2[0][e];
+      __syncthreads();
+      if (packed) {
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+          __builtin_amdgcn_sched_barrier(0);
+          const int p = t + e * S;
+          const int m = p <= NL / 2 ? p : p - NL;
+          const T kl = (T)m * klast_s;
+          const T k2_0 = kmid2 + kl * kl;
+          T a0, b0, b20, an, bn, b2n;
+          etd1_coeffs2<T, SCH>(F, k2_0, a.dt, a.a_scale, a.b_scale, a0, b0, b20);
+          etd1_coeffs2<T, SCH>(F, k2_0 + kny * kny, a.dt, a.a_scale, a.b_scale, an, bn, b2n);
+          const C<T> dm = cconj<T>(xm[pidx<T>((NL - p) & (NL - 1))]);
+          const T bp = (T)0.5 * (b20 + b2n), bmn = (T)0.5 * (b20 - b2n);
+          ct[0][e] = mk<T>(ct[0][e].x + bp * cg2[0][e].x + bmn * dm.x,
+                           ct[0][e].y + bp * cg2[0][e].y + bmn * dm.y);
+        }
       }
     }
     if (packed && a.mass_log && kyi == 0 && t == 0 && a.log_index < a.log_capacity)
@@ -939,9 +1005,16 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
       const int m = p <= NL / 2 ? p : p - NL;
       const T kl = (T)m * klast_s;
       const T k2 = kxv * kxv + kmid2 + kl * kl;
-      T av, bv;
-      etd1_coeffs<T, SCH>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
-      ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
+      if constexpr (CH2) {
+        T av, bv, bv2;
+        etd1_coeffs2<T, SCH>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv, bv2);
+        ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x + bv2 * cg2[0][e].x,
+                         av * ct[0][e].y + bv * cg[0][e].y + bv2 * cg2[0][e].y);
+      } else {
+        T av, bv;
+        etd1_coeffs<T, SCH>(F, k2, a.dt, a.a_scale, a.b_scale, av, bv);
+        ct[0][e] = mk<T>(av * ct[0][e].x + bv * cg[0][e].x, av * ct[0][e].y + bv * cg[0][e].y);
+      }
     }
   }
 
@@ -957,13 +1030,15 @@ __device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>*
 
 // FP64: three waves per SIMD (168 VGPRs), except 128- and 256-point lines,
 // whose 3D plane pairing needs ~176 VGPRs (spills under the cap of three).
-template <typename T, int NL, bool HAT, int SCH = 0>
+// Two explicit channels (CH2) hold a third line of registers: FP64 takes
+// two waves per SIMD there.
+template <typename T, int NL, bool HAT, int SCH = 0, bool CH2 = false>
 __global__ void __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? ((NL == 128 || NL == 256) ? 2 : 3) : SS_KWAVES)))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? ((NL == 128 || NL == 256 || CH2) ? 2 : 3) : SS_KWAVES)))
 kpass_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
-  kpass_body<T, NL, HAT, SCH, HAT ? k_pts((int)sizeof(C<T>), NL) : 8>(a, blockIdx.x, blockIdx.y,
-                                                                      reinterpret_cast<C<T>*>(ss_dyn_lds));
+  kpass_body<T, NL, HAT, SCH, HAT ? k_pts((int)sizeof(C<T>), NL) : 8, CH2>(a, blockIdx.x, blockIdx.y,
+                                                                           reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
 
 // S^ = FFT(T) / N_last along every line of field blockIdx.y (the stepping

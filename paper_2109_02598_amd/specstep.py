@@ -233,7 +233,9 @@ def ss_set_step_arrangement(h, arr):
 
 SOLVERS = {"spectral": 0, "euler": 1}
 SCHEMES = {"etd1": 0, "implicit": 1}
-SPLIT_OUT_LEN = 61
+SPLIT_CHANNEL_LEN = 26
+SPLIT_FIELD_LEN = 5 + 2 * SPLIT_CHANNEL_LEN
+SPLIT_OUT_LEN = 1 + 2 * SPLIT_FIELD_LEN
 
 
 def _coef_arrays(coefs):
@@ -251,16 +253,21 @@ def ss_set_equations(h, text, coefs, dt, scheme=0):
 
 def ss_split_equations(text, coefs=None):
     """The split of ss_set_equations, host only: a list with, per field,
-    {"L": [l0, l1, l2, l3], "p": p, "terms": [(c, e0, e1), ...]}."""
+    {"L": [l0, l1, l2, l3], "channels": [{"p": p, "terms": [(c, e0, e1), ...]}, ...]}
+    (channels in ascending derivative order lap^p)."""
     cn, cv, n = _coef_arrays(coefs)
     out = (ctypes.c_double * SPLIT_OUT_LEN)()
     _check(lib().ss_split_equations(text.encode(), cn, cv, n, out, SPLIT_OUT_LEN))
     res = []
     for j in range(int(out[0])):
-        o = out[1 + 30 * j: 31 + 30 * j]
-        m = int(o[5])
-        res.append({"L": list(o[0:4]), "p": int(o[4]),
-                    "terms": [(o[6 + 3 * i], int(o[7 + 3 * i]), int(o[8 + 3 * i])) for i in range(m)]})
+        o = out[1 + SPLIT_FIELD_LEN * j: 1 + SPLIT_FIELD_LEN * (j + 1)]
+        chans = []
+        for c in range(int(o[4])):
+            q = o[5 + SPLIT_CHANNEL_LEN * c: 5 + SPLIT_CHANNEL_LEN * (c + 1)]
+            m = int(q[1])
+            chans.append({"p": int(q[0]),
+                          "terms": [(q[2 + 3 * i], int(q[3 + 3 * i]), int(q[4 + 3 * i])) for i in range(m)]})
+        res.append({"L": list(o[0:4]), "channels": chans})
     return res
 
 

@@ -86,6 +86,66 @@ def test_equations_outside_the_fixed_set(name, n, dtype, scheme):
     check(got, want, dtype, (name, n, scheme))
 
 
+# equations whose explicit terms sit under two derivatives in one field: an
+# identity channel and a Laplacian-power channel (two B_i of Eq. 8)
+TWO_CHANNELS = {
+    "ac_plus_conserved_cubic": (("psi' = lap(psi) - psi^3 + 0.5*lap(psi^3)", {}), 0.05, (0.1, 0.0)),
+    "gray_scott_cross_diffusion": (("u' = 0.2*lap(u) - u*v^2 + 0.03*(1 - u) + 0.01*lap(u^2*v)\n"
+                                    "v' = 0.1*lap(v) + u*v^2 - 0.09*v", {}), 0.5, (0.8, 0.25)),
+    "coupled_lap_and_bilap": (("a' = -a + lap(b + 0.2*b^2) + 0.5*a*b; b' = 0.5*lap(b) - a*b + 0.05 - 0.005*bilap(a^2)", {}),
+                              0.05, (0.2, 0.3)),
+    "conserved_with_a_source": (("m' = -bilap(m) - lap(0.2*m - m^3) - 0.1*m^3 + 0.05", {}), 0.05, (0.1, 0.0)),
+}
+
+
+@pytest.mark.parametrize("scheme", ["etd1", "implicit"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name", sorted(TWO_CHANNELS))
+@pytest.mark.parametrize("n", [(128, 64), (32, 16, 16), (8, 256)])
+def test_two_explicit_channels(name, n, dtype, scheme):
+    (text, coefs), dt, off = TWO_CHANNELS[name]
+    sp = osp.parse(text, coefs)
+    assert max(len(c) for c in sp.channels) == 2, "the text must need two channels"
+    assert any(p == 0 for p, _, _ in sp.channels[0]), "one channel without a derivative"
+    dx = tuple(1.0 + 0.05 * i for i in range(len(n)))
+    shape = tuple(reversed(n))
+    f0 = as_input(smooth_fields(len(sp.fields), shape, 37, offsets=off), dtype)
+    got, _ = gpu_equations(text, coefs, n, dx, dt, 50, f0, dtype, scheme)
+    want = osp.step_n(f0, sp, dt, dx, 50, scheme)
+    check(got, want, dtype, (name, n, scheme))
+
+
+def test_two_channels_are_refused_by_the_finite_difference_solver():
+    torch, specstep = need_gpu()
+    (text, coefs), _, _ = TWO_CHANNELS["ac_plus_conserved_cubic"]
+    g = specstep.Grid((32, 32), (1.0, 1.0), equations=text, coefs=coefs, dt=0.01)
+    with pytest.raises(specstep.SpecStepError) as e:
+        specstep.ss_set_solver(g.h, 1, 0)
+    assert e.value.code == specstep.SS_ERR_UNSUPPORTED
+    g.close()
+    h = specstep.Grid((32, 32), (1.0, 1.0), equations="psi' = lap(psi) - psi^3", coefs={}, dt=0.01,
+                      solver="euler")
+    with pytest.raises(specstep.SpecStepError) as e:
+        specstep.ss_set_equations(h.h, text, coefs, 0.01)
+    assert e.value.code == specstep.SS_ERR_UNSUPPORTED
+    h.close()
+
+
+def test_two_channels_keep_the_mass_of_a_conserved_pair():
+    """Both channels under lap: nothing enters the k = 0 mode."""
+    text = "c' = lap(c^3 - c) - 0.5*bilap(c) + 0.1*bilap(c^2)"
+    sp = osp.parse(text, {})
+    assert [p for p, _, _ in sp.channels[0]] == [1, 2]
+    n = (128, 128)
+    f0 = smooth_fields(1, (128, 128), 5, offsets=(0.1,))
+    got, mass = gpu_equations(text, {}, n, (1.0, 1.0), 0.02, 200, f0, "f64", mass_capacity=200)
+    m0 = float(np.mean(f0[0]))
+    drift = float(np.max(np.abs(mass[:, 0] - m0)))
+    say("two-channel conserved mass drift", drift)
+    assert drift < 1e-15
+    check(got, osp.step_n(f0, sp, 0.02, (1.0, 1.0), 200), "f64", "two-channel conserved")
+
+
 def test_autotuned_tiles_keep_parity():
     text, coefs = eqs.FITZHUGH_NAGUMO
     n, dx = (256, 128), (1.0, 1.0)
@@ -113,7 +173,7 @@ def test_replacing_equations_and_errors():
     g = specstep.Grid((32, 32), (1.0, 1.0), equations="psi' = lap(psi) - psi^3", coefs={}, dt=0.1)
     g.set_field(0, np.zeros((32, 32)))
     E = specstep.SpecStepError
-    for text, code in (("psi' = lap(psi) - psi^3 + lap(psi^2)", 2), ("psi' = bilap(psi^3)", 2),
+    for text, code in (("psi' = lap(psi) - psi^3 + lap(psi^2) + bilap(psi^2)", 2), ("psi' = bilap(bilap(psi^3))", 2),
                        ("psi' = psi*lap(psi)", 2), ("psi' = foo", 1), ("a' = a; b' = b; c' = c", 2)):
         with pytest.raises(E) as e:
             specstep.ss_set_equations(g.h, text, {}, 0.1)
@@ -181,7 +241,7 @@ def test_the_library_split_of_the_extremes_is_the_oracles():
                 for ex, c in list(e0.items()) + list(e1.items()):
                     key = tuple(ex) + (0,) * (2 - len(ex))
                     merged[key] = merged.get(key, 0.0) + c
-            lib = {(e0, e1): c for c, e0, e1 in got[j]["terms"]}
+            lib = {(e0, e1): c for ch in got[j]["channels"] for c, e0, e1 in ch["terms"]}
             assert set(lib) == set(merged), name
             for k in lib:
                 assert lib[k] == pytest.approx(merged[k], rel=1e-14), (name, k)
