@@ -213,6 +213,40 @@ ss_status ss_get_field(ss_grid g, int field, void* dst, int dst_on_device);
  * SS_ERR_DEVICE. */
 ss_status ss_step_n(ss_grid g, int64_t nsteps);
 
+/* ---- Stepping without allocation ----
+ *
+ * For callers that cannot allocate device memory or bind a workspace at
+ * the point of the call: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.
+ *
+ * ss_step_fields_noalloc(g, fields, nsteps) does what ss_set_field (device
+ * source) for every field, ss_step_n(g, nsteps) and ss_get_field (device
+ * destination) for every field do, with the same arithmetic and results,
+ * but keeps the spectral state and its spectrum in a fixed device array of
+ * the library (SS_NOALLOC_SCRATCH_BYTES = 64 MiB per GPU, held from the
+ * first use on that GPU until the process ends) instead of the grid's
+ * workspace, and calls no allocating routine.
+ *   fields[f]: device pointer to field f (0 .. nfields-1), a (nz, ny, nx)
+ *     array of the grid dtype, read as the initial state and overwritten
+ *     with the state after nsteps.  Caller-owned.
+ *   Needs a model (ss_set_model / ss_set_equations), not a workspace; the
+ *   grid's own workspace and fields are left untouched.  Steps are logged
+ *   in the bound mass log like ss_step_n's.  Spectral solver only.
+ *   Asynchronous on the grid's stream, which must belong to the current
+ *   device.  Every call on one GPU uses the same array, which keeps the
+ *   last call's contents: calls that overlap on one GPU (other streams,
+ *   other threads) race and must be ordered by the caller.
+ * ss_noalloc_scratch_bytes: *need = bytes this grid needs in the array
+ *   (2 nfields arrays of 256-byte-aligned field size; with two explicit
+ *   channels per field (ss_set_equations) nfields more in 2D, 2 nfields
+ *   more in 3D), *limit = its size.
+ * Errors: SS_ERR_ARG (null, nsteps < 0, need > limit, stream on another
+ * device), SS_ERR_STATE (no model), SS_ERR_UNSUPPORTED (finite-difference
+ * solver), SS_ERR_DEVICE. */
+#define SS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ss_status ss_step_fields_noalloc(ss_grid g, void* const fields[], int64_t nsteps);
+ss_status ss_noalloc_scratch_bytes(ss_grid g, size_t* need, size_t* limit);
+
 /* Optional finite check of the fields (failure detection): scans the
  * stored state of every field (the spectral state, where a NaN or an
  * infinity of any cell reaches every mode of its row, or the real fields

@@ -1820,6 +1820,128 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps) {
   return SS_OK;
 }
 
+}  // extern "C"
+
+// ---- stepping without allocation --------------------------------------------
+// The arrays of ss_step_fields_noalloc live in one fixed device array of
+// the library (each GPU the library runs on holds its own copy, allocated
+// when the code object loads, until the process ends).  In host code the
+// name is only a stand-in: kernels and copies take the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[SS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+ss_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  SS_TRY(hip_check(hipGetDevice(&dev), "ss_step_fields_noalloc: current device"));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SS_ERR_DEVICE, "ss_step_fields_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SS_TRY(hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "ss_step_fields_noalloc: address of the scratch array"));
+    if (!p || ((uintptr_t)p) % kAlign) return fail(SS_ERR_DEVICE, "ss_step_fields_noalloc: scratch array misplaced");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SS_OK;
+}
+
+// Arrays a no-allocation call carves from the fixed array: the state and
+// its spectrum (2 nf), and with two explicit channels the second channel's
+// terms (nf) and, in 3D, the real-y arrays the x passes read (nf).
+size_t noalloc_arrays(ss_grid g) {
+  size_t n = 2 * (size_t)g->nf;
+  if (g->nsets == 2) n += (size_t)g->nf * (g->ndim == 3 ? 2 : 1);
+  return n;
+}
+
+// set_field + step_n + get_field with the state and its spectrum carved
+// from `base` and every pass in place; the grid's own arrays and flags are
+// put back afterwards.
+template <typename T>
+ss_status step_fields_t(ss_grid g, void* const fields[], int64_t nsteps, char* base) {
+  const size_t fb = align_up(g->field_bytes());
+  void* keep_state[2] = {g->state[0], g->state[1]};
+  void* keep_scratch[2] = {g->scratch[0], g->scratch[1]};
+  void* keep_shat[2] = {g->shat[0], g->shat[1]};
+  void* keep_scratch2[2] = {g->scratch2[0], g->scratch2[1]};
+  void* keep_staging = g->staging;
+  const bool keep_valid = g->shat_valid;
+  const int keep_arr = g->step_arr;
+  for (int f = 0; f < 2; ++f) {
+    g->state[f] = f < g->nf ? base + (size_t)f * fb : nullptr;
+    g->scratch[f] = g->state[f];   // 3D read-out: inverse y pass in place
+    g->shat[f] = f < g->nf ? base + (size_t)(g->nf + f) * fb : nullptr;
+    g->scratch2[f] = nullptr;
+    if (g->nsets == 2 && f < g->nf) {
+      g->scratch2[f] = base + (size_t)(2 * g->nf + f) * fb;
+      if (g->ndim == 3) g->scratch[f] = base + (size_t)(3 * g->nf + f) * fb;
+    }
+  }
+  g->staging = nullptr;
+  g->shat_valid = false;
+  ensure_tiles(g);
+  g->step_arr = 1;   // every pass in place: T and S^ only
+  ss_status st = SS_OK;
+  for (int f = 0; f < g->nf && st == SS_OK; ++f) st = set_field_t<T>(g, f, fields[f]);
+  if (st == SS_OK && nsteps > 0) st = ensure_shat<T>(g);
+  for (int64_t i = 0; i < nsteps && st == SS_OK; ++i) st = step_once<T>(g, nullptr);
+  for (int f = 0; f < g->nf && st == SS_OK; ++f) st = get_field_t<T>(g, f, fields[f]);
+  for (int f = 0; f < 2; ++f) {
+    g->state[f] = keep_state[f];
+    g->scratch[f] = keep_scratch[f];
+    g->shat[f] = keep_shat[f];
+    g->scratch2[f] = keep_scratch2[f];
+  }
+  g->staging = keep_staging;
+  g->shat_valid = keep_valid;
+  g->step_arr = keep_arr;
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+ss_status ss_noalloc_scratch_bytes(ss_grid g, size_t* need, size_t* limit) {
+  if (!g || !need || !limit) return fail(SS_ERR_ARG, "ss_noalloc_scratch_bytes: null argument");
+  if (!g->has_model) return fail(SS_ERR_STATE, "ss_noalloc_scratch_bytes: call ss_set_model first");
+  *need = noalloc_arrays(g) * align_up(g->field_bytes());
+  *limit = (size_t)SS_NOALLOC_SCRATCH_BYTES;
+  return SS_OK;
+}
+
+ss_status ss_step_fields_noalloc(ss_grid g, void* const fields[], int64_t nsteps) {
+  if (!g || !fields) return fail(SS_ERR_ARG, "ss_step_fields_noalloc: null argument");
+  if (nsteps < 0) return fail(SS_ERR_ARG, "ss_step_fields_noalloc: nsteps must be >= 0");
+  if (!g->has_model) return fail(SS_ERR_STATE, "ss_step_fields_noalloc: call ss_set_model first");
+  if (g->solver == 1) return fail(SS_ERR_UNSUPPORTED, "ss_step_fields_noalloc: spectral solver only");
+  for (int f = 0; f < g->nf; ++f)
+    if (!fields[f]) return fail(SS_ERR_ARG, "ss_step_fields_noalloc: field %d is null", f);
+  const size_t need = noalloc_arrays(g) * align_up(g->field_bytes());
+  if (need > (size_t)SS_NOALLOC_SCRATCH_BYTES)
+    return fail(SS_ERR_ARG, "ss_step_fields_noalloc: this grid needs %zu bytes of scratch, the library's fixed array holds %zu",
+                need, (size_t)SS_NOALLOC_SCRATCH_BYTES);
+  if (g->stream) {   // the null stream is the current device's
+    int sdev = -1, cdev = -1;
+    SS_TRY(hip_check(hipStreamGetDevice(g->stream, &sdev), "ss_step_fields_noalloc: stream device"));
+    SS_TRY(hip_check(hipGetDevice(&cdev), "ss_step_fields_noalloc: current device"));
+    if (sdev != cdev)
+      return fail(SS_ERR_ARG, "ss_step_fields_noalloc: the grid's stream is on device %d, device %d is current", sdev, cdev);
+  }
+  void* base = nullptr;
+  SS_TRY(scratch_for_current_device(&base));
+  return g->dtype == SS_F64 ? step_fields_t<double>(g, fields, nsteps, (char*)base)
+                            : step_fields_t<float>(g, fields, nsteps, (char*)base);
+}
+
 ss_status ss_check_finite(ss_grid g, int* nonfinite_fields) {
   if (!g || !nonfinite_fields) return fail(SS_ERR_ARG, "ss_check_finite: null argument");
   if (!g->has_model || !g->ws) return fail(SS_ERR_STATE, "ss_check_finite: model and workspace must be set first");

@@ -89,6 +89,8 @@ def lib():
         "ss_batch_info": [vp, ctypes.POINTER(cint)],
         "ss_batch_destroy": [vp],
         "ss_check_finite": [vp, ctypes.POINTER(cint)],
+        "ss_step_fields_noalloc": [vp, ctypes.POINTER(vp), i64],
+        "ss_noalloc_scratch_bytes": [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -155,6 +157,17 @@ def ss_get_field(h, field, dst_ptr, on_device):
 
 def ss_step_n(h, nsteps):
     _check(lib().ss_step_n(h, int(nsteps)))
+
+
+def ss_step_fields_noalloc(h, field_ptrs, nsteps):
+    ptrs = [int(p) for p in field_ptrs]
+    _check(lib().ss_step_fields_noalloc(h, (ctypes.c_void_p * len(ptrs))(*ptrs), int(nsteps)))
+
+
+def ss_noalloc_scratch_bytes(h):
+    need, limit = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().ss_noalloc_scratch_bytes(h, ctypes.byref(need), ctypes.byref(limit)))
+    return need.value, limit.value
 
 
 def ss_check_finite(h):

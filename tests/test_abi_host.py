@@ -148,3 +148,30 @@ def test_finite_check_validation(L):
         assert L.ss_check_finite(h, ctypes.byref(m)) == ss.SS_ERR_STATE       # no field
     finally:
         ss.ss_destroy_grid(h)
+
+
+def test_noalloc_validation(L):
+    """Argument and state checks of ss_step_fields_noalloc (refused before
+    any device work)."""
+    fake = 1 << 40
+    h = ss.ss_create_grid((64, 32), (1, 1), ss.SS_F64)
+    try:
+        assert code_of(ss.ss_step_fields_noalloc, h, [fake], 1) == ss.SS_ERR_STATE
+        assert code_of(ss.ss_noalloc_scratch_bytes, h) == ss.SS_ERR_STATE
+        ss.ss_set_model(h, 2, (1, 1, 1, 1), 0.1)
+        need, limit = ss.ss_noalloc_scratch_bytes(h)
+        assert need == 2 * 64 * 32 * 8 and limit == 64 << 20
+        assert code_of(ss.ss_step_fields_noalloc, h, [0], 1) == ss.SS_ERR_ARG
+        assert code_of(ss.ss_step_fields_noalloc, h, [fake], -1) == ss.SS_ERR_ARG
+        assert L.ss_step_fields_noalloc(h, None, 1) == ss.SS_ERR_ARG
+    finally:
+        ss.ss_destroy_grid(h)
+    big = ss.ss_create_grid((256, 256, 256), (1, 1, 1), ss.SS_F32)
+    try:
+        ss.ss_set_model(big, 3, (-0.25, 1, 0, 1), 0.5)
+        need, limit = ss.ss_noalloc_scratch_bytes(big)
+        assert need == 2 * 256 ** 3 * 4 > limit
+        assert code_of(ss.ss_step_fields_noalloc, big, [fake], 1) == ss.SS_ERR_ARG
+        assert "scratch" in ss.ss_last_error()
+    finally:
+        ss.ss_destroy_grid(big)
