@@ -133,7 +133,8 @@ def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
 
 def run_batch(steps=500, reps=3):
     """64 uneven Cahn-Hilliard grids (FP32): one captured graph of `steps`
-    batched steps, against the same members stepped one grid at a time."""
+    batched steps in each form (grouped launches, one launch), the tuned
+    form eager, and the same members stepped one grid at a time."""
     import torch
     from paper_2109_02598_amd import inputs, specstep
     ws = inputs.cahn_hilliard_batch(count=64, steps=steps)
@@ -146,20 +147,34 @@ def run_batch(steps=500, reps=3):
         gs.append(g)
     cells = sum(w.cells for w in ws)
     b = specstep.Batch(gs, autotune=True, reps=reps)
-    b.capture(steps)
-    b.launch()                      # warm-up replay
-    torch.cuda.synchronize()
+    tuned_mode = b.mode()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+
+    def graph_ms(mode):
+        b.set_mode(mode)
+        b.capture(steps)
+        b.launch()                  # warm-up replay
+        b.check()
+        e0.record(stream)
+        b.launch()
+        e1.record(stream)
+        b.check()
+        return e0.elapsed_time(e1)
+
+    # both forms, each one captured graph of `steps` steps (the single launch
+    # needs one block size for both passes)
+    ms_modes = {0: graph_ms(0), 1: None}
+    try:
+        ms_modes[1] = graph_ms(1)
+    except specstep.SpecStepError:
+        pass
+    b.set_mode(tuned_mode)
+    ms_graph = ms_modes[tuned_mode]
     e0.record(stream)
-    b.launch()
+    b.step(steps)                   # the same steps, eager
     e1.record(stream)
-    torch.cuda.synchronize()
-    ms_graph = e0.elapsed_time(e1)
-    e0.record(stream)
-    b.step(steps)                   # the same steps as eager grouped launches
-    e1.record(stream)
-    torch.cuda.synchronize()
+    b.check()
     ms_eager = e0.elapsed_time(e1)
     # the plain path: every member on its own, one after another
     for g in gs:
@@ -185,7 +200,10 @@ def run_batch(steps=500, reps=3):
                          "unit": "GB/s", "frac": round(agg / HBM_PEAK_GBS, 4)},
             "cells": cells, "value": round(cells * steps / (ms_graph * 1e-3), 1),
             "unit": "cell-updates/s", "ms_graph_launch": round(ms_graph, 3),
-            "ms_eager_grouped": round(ms_eager, 3), "ms_sequential_plain": round(ms_plain, 3),
+            "mode": {0: "grouped launches", 1: "single launch"}[tuned_mode],
+            "ms_graph_grouped": round(ms_modes[0], 3),
+            "ms_graph_single_launch": None if ms_modes[1] is None else round(ms_modes[1], 3),
+            "ms_eager": round(ms_eager, 3), "ms_sequential_plain": round(ms_plain, 3),
             "speedup_vs_sequential_plain": round(ms_plain / ms_graph, 2),
             "threads_per_block": info[0], "x_tiles": info[1], "k_tiles": info[2]}
 

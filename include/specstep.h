@@ -161,13 +161,27 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
  *   Laplacian replaced by a finite-difference stencil
  *   (Sec. 2.2.2; periodic wrap; higher powers by composition):
  *   stencil 0 (or 5 in 2D, 7 in 3D): axis-wise central differences,
- *   sum_a (f[-1] - 2 f + f[+1]) / dx_a^2;  stencil 9 (2D) or 19 (3D): the
- *   isotropic stencils (4 edge + 1 corner - 20 centre) / (6 h^2) and
- *   (2 face + 1 edge - 24 centre) / (6 h^2), which need equal spacings;
- *   stencil 27 (3D): the isotropic (14 face + 3 edge + 1 corner
- *   - 128 centre) / (30 h^2), equal spacings; stencil 4: the fourth-order
+ *   sum_a (f[-1] - 2 f + f[+1]) / dx_a^2;  stencil 4: the fourth-order
  *   axis-wise stencil (fourth-order family, 9 points in 2D, 13 in 3D),
  *   sum_a (-f[-2] + 16 f[-1] - 30 f + 16 f[+1] - f[+2]) / (12 dx_a^2).
+ *   The isotropic stencils need equal spacings h (faces / edges / corners:
+ *   the neighbours at distance 1 / sqrt 2 / sqrt 3; A1, A2 the axis ones at
+ *   1 and 2, D1, D2 the diagonal ones at (1, 1) and (2, 2), K the 8 at
+ *   (1, 2) and (2, 1)), second order:
+ *     9 (2D):  (4 edges + corners - 20 centre) / (6 h^2);
+ *     15 (3D): (8 faces + corners - 56 centre) / (12 h^2);
+ *     19 (3D): (2 faces + edges - 24 centre) / (6 h^2);
+ *     21 (3D): (4 edges - corners - 40 centre) / (12 h^2) (its symbol is
+ *              +4/(3 h^2) at the checkerboard mode: explicit diffusion
+ *              with it amplifies that mode);
+ *     27 (3D): (14 faces + 3 edges + corners - 128 centre) / (30 h^2);
+ *   fourth order (2D only):
+ *     17: (128 A1 + 16 D1 - 8 A2 - D2 - 540 centre) / (120 h^2);
+ *     21: (52 A1 + 16 D1 - A2 - 2 K - 252 centre) / (60 h^2).
+ *   Sec. 2.2.2 names these point counts; the weights are those its
+ *   families' defining conditions fix on each point set (zero sum, second
+ *   moment 2 per axis, an error term that depends on |k| only: h^2 |k|^4
+ *   / 12 for second order, h^4 |k|^6 / 90 for fourth order).
  *   Explicit: stable only for dt below the stencil's limit (the caller's
  *   choice).  The fields live in real space; ss_set_field / ss_get_field /
  *   ss_step_n work as with the spectral solver; the mass log is not
@@ -179,6 +193,25 @@ ss_status ss_split_equations(const char* equations, const char* const names[], c
  * SS_ERR_UNSUPPORTED (isotropic stencil with unequal spacings; solver 1
  * for equations set with scheme 1). */
 ss_status ss_set_solver(ss_grid g, int solver, int stencil);
+
+/* Kernel that advances the spectral step (results agree to rounding).
+ * kind 0: the pass kernels, two launches per step (every grid).
+ * kind 1: one workgroup runs all the steps of a call of ss_step_n: the
+ *   spectral state of the grid stays in its registers and LDS between
+ *   steps (no launch, no HBM traffic per step) and the per-mode factors
+ *   A and B N are computed once per call into the grid's scratch and
+ *   staging arrays.  For the small grids on which the pass kernels are
+ *   latency-bound: 2D square grids of 16, 32, 64 or 128 points a side, one
+ *   field, the fixed models (SS_ALLEN_CAHN, SS_CAHN_HILLIARD, SS_PFC),
+ *   spectral solver.  The mass log is written as with kind 0.
+ * ss_autotune (while no field is stored) times both and keeps the faster
+ * unless ss_set_step_kernel chose; ss_get_step_kernel reports the kind
+ * ss_step_n uses.  ss_step_n_profiled, ss_time_pass and
+ * ss_step_fields_noalloc use the pass kernels.
+ * Errors: SS_ERR_ARG (kind), SS_ERR_STATE (no model), SS_ERR_UNSUPPORTED
+ * (kind 1 for another grid). */
+ss_status ss_set_step_kernel(ss_grid g, int kind);
+ss_status ss_get_step_kernel(ss_grid g, int* kind);
 
 /* Bytes of device workspace the grid needs (after ss_set_model or
  * ss_set_equations): for the spectral solver (3 nfields + 1) arrays of
@@ -379,22 +412,53 @@ typedef struct ss_batch_s* ss_batch;
  * (member without model or workspace). */
 ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out);
 
-/* Device bytes the batch needs for its member tables (caller-owned,
- * 256-byte aligned, bound with ss_batch_bind_workspace). */
+/* Device bytes the batch needs for its member tables and the counters of
+ * its single launch (caller-owned, 256-byte aligned, bound with
+ * ss_batch_bind_workspace). */
 ss_status ss_batch_workspace_size(ss_batch b, size_t* bytes);
 ss_status ss_batch_bind_workspace(ss_batch b, void* device_ptr, size_t bytes);
 
 /* Time each valid block size (128, 256, 512 threads) for the grouped
- * launches `reps` times and keep the fastest.  Fields are untouched (the
- * timed k-space launches run on the members' scratch arrays).
- * Synchronises the stream. */
+ * launches `reps` times and keep the fastest; then, unless ss_batch_set_mode
+ * fixed the form, time 8 steps as grouped launches against 8 steps in one
+ * launch and keep the faster form.  Fields are untouched (the timed
+ * launches run on the members' scratch arrays).  Synchronises the stream. */
 ss_status ss_batch_autotune(ss_batch b, int reps);
 
-/* Advance every member by nsteps (eager launches on the stream). */
+/* Form of the batched steps.  mode 0: grouped, two launches per step (x
+ * pass, k-space pass), each covering the tiles of every member, the kernel
+ * boundary ordering the passes.  mode 1: one launch for all the steps of a
+ * call: each workgroup, as it starts, draws one work item (a tile of one
+ * pass of one member at one step) from a ticket counter in (step, pass)
+ * order, and per-member counters of finished tiles order the passes of
+ * each member (its k-space tiles wait for its x tiles of the step, its next
+ * x tiles for its k-space tiles), so the members advance independently
+ * and the step boundary drains no launch; a small kernel resets the
+ * counters before each launch.  Both forms run the same tile code and give
+ * the same bits.  Mode 1 needs one block size for both passes
+ * (SS_ERR_UNSUPPORTED otherwise).  Waits inside the launch are bounded: one
+ * that runs out makes every later workgroup leave and is reported by
+ * ss_batch_check.  ss_batch_get_mode returns the current form (set here or
+ * by the tuner). */
+ss_status ss_batch_set_mode(ss_batch b, int mode);
+ss_status ss_batch_get_mode(ss_batch b, int* mode);
+
+/* Synchronise the batch's stream; SS_ERR_DEVICE if a single launch gave
+ * up a wait (its results are then incomplete). */
+ss_status ss_batch_check(ss_batch b);
+
+/* Bound of each wait of the single launch, in sleeps of about 128 cycles
+ * (default 2^22, a fraction of a second; 0 gives up at the first unmet
+ * wait, which tests of the failure path use). */
+ss_status ss_batch_set_wait_limit(ss_batch b, unsigned limit);
+
+/* Advance every member by nsteps on the stream (mode 0: 2 nsteps grouped
+ * launches; mode 1: one launch). */
 ss_status ss_batch_step_n(ss_batch b, int64_t nsteps);
 
 /* Capture nsteps batched steps into a HIP graph (replaces a previous
- * capture).  The batch's stream must not be the null stream. */
+ * capture): 2 nsteps grouped launches, or, in mode 1, the counter reset and
+ * one launch.  The batch's stream must not be the null stream. */
 ss_status ss_batch_capture(ss_batch b, int64_t nsteps);
 
 /* Replay the captured graph once on the batch's stream (nsteps steps). */

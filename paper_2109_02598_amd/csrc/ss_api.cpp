@@ -103,6 +103,10 @@ struct ss_grid_s {
   // scratch arrays and T over it, then state and scratch swap roles
   int step_arr = 1;
   bool step_arr_set = false;   // chosen by ss_set_step_arrangement: the tile cache leaves it alone
+  // 0: the pass kernels (two launches per step); 1: one workgroup runs a
+  // whole call of ss_step_n (small square one-field grids)
+  int step_kind = 0;
+  bool step_kind_set = false;  // chosen by ss_set_step_kernel: the tuner leaves it alone
   int lb = -1;          // log2 of the row block B of the spectral layout (-1: not chosen)
 
   // reverse mode: caller-owned workspace with checkpoints and segment
@@ -431,6 +435,44 @@ ss_status ensure_shat(ss_grid g) {
   return SS_OK;
 }
 
+// The one-workgroup step: 2D square grids N = 16 .. 128, one field, the
+// fixed models' pointwise terms, ETD1 factors.
+bool small_ok(ss_grid g) {
+  return g->ndim == 2 && g->nf == 1 && g->solver == 0 && g->nlm == ss::NLIN_POLY && g->scheme == 0 &&
+         g->n[0] == g->n[1] && ss::small_size_ok((int)g->n[0]);
+}
+
+// nsteps steps in one workgroup; the factor tables go to the scratch and
+// staging arrays (free between the steps of the stepping form)
+template <typename T>
+ss_status small_run(ss_grid g, int64_t nsteps) {
+  if (nsteps > 0x7fffffff) return fail(SS_ERR_ARG, "ss_step_n: too many steps for one run");
+  ensure_tiles(g);
+  ss::SmallArgs a;
+  memset(&a, 0, sizeof(a));
+  a.state = g->state[0];
+  a.shat = g->shat[0];
+  a.coef = g->scratch[0];
+  a.coef_nyq = g->staging;
+  a.lb = g->lb;
+  a.nsteps = (int)nsteps;
+  a.load_shat = g->shat_valid ? 1 : 0;
+  const double two_pi = 6.283185307179586476925286766559;
+  a.sx = two_pi / ((double)g->n[0] * g->dx[0]);
+  a.sy = two_pi / ((double)g->n[1] * g->dx[1]);
+  a.dt = g->dt;
+  a.b_scale = 1.0 / (double)g->cells();
+  a.f = g->kf[0];
+  for (int i = 0; i < 3; ++i) a.p[i] = g->p[i];
+  a.mass_log = g->mass_log;
+  a.log_index = g->log_count;
+  a.log_capacity = g->log_cap;
+  SS_TRY(hip_check(ss::run_small<T>((int)g->n[0], a, g->stream), "one-workgroup step launch"));
+  g->shat_valid = true;
+  g->log_count += nsteps;
+  return SS_OK;
+}
+
 // One step.  hat: the stepping form (S^ carried between steps; the caller
 // has made it valid); otherwise the three-transform form, which leaves S^
 // stale (the adjoint's checkpointed forward and its recomputation use it,
@@ -489,6 +531,10 @@ ss_status step_once(ss_grid g, PassTimer* pt, bool hat = true) {
 }
 
 // ---- forward-Euler finite-difference step (Sec. 2.4.1, 2.2.2) -------------
+// The kernels' stencil code: the axis-wise second-order stencil is 0 whether
+// it was named by its point count (5 in 2D, 7 in 3D) or not.
+int fd_kernel_stencil(ss_grid g) { return (g->stencil == 5 || g->stencil == 7) ? 0 : g->stencil; }
+
 ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* out0, void* out1, double s0) {
   ss::FDArgs a;
   memset(&a, 0, sizeof(a));
@@ -504,6 +550,9 @@ ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* o
   for (int d = 0; d < 3; ++d) a.ih2[d] = d < g->ndim ? 1.0 / (g->dx[d] * g->dx[d]) : 0.0;
   a.i6h2 = 1.0 / (6.0 * g->dx[0] * g->dx[0]);
   a.i30h2 = 1.0 / (30.0 * g->dx[0] * g->dx[0]);
+  a.i12h2 = 1.0 / (12.0 * g->dx[0] * g->dx[0]);
+  a.i60h2 = 1.0 / (60.0 * g->dx[0] * g->dx[0]);
+  a.i120h2 = 1.0 / (120.0 * g->dx[0] * g->dx[0]);
   a.dt = g->dt;
   a.op = op;
   if (op == ss::FD_UPD) {
@@ -511,7 +560,7 @@ ss_status fd_launch(ss_grid g, int op, const void* in0, const void* in1, void* o
   } else {
     for (int i = 0; i < g->ncoef && i < 6; ++i) a.p[i] = g->coef[i];
   }
-  const int st = (g->stencil == 9 || g->stencil == 19 || g->stencil == 27 || g->stencil == 4) ? g->stencil : 0;
+  const int st = fd_kernel_stencil(g);
   hipError_t e = g->dtype == SS_F64 ? ss::run_fd<double>(g->ndim, st, a, g->stream)
                                     : ss::run_fd<float>(g->ndim, st, a, g->stream);
   return hip_check(e, "finite-difference launch");
@@ -536,8 +585,11 @@ ss_status fd_eq_launch(ss_grid g, const ss::FDEq& q, int depth) {
   for (int d = 0; d < 3; ++d) a.ih2[d] = d < g->ndim ? 1.0 / (g->dx[d] * g->dx[d]) : 0.0;
   a.i6h2 = 1.0 / (6.0 * g->dx[0] * g->dx[0]);
   a.i30h2 = 1.0 / (30.0 * g->dx[0] * g->dx[0]);
+  a.i12h2 = 1.0 / (12.0 * g->dx[0] * g->dx[0]);
+  a.i60h2 = 1.0 / (60.0 * g->dx[0] * g->dx[0]);
+  a.i120h2 = 1.0 / (120.0 * g->dx[0] * g->dx[0]);
   a.dt = g->dt;
-  const int st = (g->stencil == 9 || g->stencil == 19 || g->stencil == 27 || g->stencil == 4) ? g->stencil : 0;
+  const int st = fd_kernel_stencil(g);
   hipError_t e = g->dtype == SS_F64 ? ss::run_fd_eq<double>(g->ndim, st, depth, a, q, g->stream)
                                     : ss::run_fd_eq<float>(g->ndim, st, depth, a, q, g->stream);
   return hip_check(e, "finite-difference launch");
@@ -556,7 +608,7 @@ int fd_eq_top(const ss::EqSplit& sp, int j) {
 
 ss_status fd_eq_step(ss_grid g) {
   const ss::EqSplit& sp = g->eq;
-  const int st = (g->stencil == 9 || g->stencil == 19 || g->stencil == 27 || g->stencil == 4) ? g->stencil : 0;
+  const int st = fd_kernel_stencil(g);
   ss::FDEq q;
   memset(&q, 0, sizeof(q));
   for (int j = 0; j < sp.nf; ++j) {
@@ -1054,6 +1106,33 @@ ss_status autotune_t(ss_grid g, int reps) {
       }
     g->tile_x_step = bx;
     g->tile_x_ppb = bppb;
+    // small grids: the pass kernels against one workgroup running the steps
+    if (small_ok(g) && !g->step_kind_set) {
+      const int n = 10 * reps;
+      float best_small = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipEvent_t e[2];
+        SS_TRY(hip_check(hipEventCreate(&e[0]), "hipEventCreate"));
+        SS_TRY(hip_check(hipEventCreate(&e[1]), "hipEventCreate"));
+        double* log = g->mass_log;
+        const int64_t count = g->log_count;
+        g->mass_log = nullptr;
+        ss_status st = hip_check(hipEventRecord(e[0], g->stream), "hipEventRecord");
+        if (st == SS_OK) st = small_run<T>(g, n);
+        if (st == SS_OK) st = hip_check(hipEventRecord(e[1], g->stream), "hipEventRecord");
+        if (st == SS_OK) st = hip_check(hipEventSynchronize(e[1]), "hipEventSynchronize");
+        float t = 0.f;
+        if (st == SS_OK) st = hip_check(hipEventElapsedTime(&t, e[0], e[1]), "hipEventElapsedTime");
+        g->mass_log = log;
+        g->log_count = count;
+        g->shat_valid = false;
+        hipEventDestroy(e[0]);
+        hipEventDestroy(e[1]);
+        SS_TRY(st);
+        best_small = std::min(best_small, t / (float)n);
+      }
+      g->step_kind = best_small < best_step ? 1 : 0;
+    }
   }
   std::lock_guard<std::mutex> lk(g_tile_mu);
   g_tile_cache[tile_key(g)] = Tiles{g->tile_x_step, g->tile_y, g->tile_k, g->tile_x_ppb, g->lb,
@@ -1083,6 +1162,11 @@ struct ss_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t graph_steps = 0;
+  // 0: grouped launches (two per step); 1: one launch per run (a workgroup
+  // per work item, ordered by a ticket counter)
+  int mode = 0;
+  bool mode_set = false;    // chosen by ss_batch_set_mode: the tuner leaves it alone
+  unsigned spin_limit = 1u << 22;   // sleeps a wait of the single launch takes before it gives up
 };
 
 namespace {
@@ -1181,6 +1265,29 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
 }
 
 size_t batch_table_bytes(ss_batch b) { return align_up(sizeof(ss::BatchMember) * b->grids.size()); }
+// after the two tables: ticket and error flag, then per-member counters
+size_t batch_sync_bytes(ss_batch b) { return align_up(sizeof(unsigned) * (2 + 2 * b->grids.size())); }
+
+ss::BatchSync batch_sync(ss_batch b, int64_t nsteps) {
+  ss::BatchSync y;
+  unsigned* base = (unsigned*)((char*)b->ws + 2 * batch_table_bytes(b));
+  y.ctl = base;
+  y.xdone = base + 2;
+  y.kdone = base + 2 + b->grids.size();
+  y.nsteps = (int)nsteps;
+  y.spin_limit = b->spin_limit;
+  return y;
+}
+
+// The single launch needs one block size for both passes.
+bool batch_single_ok(ss_batch b) { return b->uploaded && b->threads_x == b->threads; }
+
+// Steps one launch can hold: a workgroup per work item, and the dispatch
+// counts work-items (threads) in 32 bits.
+int64_t batch_single_max_steps(ss_batch b) {
+  const int64_t per_step = (int64_t)(b->x_total + b->k_total) * b->threads;
+  return std::max<int64_t>(1, (int64_t)0xffffffffLL / per_step);
+}
 
 ss_status batch_upload(ss_batch b, int threads) {
   if (!build_batch_table(b, threads, b->table, b->table_tune, b->x_total, b->k_total, b->lds_x, b->lds_k,
@@ -1236,6 +1343,52 @@ ss_status batch_launch_step(ss_batch b, bool tune_table, ss::LaunchEvents evx, s
 
 ss_status batch_step_once(ss_batch b) {
   return b->dtype == SS_F64 ? batch_launch_step<double>(b, false, {}, {}) : batch_launch_step<float>(b, false, {}, {});
+}
+
+// nsteps steps of every member in one launch (after the reset of its
+// counters): one workgroup per work item.
+template <typename T>
+ss_status batch_launch_single(ss_batch b, int64_t nsteps, bool tune_table, ss::LaunchEvents ev) {
+  if (!batch_single_ok(b))
+    return fail(SS_ERR_UNSUPPORTED, "batch: the single launch needs one block size for both passes");
+  if (nsteps < 1 || nsteps > batch_single_max_steps(b))
+    return fail(SS_ERR_ARG, "batch: %lld steps do not fit one launch", (long long)nsteps);
+  ss::BatchArgs a;
+  a.m = (const ss::BatchMember*)((char*)b->ws + (tune_table ? batch_table_bytes(b) : 0));
+  a.count = (int)b->grids.size();
+  a.x_total = b->x_total;
+  a.k_total = b->k_total;
+  return hip_check(ss::run_batch_single<T>(a, batch_sync(b, nsteps), b->threads,
+                                           std::max(b->lds_x, b->lds_k), b->stream, ev),
+                   "batch single launch");
+}
+
+// Synchronise the batch's stream and report a single launch whose bounded
+// wait ran out.
+ss_status batch_check_error(ss_batch b) {
+  if (!b->ws) return SS_OK;
+  unsigned flag = 0;
+  SS_TRY(hip_check(hipMemcpyAsync(&flag, batch_sync(b, 1).ctl + 1, sizeof(flag), hipMemcpyDeviceToHost, b->stream),
+                   "batch: error flag copy"));
+  SS_TRY(hip_check(hipStreamSynchronize(b->stream), "batch: synchronise"));
+  if (flag) return fail(SS_ERR_DEVICE, "batch: a single launch gave up waiting for a member's tiles");
+  return SS_OK;
+}
+
+ss_status batch_run(ss_batch b, int64_t nsteps) {
+  if (nsteps < 1) return SS_OK;
+  if (b->mode == 1) {
+    // one launch, or several in a row when the steps exceed one launch's size
+    for (int64_t done = 0; done < nsteps;) {
+      const int64_t n = std::min(nsteps - done, batch_single_max_steps(b));
+      SS_TRY(b->dtype == SS_F64 ? batch_launch_single<double>(b, n, false, {})
+                                : batch_launch_single<float>(b, n, false, {}));
+      done += n;
+    }
+    return SS_OK;
+  }
+  for (int64_t i = 0; i < nsteps; ++i) SS_TRY(batch_step_once(b));
+  return SS_OK;
 }
 
 }  // namespace
@@ -1716,6 +1869,25 @@ ss_status ss_set_step_arrangement(ss_grid g, int arr) {
   return SS_OK;
 }
 
+ss_status ss_set_step_kernel(ss_grid g, int kind) {
+  if (!g) return fail(SS_ERR_ARG, "ss_set_step_kernel: null grid");
+  if (kind != 0 && kind != 1) return fail(SS_ERR_ARG, "ss_set_step_kernel: kind %d is not 0 or 1", kind);
+  if (kind == 1 && !g->has_model) return fail(SS_ERR_STATE, "ss_set_step_kernel: call ss_set_model first");
+  if (kind == 1 && !small_ok(g))
+    return fail(SS_ERR_UNSUPPORTED,
+                "ss_set_step_kernel: one workgroup takes 2D square one-field grids of 16 to 128 points a side, "
+                "the fixed models, spectral solver");
+  g->step_kind = kind;
+  g->step_kind_set = true;
+  return SS_OK;
+}
+
+ss_status ss_get_step_kernel(ss_grid g, int* kind) {
+  if (!g || !kind) return fail(SS_ERR_ARG, "ss_get_step_kernel: null argument");
+  *kind = (g->step_kind == 1 && small_ok(g)) ? 1 : 0;
+  return SS_OK;
+}
+
 ss_status ss_set_solver(ss_grid g, int solver, int stencil) {
   if (!g) return fail(SS_ERR_ARG, "ss_set_solver: null grid");
   if (solver != 0 && solver != 1) return fail(SS_ERR_ARG, "ss_set_solver: unknown solver %d", solver);
@@ -1725,9 +1897,10 @@ ss_status ss_set_solver(ss_grid g, int solver, int stencil) {
     return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the finite-difference solver takes one explicit channel per field");
   if (solver == 1) {
     const bool ok = stencil == 0 || stencil == 4 ||
-                    (g->ndim == 2 ? (stencil == 5 || stencil == 9) : (stencil == 7 || stencil == 19 || stencil == 27));
+                    (g->ndim == 2 ? (stencil == 5 || stencil == 9 || stencil == 17 || stencil == 21)
+                                  : (stencil == 7 || stencil == 15 || stencil == 19 || stencil == 21 || stencil == 27));
     if (!ok) return fail(SS_ERR_ARG, "ss_set_solver: stencil %d is not available in %dD", stencil, g->ndim);
-    if (stencil == 9 || stencil == 19 || stencil == 27)
+    if (stencil != 0 && stencil != 4 && stencil != 5 && stencil != 7)
       for (int d = 1; d < g->ndim; ++d)
         if (std::fabs(g->dx[d] - g->dx[0]) > 1e-12 * g->dx[0])
           return fail(SS_ERR_UNSUPPORTED, "ss_set_solver: the isotropic stencil needs equal spacings");
@@ -1812,6 +1985,8 @@ ss_status ss_step_n(ss_grid g, int64_t nsteps) {
     for (int64_t i = 0; i < nsteps; ++i) SS_TRY(fd_step_once(g));
     return SS_OK;
   }
+  if (nsteps > 0 && g->step_kind == 1 && small_ok(g))
+    return g->dtype == SS_F64 ? small_run<double>(g, nsteps) : small_run<float>(g, nsteps);
   if (nsteps > 0) SS_TRY(g->dtype == SS_F64 ? ensure_shat<double>(g) : ensure_shat<float>(g));
   for (int64_t i = 0; i < nsteps; ++i) {
     ss_status st = g->dtype == SS_F64 ? step_once<double>(g, nullptr) : step_once<float>(g, nullptr);
@@ -2174,14 +2349,15 @@ ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out) {
 
 ss_status ss_batch_workspace_size(ss_batch b, size_t* bytes) {
   if (!b || !bytes) return fail(SS_ERR_ARG, "ss_batch_workspace_size: null argument");
-  *bytes = 2 * batch_table_bytes(b);
+  *bytes = 2 * batch_table_bytes(b) + batch_sync_bytes(b);
   return SS_OK;
 }
 
 ss_status ss_batch_bind_workspace(ss_batch b, void* device_ptr, size_t bytes) {
   if (!b || !device_ptr) return fail(SS_ERR_ARG, "ss_batch_bind_workspace: null argument");
   if (((uintptr_t)device_ptr) % kAlign) return fail(SS_ERR_ARG, "ss_batch_bind_workspace: pointer not 256-byte aligned");
-  if (bytes < 2 * batch_table_bytes(b)) return fail(SS_ERR_ARG, "ss_batch_bind_workspace: workspace too small");
+  if (bytes < 2 * batch_table_bytes(b) + batch_sync_bytes(b))
+    return fail(SS_ERR_ARG, "ss_batch_bind_workspace: workspace too small");
   b->ws = device_ptr;
   b->ws_bytes = bytes;
   b->uploaded = false;
@@ -2216,7 +2392,35 @@ ss_status ss_batch_autotune(ss_batch b, int reps) {
     }
   }
   if (!best_t) return fail(SS_ERR_UNSUPPORTED, "ss_batch_autotune: no block size fits every member");
-  return batch_upload(b, best_t);
+  SS_TRY(batch_upload(b, best_t));
+  if (!b->mode_set) {
+    // grouped launches against the single launch over a run of steps
+    // (on the tuning table, which leaves the fields alone)
+    b->mode = 0;
+    if (batch_single_ok(b)) {
+      const int64_t nrun = 8;
+      auto grouped = [&](ss::LaunchEvents ev) {
+        for (int64_t i = 0; i < nrun; ++i) {
+          ss::LaunchEvents ex, ek;
+          if (i == 0) ex.start = ev.start;
+          if (i == nrun - 1) ek.stop = ev.stop;
+          SS_TRY(b->dtype == SS_F64 ? batch_launch_step<double>(b, true, ex, ek)
+                                    : batch_launch_step<float>(b, true, ex, ek));
+        }
+        return SS_OK;
+      };
+      auto single = [&](ss::LaunchEvents ev) {
+        return b->dtype == SS_F64 ? batch_launch_single<double>(b, nrun, true, ev)
+                                  : batch_launch_single<float>(b, nrun, true, ev);
+      };
+      float tg, tp;
+      SS_TRY(time_launch(b->grids[0], grouped, reps, &tg));
+      SS_TRY(time_launch(b->grids[0], single, reps, &tp));
+      SS_TRY(batch_check_error(b));
+      if (tp < tg) b->mode = 1;
+    }
+  }
+  return SS_OK;
 }
 
 ss_status ss_batch_step_n(ss_batch b, int64_t nsteps) {
@@ -2226,7 +2430,7 @@ ss_status ss_batch_step_n(ss_batch b, int64_t nsteps) {
   SS_TRY(batch_check_members(b));
   if (!b->uploaded) SS_TRY(batch_upload(b, b->threads));
   if (nsteps > 0) SS_TRY(batch_refresh(b));
-  for (int64_t i = 0; i < nsteps; ++i) SS_TRY(batch_step_once(b));
+  SS_TRY(batch_run(b, nsteps));
   for (ss_grid g : b->grids) g->log_count += nsteps;
   return SS_OK;
 }
@@ -2248,8 +2452,7 @@ ss_status ss_batch_capture(ss_batch b, int64_t nsteps) {
   }
   SS_TRY(batch_refresh(b));   // outside the capture
   SS_TRY(hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"));
-  ss_status st = SS_OK;
-  for (int64_t i = 0; st == SS_OK && i < nsteps; ++i) st = batch_step_once(b);
+  ss_status st = batch_run(b, nsteps);
   hipGraph_t graph = nullptr;
   ss_status st2 = hip_check(hipStreamEndCapture(b->stream, &graph), "hipStreamEndCapture");
   if (st != SS_OK) {
@@ -2271,6 +2474,35 @@ ss_status ss_batch_launch(ss_batch b) {
   SS_TRY(hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch"));
   for (ss_grid g : b->grids) g->log_count += b->graph_steps;
   return SS_OK;
+}
+
+ss_status ss_batch_set_mode(ss_batch b, int mode) {
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_set_mode: null batch");
+  if (mode != 0 && mode != 1) return fail(SS_ERR_ARG, "ss_batch_set_mode: mode %d is not 0 or 1", mode);
+  if (!b->ws) return fail(SS_ERR_STATE, "ss_batch_set_mode: bind the batch workspace first");
+  if (!b->uploaded) SS_TRY(batch_upload(b, b->threads));
+  if (mode == 1 && !batch_single_ok(b))
+    return fail(SS_ERR_UNSUPPORTED, "ss_batch_set_mode: the single launch needs one block size for both passes");
+  b->mode = mode;
+  b->mode_set = true;
+  return SS_OK;
+}
+
+ss_status ss_batch_get_mode(ss_batch b, int* mode) {
+  if (!b || !mode) return fail(SS_ERR_ARG, "ss_batch_get_mode: null argument");
+  *mode = b->mode;
+  return SS_OK;
+}
+
+ss_status ss_batch_set_wait_limit(ss_batch b, unsigned limit) {
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_set_wait_limit: null batch");
+  b->spin_limit = limit;
+  return SS_OK;
+}
+
+ss_status ss_batch_check(ss_batch b) {
+  if (!b) return fail(SS_ERR_ARG, "ss_batch_check: null batch");
+  return batch_check_error(b);
 }
 
 ss_status ss_batch_info(ss_batch b, int info[3]) {

@@ -13,6 +13,7 @@
 #include "ss_batch.hpp"
 #include "ss_fd.hpp"
 #include "ss_kernels.hpp"
+#include "ss_small.hpp"
 
 namespace ss {
 
@@ -109,6 +110,10 @@ template <typename T>
 hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev);
 template <typename T>
 hipError_t run_batch_k(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev);
+// single-launch form: the counter reset, then one launch of y.nsteps
+// steps, one workgroup per work item
+template <typename T>
+hipError_t run_batch_single(BatchArgs b, BatchSync y, int threads, uint32_t lds, hipStream_t s, LaunchEvents ev);
 
 // adjoint (Gray-Scott, 2D): sizes 8 .. 1024
 inline int xadj_tile(int esz, int nx, int64_t rows) {
@@ -146,6 +151,11 @@ template <typename T>
 hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s);
 template <typename T>
 hipError_t run_finite(FiniteArgs a, hipStream_t s);
+// one-workgroup run of a.nsteps steps of a square N x N one-field grid
+// (N = 16 .. 128): the factor table, then the steps
+inline bool small_size_ok(int n) { return n == 16 || n == 32 || n == 64 || n == 128; }
+template <typename T>
+hipError_t run_small(int n, SmallArgs a, hipStream_t s);
 template <typename T>
 hipError_t run_fd_eq(int dim, int stencil, int depth, FDArgs a, const FDEq& q, hipStream_t s);
 
@@ -306,7 +316,7 @@ constexpr int fd_rows(int dim, int st) {
 // where the grid tiles into its blocks; false: use fd_kernel.
 template <typename T, int ST>
 bool launch_fd3_march(FDArgs a, hipStream_t s, hipError_t* e) {
-  constexpr int HALO = ST == 4 ? 2 : 1;
+  constexpr int HALO = fd_halo(3, ST);
   constexpr int TY = FD3_BY * fd3_rows(ST);
   if (a.nx % FD3_BX || a.ny % TY || a.nz % FD3_ZC) return false;
   const dim3 grid((unsigned)((a.nx / FD3_BX) * (a.ny / TY) * (a.nz / FD3_ZC))), block(256);
@@ -324,7 +334,7 @@ bool launch_fd3_march(FDArgs a, hipStream_t s, hipError_t* e) {
 
 template <typename T, int ST>
 bool launch_fd2_march(FDArgs a, hipStream_t s, hipError_t* e) {
-  constexpr int HALO = ST == 4 ? 2 : 1;
+  constexpr int HALO = fd_halo(2, ST);
   if (a.nx % FD2_BX || a.ny % FD2_YC) return false;
   const dim3 grid((unsigned)((a.nx / FD2_BX) * (a.ny / FD2_YC))), block(256);
   switch (a.op) {
@@ -372,7 +382,11 @@ hipError_t run_fd(int dim, int stencil, FDArgs a, hipStream_t s) {
   if (dim == 2 && stencil == 0) return launch_fd<T, 2, 0>(a, s);
   if (dim == 2 && stencil == 9) return launch_fd<T, 2, 9>(a, s);
   if (dim == 2 && stencil == 4) return launch_fd<T, 2, 4>(a, s);
+  if (dim == 2 && stencil == 17) return launch_fd<T, 2, 17>(a, s);
+  if (dim == 2 && stencil == 21) return launch_fd<T, 2, 21>(a, s);
   if (dim == 3 && stencil == 0) return launch_fd<T, 3, 0>(a, s);
+  if (dim == 3 && stencil == 15) return launch_fd<T, 3, 15>(a, s);
+  if (dim == 3 && stencil == 21) return launch_fd<T, 3, 21>(a, s);
   if (dim == 3 && stencil == 19) return launch_fd<T, 3, 19>(a, s);
   if (dim == 3 && stencil == 27) return launch_fd<T, 3, 27>(a, s);
   if (dim == 3 && stencil == 4) return launch_fd<T, 3, 4>(a, s);
@@ -404,16 +418,17 @@ hipError_t run_fd_eq_nf(int dim, int stencil, int depth, FDArgs a, const FDEq& q
                                : (a.nx % FD3_BX == 0 && a.ny % ty3 == 0 && a.nz % FD3_ZC == 0));
 #define SS_FDEQM(D, S)                                                                                        \
   if (march && dim == D && stencil == S) {                                                                    \
-    constexpr int HALO = S == 4 ? 2 : 1;                                                                      \
+    constexpr int HALO = fd_halo(D, S);                                                                       \
     const dim3 g((unsigned)(D == 2 ? (a.nx / FD2_BX) * (a.ny / FD2_YC)                                       \
                                    : (a.nx / FD3_BX) * (a.ny / ty3) * (a.nz / FD3_ZC)));                      \
     return lw ? launch_with(fd_eq_march_kernel<T, D, S, true, NF, HALO>, g, block, 0, s, LaunchEvents(), a, q)  \
               : launch_with(fd_eq_march_kernel<T, D, S, false, NF, HALO>, g, block, 0, s, LaunchEvents(), a, q); \
   }
-  SS_FDEQM(2, 0) SS_FDEQM(2, 9) SS_FDEQM(2, 4) SS_FDEQM(3, 0) SS_FDEQM(3, 19) SS_FDEQM(3, 27) SS_FDEQM(3, 4)
+  SS_FDEQM(2, 0) SS_FDEQM(2, 9) SS_FDEQM(2, 4) SS_FDEQM(2, 17) SS_FDEQM(2, 21)
+  SS_FDEQM(3, 0) SS_FDEQM(3, 15) SS_FDEQM(3, 19) SS_FDEQM(3, 21) SS_FDEQM(3, 27) SS_FDEQM(3, 4)
 #undef SS_FDEQM
-  SS_FDEQ(2, 0, 1) SS_FDEQ(2, 9, 1) SS_FDEQ(2, 4, 1)
-  SS_FDEQ(3, 0, 1) SS_FDEQ(3, 19, 1) SS_FDEQ(3, 27, 1) SS_FDEQ(3, 4, 1)
+  SS_FDEQ(2, 0, 1) SS_FDEQ(2, 9, 1) SS_FDEQ(2, 4, 1) SS_FDEQ(2, 17, 1) SS_FDEQ(2, 21, 1)
+  SS_FDEQ(3, 0, 1) SS_FDEQ(3, 15, 1) SS_FDEQ(3, 19, 1) SS_FDEQ(3, 21, 1) SS_FDEQ(3, 27, 1) SS_FDEQ(3, 4, 1)
 #undef SS_FDEQ
   return hipErrorInvalidValue;
 }
@@ -430,6 +445,16 @@ hipError_t run_batch_x(BatchArgs b, int threads, int blocks, uint32_t lds, hipSt
 template <typename T>
 hipError_t run_batch_k(BatchArgs b, int threads, int blocks, uint32_t lds, hipStream_t s, LaunchEvents ev) {
   return launch_with(kpass_grouped<T>, dim3(blocks), dim3(threads), lds, s, ev, b);
+}
+template <typename T>
+hipError_t run_batch_single(BatchArgs b, BatchSync y, int threads, uint32_t lds, hipStream_t s, LaunchEvents ev) {
+  if (threads < 64 || threads > 512 || y.nsteps < 1) return hipErrorInvalidConfiguration;
+  const uint64_t items = (uint64_t)(b.x_total + b.k_total) * (uint64_t)y.nsteps;
+  if (items * (uint64_t)threads > 0xffffffffull) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(batch_sync_reset<T>, dim3(1), dim3(256), 0, s, b, y);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_with(batch_single<T>, dim3((unsigned)items), dim3(threads), lds, s, ev, b, y);
 }
 
 #define SS_ADJ_CASES(M) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024)
@@ -484,12 +509,37 @@ hipError_t run_finite(FiniteArgs a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int N>
+hipError_t launch_small(SmallArgs a, hipStream_t s) {
+  constexpr int W = SmallCfg<T, N>::W;
+  constexpr uint32_t lds = (uint32_t)small_lds((int)sizeof(C<T>), N);
+  static_assert(small_lds((int)sizeof(C<T>), N) <= LDS_BUDGET, "LDS");
+  hipLaunchKernelGGL((small_coef_kernel<T, N>), dim3(1), dim3(W), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_with(small_step_kernel<T, N>, dim3(1), dim3(W), lds, s, LaunchEvents(), a);
+}
+
+template <typename T>
+hipError_t run_small(int n, SmallArgs a, hipStream_t s) {
+  if (a.nsteps < 0) return hipErrorInvalidValue;
+  switch (n) {
+    case 16: return launch_small<T, 16>(a, s);
+    case 32: return launch_small<T, 32>(a, s);
+    case 64: return launch_small<T, 64>(a, s);
+    case 128: return launch_small<T, 128>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 #define SS_INSTANTIATE(T)                                                                  \
+  template hipError_t run_small<T>(int, SmallArgs, hipStream_t);                          \
   template hipError_t run_finite<T>(FiniteArgs, hipStream_t);                             \
   template hipError_t run_kadj<T>(int, KAdjArgs, hipStream_t);                          \
   template hipError_t run_xadj<T>(int, XAdjArgs, hipStream_t);                          \
   template hipError_t run_batch_x<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_batch_k<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
+  template hipError_t run_batch_single<T>(BatchArgs, BatchSync, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t, LaunchEvents); \
   template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t, LaunchEvents);  \
   template hipError_t run_kpass<T>(int, KArgs, int, hipStream_t, LaunchEvents);           \

@@ -1,17 +1,28 @@
 // Explicit forward-Euler finite-difference solver (Sec. 2.4.1) with the
 // second-order Laplacian stencils of Sec. 2.2.2, on the real-space fields.
 //
-// Stencils (periodic wrap; axes are powers of two, so wrapping is a mask):
+// Stencils (periodic wrap; axes are powers of two, so wrapping is a mask;
+// all but the axis-wise ones need equal spacing h on every axis):
 //   ST = 0  axis-wise central differences (5 points in 2D, 7 in 3D),
 //           sum over axes of (f[-1] - 2 f + f[+1]) / h_a^2;
 //   ST = 9  2D isotropic: (4 sum(edge neighbours) + sum(corners) - 20 f) / (6 h^2);
+//   ST = 15 3D isotropic: (8 sum(face neighbours) + sum(corners) - 56 f) / (12 h^2);
 //   ST = 19 3D isotropic: (2 sum(face neighbours) + sum(edge neighbours)
-//           - 24 f) / (6 h^2)   (equal spacing on every axis);
+//           - 24 f) / (6 h^2);
+//   ST = 21 (3D) isotropic: (4 sum(edge neighbours) - sum(corners) - 40 f) / (12 h^2);
 //   ST = 27 3D isotropic: (14 sum(faces) + 3 sum(edges) + sum(corners)
-//           - 128 f) / (30 h^2) (equal spacing);
+//           - 128 f) / (30 h^2);
 //   ST = 4  fourth-order axis-wise (the fourth-order family; 9 points in
 //           2D, 13 in 3D): sum over axes of
-//           (-f[-2] + 16 f[-1] - 30 f + 16 f[+1] - f[+2]) / (12 h_a^2).
+//           (-f[-2] + 16 f[-1] - 30 f + 16 f[+1] - f[+2]) / (12 h_a^2);
+//   ST = 17 2D fourth-order isotropic: (128 A1 + 16 D1 - 8 A2 - D2 - 540 f) / (120 h^2);
+//   ST = 21 (2D) fourth-order isotropic: (52 A1 + 16 D1 - A2 - 2 K - 252 f) / (60 h^2)
+// (A1, A2: axis neighbours at distance 1 and 2; D1, D2: diagonal ones at
+// (+-1, +-1) and (+-2, +-2); K: the 8 at (+-1, +-2) and (+-2, +-1)).  The
+// weights of each family follow from its moment conditions on its points:
+// zero sum, second moment 2 per axis, and an error term of |k| only
+// (second order: h^2 |k|^4 / 12; fourth order: vanishing fourth moments
+// and h^4 |k|^6 / 90).
 // The leading error of the isotropic stencils depends on |k| only.
 //
 // One launch applies one operation at every cell: where the grid tiles,
@@ -60,6 +71,9 @@ struct FDArgs {
   double ih2[3];             // 1 / h_a^2 (x, y, z) for the axis-wise stencil
   double i6h2;               // 1 / (6 h^2) for the 9- and 19-point stencils
   double i30h2;              // 1 / (30 h^2) for the 27-point stencil
+  double i12h2;              // 1 / (12 h^2) for the 15- and 21-point 3D stencils
+  double i60h2;              // 1 / (60 h^2) for the 21-point 2D stencil
+  double i120h2;             // 1 / (120 h^2) for the 17-point 2D stencil
   double dt;
   double p[6];               // operation coefficients
   int op;
@@ -80,24 +94,50 @@ __device__ __forceinline__ T fd_stencil(AT&& at, const FDArgs& a) {
     if constexpr (DIM == 3)
       s += (-(at(0, 0, -2) + at(0, 0, 2)) + (T)16 * (at(0, 0, -1) + at(0, 0, 1)) - (T)30 * c) * (T)a.ih2[2];
     return s * ((T)1 / (T)12);
-  } else if constexpr (ST == 9) {
+  } else if constexpr (DIM == 2 && ST == 9) {
     const T edge = at(-1, 0, 0) + at(1, 0, 0) + at(0, -1, 0) + at(0, 1, 0);
     const T corner = at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0);
     return ((T)4 * edge + corner - (T)20 * c) * (T)a.i6h2;
+  } else if constexpr (DIM == 2) {   // 17 or 21: fourth-order isotropic
+    const T a1 = at(-1, 0, 0) + at(1, 0, 0) + at(0, -1, 0) + at(0, 1, 0);
+    const T d1 = at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0);
+    const T a2 = at(-2, 0, 0) + at(2, 0, 0) + at(0, -2, 0) + at(0, 2, 0);
+    if constexpr (ST == 17) {
+      const T d2 = at(-2, -2, 0) + at(2, -2, 0) + at(-2, 2, 0) + at(2, 2, 0);
+      return ((T)128 * a1 + (T)16 * d1 - (T)8 * a2 - d2 - (T)540 * c) * (T)a.i120h2;
+    } else {
+      const T kn = at(-1, -2, 0) + at(1, -2, 0) + at(-2, -1, 0) + at(2, -1, 0) +
+                   at(-2, 1, 0) + at(2, 1, 0) + at(-1, 2, 0) + at(1, 2, 0);
+      return ((T)52 * a1 + (T)16 * d1 - a2 - (T)2 * kn - (T)252 * c) * (T)a.i60h2;
+    }
   } else {
-    const T face = at(-1, 0, 0) + at(1, 0, 0) + at(0, -1, 0) + at(0, 1, 0) + at(0, 0, -1) + at(0, 0, 1);
-    const T edge = at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0) +
-                   at(-1, 0, -1) + at(1, 0, -1) + at(-1, 0, 1) + at(1, 0, 1) +
-                   at(0, -1, -1) + at(0, 1, -1) + at(0, -1, 1) + at(0, 1, 1);
-    if constexpr (ST == 19) {
-      return ((T)2 * face + edge - (T)24 * c) * (T)a.i6h2;
+    auto faces = [&]() {
+      return at(-1, 0, 0) + at(1, 0, 0) + at(0, -1, 0) + at(0, 1, 0) + at(0, 0, -1) + at(0, 0, 1);
+    };
+    auto edges = [&]() {
+      return at(-1, -1, 0) + at(1, -1, 0) + at(-1, 1, 0) + at(1, 1, 0) +
+             at(-1, 0, -1) + at(1, 0, -1) + at(-1, 0, 1) + at(1, 0, 1) +
+             at(0, -1, -1) + at(0, 1, -1) + at(0, -1, 1) + at(0, 1, 1);
+    };
+    auto corners = [&]() {
+      return at(-1, -1, -1) + at(1, -1, -1) + at(-1, 1, -1) + at(1, 1, -1) +
+             at(-1, -1, 1) + at(1, -1, 1) + at(-1, 1, 1) + at(1, 1, 1);
+    };
+    if constexpr (ST == 15) {
+      return ((T)8 * faces() + corners() - (T)56 * c) * (T)a.i12h2;
+    } else if constexpr (ST == 19) {
+      return ((T)2 * faces() + edges() - (T)24 * c) * (T)a.i6h2;
+    } else if constexpr (ST == 21) {
+      return ((T)4 * edges() - corners() - (T)40 * c) * (T)a.i12h2;
     } else {   // 27
-      const T corner = at(-1, -1, -1) + at(1, -1, -1) + at(-1, 1, -1) + at(1, 1, -1) +
-                       at(-1, -1, 1) + at(1, -1, 1) + at(-1, 1, 1) + at(1, 1, 1);
-      return ((T)14 * face + (T)3 * edge + corner - (T)128 * c) * (T)a.i30h2;
+      return ((T)14 * faces() + (T)3 * edges() + corners() - (T)128 * c) * (T)a.i30h2;
     }
   }
 }
+
+// Cells of rim the stencil needs around a cell: two for the fourth-order
+// family (and its knight and (2, 2) points), one otherwise.
+constexpr int fd_halo(int dim, int st) { return (st == 4 || (dim == 2 && (st == 17 || st == 21))) ? 2 : 1; }
 
 // The stencil applied to array f around cell (x, y, z) (periodic wrap;
 // x, y, z may lie one or two cells outside the grid).
@@ -358,7 +398,7 @@ __global__ void __launch_bounds__(256) fd_kernel(FDArgs a) {
 // keeping the 2 HALO + 1 planes z - HALO .. z + HALO of the Laplacian's
 // input (of both fields for Gray-Scott and Model C; with a HALO-cell rim)
 // in LDS, so that a cell's neighbours are read from LDS and the input is read
-// from memory about once (HALO = 1: 7, 19 and 27 points; 2: fourth order).
+// from memory about once (HALO = 1: 7, 15, 19, 21 and 27 points; 2: fourth order).
 // Needs nx % 64, ny % 4 and nz % ZC to be 0 (the host falls back to
 // fd_kernel otherwise).
 constexpr int FD3_BX = 64, FD3_BY = 4, FD3_ZC = 8;   // 8 planes a block: measured faster than 16 or 32 (more blocks in flight)

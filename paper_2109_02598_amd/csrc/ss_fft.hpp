@@ -77,7 +77,7 @@ constexpr int ipow(int b, int e) { return e <= 0 ? 1 : b * ipow(b, e - 1); }
 
 template <int N, int P = 8>
 struct Plan {
-  static_assert(P == 8 || P == 16, "8 or 16 points per thread");
+  static_assert(P == 2 || P == 4 || P == 8 || P == 16, "2, 4, 8 or 16 points per thread");
   static constexpr int LOG = ilog2c(N);
   static constexpr int LP = ilog2c(P);
   static constexpr int FIRST = (LOG % LP == 0) ? P : (1 << (LOG % LP));

@@ -88,8 +88,14 @@ def lib():
         "ss_batch_launch": [vp],
         "ss_batch_info": [vp, ctypes.POINTER(cint)],
         "ss_batch_destroy": [vp],
-        "ss_check_finite": [vp, ctypes.POINTER(cint)],
+        "ss_batch_set_mode": [vp, cint],
+        "ss_batch_get_mode": [vp, ctypes.POINTER(cint)],
+        "ss_batch_check": [vp],
+        "ss_batch_set_wait_limit": [vp, ctypes.c_uint],
         "ss_step_fields_noalloc": [vp, ctypes.POINTER(vp), i64],
+        "ss_check_finite": [vp, ctypes.POINTER(cint)],
+        "ss_set_step_kernel": [vp, cint],
+        "ss_get_step_kernel": [vp, ctypes.POINTER(cint)],
         "ss_noalloc_scratch_bytes": [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
     }
     for name, args in sig.items():
@@ -164,10 +170,14 @@ def ss_step_fields_noalloc(h, field_ptrs, nsteps):
     _check(lib().ss_step_fields_noalloc(h, (ctypes.c_void_p * len(ptrs))(*ptrs), int(nsteps)))
 
 
-def ss_noalloc_scratch_bytes(h):
-    need, limit = ctypes.c_size_t(), ctypes.c_size_t()
-    _check(lib().ss_noalloc_scratch_bytes(h, ctypes.byref(need), ctypes.byref(limit)))
-    return need.value, limit.value
+def ss_set_step_kernel(h, kind):
+    _check(lib().ss_set_step_kernel(h, int(kind)))
+
+
+def ss_get_step_kernel(h):
+    k = ctypes.c_int()
+    _check(lib().ss_get_step_kernel(h, ctypes.byref(k)))
+    return k.value
 
 
 def ss_check_finite(h):
@@ -177,6 +187,12 @@ def ss_check_finite(h):
     if st not in (SS_OK, SS_ERR_NONFINITE):
         _check(st)
     return m.value
+
+
+def ss_noalloc_scratch_bytes(h):
+    need, limit = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().ss_noalloc_scratch_bytes(h, ctypes.byref(need), ctypes.byref(limit)))
+    return need.value, limit.value
 
 
 SS_NPASS = 4
@@ -356,6 +372,24 @@ def ss_batch_info(b):
     i = (ctypes.c_int * 3)()
     _check(lib().ss_batch_info(b, i))
     return list(i)
+
+
+def ss_batch_set_mode(b, mode):
+    _check(lib().ss_batch_set_mode(b, int(mode)))
+
+
+def ss_batch_get_mode(b):
+    m = ctypes.c_int()
+    _check(lib().ss_batch_get_mode(b, ctypes.byref(m)))
+    return m.value
+
+
+def ss_batch_check(b):
+    _check(lib().ss_batch_check(b))
+
+
+def ss_batch_set_wait_limit(b, limit):
+    _check(lib().ss_batch_set_wait_limit(b, int(limit)))
 
 
 def ss_batch_destroy(b):
@@ -571,6 +605,18 @@ class Batch:
 
     def info(self):
         return ss_batch_info(self.b)
+
+    def set_mode(self, mode):
+        """0: grouped launches per step; 1: one launch per run (a workgroup
+        per work item, ordered by a ticket counter)."""
+        ss_batch_set_mode(self.b, mode)
+
+    def mode(self):
+        return ss_batch_get_mode(self.b)
+
+    def check(self):
+        """Synchronise; raises if a single launch gave up a wait."""
+        ss_batch_check(self.b)
 
     def close(self):
         if getattr(self, "b", None):

@@ -42,6 +42,9 @@ def grids_for(specstep, ws, dtype, stream):
 
 
 SIZES = [(64, 64), (128, 64), (64, 256), (256, 256), (512, 128), (128, 128), (1024, 64), (64, 512)]
+# the single-launch form runs both passes with one block size (256 threads):
+# rows of at least 128 points (the workload's sizes)
+PSIZES = [(128, 64), (256, 256), (512, 128), (128, 128), (1024, 64), (128, 512), (256, 1024)]
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -90,6 +93,103 @@ def test_batch_graph_replay_equals_eager(dtype):
     bg.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_single_launch_matches_plain_grouped_and_oracle(dtype):
+    """One launch per run (a workgroup per work item, items drawn from a
+    ticket counter, per-member counters ordering the passes) gives the bits
+    of the plain path and of the grouped launches."""
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = make_members(PSIZES, dtype, seed0=4200)
+    steps = 20
+    plain = grids_for(specstep, ws, dtype, stream.cuda_stream)
+    for g in plain:
+        g.step(steps)
+    want = [g.get_field(0).cpu().numpy() for g in plain]
+    gp = grids_for(specstep, ws, dtype, stream.cuda_stream)
+    bp = specstep.Batch(gp, autotune=False)
+    bp.set_mode(1)
+    assert bp.mode() == 1
+    bp.step(7)
+    bp.step(steps - 7)          # two launches: the counters restart per launch
+    bp.check()
+    gg = grids_for(specstep, ws, dtype, stream.cuda_stream)
+    bg = specstep.Batch(gg, autotune=False)
+    bg.set_mode(0)
+    bg.step(steps)
+    torch.cuda.synchronize()
+    for i, w in enumerate(ws):
+        got = gp[i].get_field(0).cpu().numpy()
+        assert same_as_plain(got, want[i]), (i, w.n, "single launch vs plain")
+        assert same_as_plain(gg[i].get_field(0).cpu().numpy(), want[i]), (i, w.n, "grouped vs plain")
+        ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, steps)[0]
+        assert_parity(got, ref, dtype, ("single-launch member", i, w.n))
+    bp.close()
+    bg.close()
+
+
+def test_single_launch_graph_replay_equals_eager():
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = make_members(PSIZES[:6], "f32", seed0=4300)
+    eager = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    be = specstep.Batch(eager, autotune=False)
+    be.set_mode(1)
+    graph = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    bg = specstep.Batch(graph, autotune=False)
+    bg.set_mode(1)
+    bg.capture(5)
+    for rep in range(3):
+        bg.launch()
+        be.step(5)
+        bg.check()
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        for a, c in zip(graph, eager):
+            assert np.array_equal(a.get_field(0).cpu().numpy(), c.get_field(0).cpu().numpy()), rep
+    be.close()
+    bg.close()
+
+
+def test_single_launch_refused_without_one_block_size():
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = make_members([(64, 64), (256, 128)], "f32", seed0=4500)
+    gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    b = specstep.Batch(gs, autotune=False)
+    with pytest.raises(specstep.SpecStepError) as e:
+        b.set_mode(1)
+    assert e.value.code == specstep.SS_ERR_UNSUPPORTED
+    assert b.mode() == 0
+    b.close()
+
+
+def test_single_launch_wait_limit_is_reported_and_recovered():
+    """A wait bound of zero gives up at the first unmet wait: every
+    workgroup leaves, the launch ends, ss_batch_check reports it; with the
+    bound restored the batch steps correctly again."""
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = make_members(PSIZES[:4], "f32", seed0=4400)
+    gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    b = specstep.Batch(gs, autotune=False)
+    b.set_mode(1)
+    specstep.ss_batch_set_wait_limit(b.b, 0)
+    b.step(10)
+    with pytest.raises(specstep.SpecStepError) as e:
+        b.check()
+    assert e.value.code == specstep.SS_ERR_DEVICE
+    say("reported:", specstep.ss_last_error())
+    specstep.ss_batch_set_wait_limit(b.b, 1 << 22)
+    for g, w in zip(gs, ws):
+        g.set_field(0, w.fields[0].astype(np.float32))
+    b.step(10)
+    b.check()
+    for g, w in zip(gs, ws):
+        ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, 10)[0]
+        assert_parity(g.get_field(0).cpu().numpy(), ref, "f32", ("recovered", w.n))
+    b.close()
+
+
 @pytest.mark.timeout(1200)
 def test_batch_64_uneven_members():
     """The 64-member workload (sizes from {128, 256, 512, 1024}^2, M and kappa
@@ -104,12 +204,24 @@ def test_batch_64_uneven_members():
     steps = 50
     gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
     b = specstep.Batch(gs, autotune=True, reps=2)
-    say("64-member batch info:", b.info(), "cells", sum(w.cells for w in ws))
+    b_mode = b.mode()
+    say("64-member batch info:", b.info(), "mode", b_mode, "cells", sum(w.cells for w in ws))
     b.capture(steps)
     b.launch()
-    torch.cuda.synchronize()
+    b.check()
     got = [g.get_field(0).cpu().numpy() for g in gs]
     b.close()
+    # the other form of the batched step on the same members: the same bits
+    go = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    bo = specstep.Batch(go, autotune=False)
+    other = 1 - b_mode
+    bo.set_mode(other)
+    bo.capture(steps)
+    bo.launch()
+    bo.check()
+    for i in range(len(ws)):
+        assert same_as_plain(go[i].get_field(0).cpu().numpy(), got[i]), (i, "mode", other)
+    bo.close()
     for i, w in enumerate(ws):
         p = specstep.Grid(w.n, w.dx, dtype="f32", model=w.model, coef=w.coef, dt=w.dt,
                           stream=stream.cuda_stream)

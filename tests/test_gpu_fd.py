@@ -1,7 +1,8 @@
 """Forward-Euler finite-difference solver on the GPU (Sec. 2.4.1, stencils of
 Sec. 2.2.2) against the oracle's forward-Euler solver with the same stencil,
-element by element, for every model in 2D and 3D, with the axis-wise and the
-isotropic second-order Laplacians."""
+element by element, for every model in 2D and 3D, with every Laplacian
+stencil: second order (5, 9; 7, 15, 19, 21, 27 points) and fourth order
+(axis-wise; 17 and 21 points in 2D)."""
 import numpy as np
 import pytest
 
@@ -33,12 +34,15 @@ def gpu_euler(model, n, dx, dt, steps, fields, dtype, stencil):
 @pytest.mark.parametrize("n,stencil", [((64, 32), 0), ((32, 64), 9), ((16, 8, 32), 0), ((16, 16, 16), 19),
                                        ((16, 16, 16), 27), ((32, 64), 4), ((16, 8, 32), 4),
                                        ((64, 8, 32), 19), ((128, 8, 16), 27), ((64, 16, 16), 0), ((64, 8, 32), 4),
-                                       ((256, 16), 9), ((512, 8), 4), ((256, 32), 0)])
+                                       ((256, 16), 9), ((512, 8), 4), ((256, 32), 0),
+                                       ((32, 64), 17), ((32, 64), 21), ((16, 16, 16), 15), ((16, 16, 16), 21),
+                                       ((256, 16), 17), ((512, 8), 21), ((64, 8, 32), 15), ((128, 8, 16), 21)])
 def test_euler_vs_oracle(model, n, stencil, dtype):
     dx = (1.0,) * len(n)
     steps = 20
-    # the fourth-order stencil's largest eigenvalue is 4/3 of the second-order one's
-    dt = DT[model] * (0.5 if stencil == 4 else 1.0)
+    # the largest eigenvalue of the fourth-order axis-wise and 17-point
+    # stencils is above that of the second-order axis-wise one
+    dt = DT[model] * (0.5 if stencil in (4, 17) else 1.0)
     fields = synth_fields(model, n, dx, 500 + len(n))
     got = gpu_euler(model, n, dx, dt, steps, [f.astype(np.float32) if dtype == "f32" else f for f in fields],
                     dtype, stencil)
@@ -47,7 +51,8 @@ def test_euler_vs_oracle(model, n, stencil, dtype):
 
 
 @pytest.mark.parametrize("stencil,n", [(0, (128, 64)), (9, (64, 64)), (19, (32, 32, 32)), (27, (32, 32, 32)),
-                                       (4, (64, 128))])
+                                       (4, (64, 128)), (17, (256, 64)), (21, (64, 64)), (15, (32, 32, 32)),
+                                       (21, (64, 16, 32))])
 def test_euler_cahn_hilliard_conserves_mass(stencil, n):
     """The update is dt M L(mu), and every stencil's weights sum to zero on a
     periodic grid: the field's sum is conserved to rounding."""
@@ -67,13 +72,26 @@ def test_solver_choice_errors():
     with pytest.raises(specstep.SpecStepError):
         specstep.ss_set_solver(g.h, 1, 27)       # 27 points is 3D
     with pytest.raises(specstep.SpecStepError):
+        specstep.ss_set_solver(g.h, 1, 15)       # 15 points is 3D
+    specstep.ss_set_solver(g.h, 1, 21)           # 21 points: fourth order in 2D
+    specstep.ss_set_solver(g.h, 1, 17)
+    specstep.ss_set_solver(g.h, 0, 0)
+    with pytest.raises(specstep.SpecStepError):
         specstep.ss_set_solver(g.h, 2, 0)        # unknown solver
     with pytest.raises(specstep.SpecStepError):
         specstep.ss_set_solver(g.h, 0, 9)        # the spectral solver takes no stencil
     g.close()
-    with pytest.raises(specstep.SpecStepError):
-        specstep.Grid((32, 32), (1.0, 2.0), model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1,
-                      solver="euler", stencil=9)   # isotropic stencil, unequal spacing
+    for st in (9, 17, 21):                          # isotropic stencils, unequal spacing
+        with pytest.raises(specstep.SpecStepError):
+            specstep.Grid((32, 32), (1.0, 2.0), model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1,
+                          solver="euler", stencil=st)
+    g = specstep.Grid((16, 16, 16), (1.0, 1.0, 1.0), model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1)
+    for st in (17, 9, 5):                           # 2D stencils
+        with pytest.raises(specstep.SpecStepError):
+            specstep.ss_set_solver(g.h, 1, st)
+    for st in (15, 21, 7):
+        specstep.ss_set_solver(g.h, 1, st)
+    g.close()
     g = specstep.Grid((32, 32), (1.0, 1.0), model="allen_cahn", coef=COEF["allen_cahn"], dt=0.1, solver="euler")
     g.set_field(0, np.zeros((32, 32)))
     for call in (lambda: g.autotune(1), lambda: g.structure_factor(0), lambda: g.time_pass("xpass", 2)):

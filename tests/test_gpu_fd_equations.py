@@ -22,7 +22,10 @@ CASES = [((64, 32), 0), ((32, 64), 9), ((32, 64), 4), ((16, 8, 32), 0), ((16, 16
          ((256, 16), 9), ((512, 8), 4), ((64, 8, 16), 27), ((64, 8, 16), 0),
          # the 2D axis-wise and the 3D fourth-order marching tiles (two rows a
          # thread, a two-cell rim), in both precisions
-         ((256, 32), 0), ((64, 8, 32), 4)]
+         ((256, 32), 0), ((64, 8, 32), 4),
+         # the 2D fourth-order and 3D 15- and 21-point isotropic stencils, on
+         # the marching tiles and on the grids they do not tile
+         ((256, 16), 17), ((32, 64), 21), ((16, 16, 16), 15), ((64, 8, 16), 21)]
 
 
 def gpu_euler_eq(text, coefs, n, dx, dt, steps, fields, dtype, stencil):
@@ -39,8 +42,9 @@ def gpu_euler_eq(text, coefs, n, dx, dt, steps, fields, dtype, stencil):
 
 def stable_dt(split, ndim, stencil, h=1.0, frac=0.4):
     """frac / max |L| over the stencils' eigenvalue range (an upper bound of
-    the Laplacian's magnitude: 4 per axis / h^2, 16/3 for the fourth-order)."""
-    lam = 4.0 * ndim / (h * h) * (4.0 / 3.0 if stencil == 4 else 1.0)
+    the Laplacian's magnitude: 4 per axis / h^2, 16/3 for the fourth-order
+    axis-wise and 17-point stencils)."""
+    lam = 4.0 * ndim / (h * h) * (4.0 / 3.0 if stencil in (4, 17) else 1.0)
     x = -np.linspace(0.0, lam, 2001)
     big = 1e-3
     for Lj in split.L:
@@ -61,7 +65,7 @@ def check(got, want, dtype, what):
 def test_fixed_models_written_as_equations(model, n, stencil, dtype):
     torch, specstep = need_gpu()
     dx = (1.0,) * len(n)
-    dt = DT_FIXED[model] * (0.5 if stencil == 4 else 1.0)
+    dt = DT_FIXED[model] * (0.5 if stencil in (4, 17) else 1.0)
     text, coefs = eqs.fixed(model, COEF_FD[model])
     f0 = as_input(synth_fields(model, n, dx, 600 + len(n)), dtype)
     got = gpu_euler_eq(text, coefs, n, dx, dt, 20, f0, dtype, stencil)
@@ -108,7 +112,8 @@ def test_new_equations(name, n, stencil, dtype):
 
 
 @pytest.mark.parametrize("stencil,n", [(0, (128, 64)), (9, (64, 64)), (19, (32, 32, 32)), (27, (32, 32, 32)),
-                                       (4, (64, 128))])
+                                       (4, (64, 128)), (17, (256, 64)), (21, (64, 64)), (15, (32, 32, 32)),
+                                       (21, (64, 16, 32))])
 def test_conserved_equation_keeps_its_sum(stencil, n):
     """Every term of a conserved equation sits under a Laplacian whose
     stencil weights sum to zero: the field's sum stays put to rounding."""
@@ -128,7 +133,8 @@ def test_edge_shapes_and_a_single_step():
     text, coefs = eqs.fixed("cahn_hilliard", COEF_FD["cahn_hilliard"])
     sp = osp.parse(text, coefs)
     for n, stencil, steps in [((4096, 8), 0, 3), ((8, 1024), 9, 3), ((16, 8, 8), 27, 3), ((8, 8), 4, 1),
-                              ((8, 8, 8), 0, 2)]:
+                              ((8, 8, 8), 0, 2), ((8, 16), 17, 2), ((16, 8), 21, 2), ((8, 8, 8), 15, 2),
+                              ((8, 16, 8), 21, 2)]:
         dx = (1.0,) * len(n)
         dt = stable_dt(sp, len(n), stencil)
         f0 = smooth_fields(1, n[::-1], 3, offsets=(0.1, 0.0))
