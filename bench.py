@@ -132,9 +132,10 @@ def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
 
 
 def run_batch(steps=500, reps=3):
-    """64 uneven Cahn-Hilliard grids (FP32): one captured graph of `steps`
-    batched steps in each form (grouped launches, one launch), the tuned
-    form eager, and the same members stepped one grid at a time."""
+    """64 uneven Cahn-Hilliard grids (FP32): one captured run of `steps`
+    batched steps in each form (grouped launches in a graph, one launch, one
+    cooperative launch), the tuned form eager, and the same members stepped
+    one grid at a time."""
     import torch
     from paper_2109_02598_amd import inputs, specstep
     ws = inputs.cahn_hilliard_batch(count=64, steps=steps)
@@ -162,13 +163,14 @@ def run_batch(steps=500, reps=3):
         b.check()
         return e0.elapsed_time(e1)
 
-    # both forms, each one captured graph of `steps` steps (the single launch
-    # needs one block size for both passes)
-    ms_modes = {0: graph_ms(0), 1: None}
-    try:
-        ms_modes[1] = graph_ms(1)
-    except specstep.SpecStepError:
-        pass
+    # every form, each one captured run of `steps` steps (the single and the
+    # cooperative launch need one block size for both passes)
+    ms_modes = {0: graph_ms(0), 1: None, 2: None}
+    for m in (1, 2):
+        try:
+            ms_modes[m] = graph_ms(m)
+        except specstep.SpecStepError:
+            pass
     b.set_mode(tuned_mode)
     ms_graph = ms_modes[tuned_mode]
     e0.record(stream)
@@ -200,9 +202,10 @@ def run_batch(steps=500, reps=3):
                          "unit": "GB/s", "frac": round(agg / HBM_PEAK_GBS, 4)},
             "cells": cells, "value": round(cells * steps / (ms_graph * 1e-3), 1),
             "unit": "cell-updates/s", "ms_graph_launch": round(ms_graph, 3),
-            "mode": {0: "grouped launches", 1: "single launch"}[tuned_mode],
+            "mode": {0: "grouped launches", 1: "single launch", 2: "cooperative launch"}[tuned_mode],
             "ms_graph_grouped": round(ms_modes[0], 3),
             "ms_graph_single_launch": None if ms_modes[1] is None else round(ms_modes[1], 3),
+            "ms_cooperative_launch": None if ms_modes[2] is None else round(ms_modes[2], 3),
             "ms_eager": round(ms_eager, 3), "ms_sequential_plain": round(ms_plain, 3),
             "speedup_vs_sequential_plain": round(ms_plain / ms_graph, 2),
             "threads_per_block": info[0], "x_tiles": info[1], "k_tiles": info[2]}

@@ -413,15 +413,16 @@ typedef struct ss_batch_s* ss_batch;
 ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out);
 
 /* Device bytes the batch needs for its member tables and the counters of
- * its single launch (caller-owned, 256-byte aligned, bound with
- * ss_batch_bind_workspace). */
+ * its single launches (caller-owned, 256-byte aligned, bound with
+ * ss_batch_bind_workspace, which clears the counters and the error flag
+ * on the batch's stream). */
 ss_status ss_batch_workspace_size(ss_batch b, size_t* bytes);
 ss_status ss_batch_bind_workspace(ss_batch b, void* device_ptr, size_t bytes);
 
 /* Time each valid block size (128, 256, 512 threads) for the grouped
  * launches `reps` times and keep the fastest; then, unless ss_batch_set_mode
- * fixed the form, time 8 steps as grouped launches against 8 steps in one
- * launch and keep the faster form.  Fields are untouched (the timed
+ * fixed the form, time 8 steps in each of the three forms below and keep
+ * the fastest.  Fields are untouched (the timed
  * launches run on the members' scratch arrays).  Synchronises the stream. */
 ss_status ss_batch_autotune(ss_batch b, int reps);
 
@@ -434,12 +435,19 @@ ss_status ss_batch_autotune(ss_batch b, int reps);
  * each member (its k-space tiles wait for its x tiles of the step, its next
  * x tiles for its k-space tiles), so the members advance independently
  * and the step boundary drains no launch; a small kernel resets the
- * counters before each launch.  Both forms run the same tile code and give
- * the same bits.  Mode 1 needs one block size for both passes
- * (SS_ERR_UNSUPPORTED otherwise).  Waits inside the launch are bounded: one
- * that runs out makes every later workgroup leave and is reported by
- * ss_batch_check.  ss_batch_get_mode returns the current form (set here or
- * by the tuner). */
+ * counters before each launch.  mode 2: one cooperative launch for all
+ * the steps of a call (as many workgroups as are resident at once, at most
+ * one per tile of the larger pass): in each step workgroup g takes the
+ * tiles g, g + G, ... of the x pass, waits at a device-wide barrier for
+ * every workgroup, takes its k-space tiles the same way and waits again,
+ * so that two barriers replace the two launches of a step (for a few small
+ * grids, whose grouped steps are mostly launch gaps).  ss_batch_capture in
+ * mode 2 records no graph: ss_batch_launch issues the cooperative launch
+ * itself.  All forms run the same tile code and give the same bits.  Modes
+ * 1 and 2 need one block size for both passes (SS_ERR_UNSUPPORTED
+ * otherwise).  Waits inside the launches are bounded: one that runs out
+ * makes every workgroup leave and is reported by ss_batch_check.
+ * ss_batch_get_mode returns the current form (set here or by the tuner). */
 ss_status ss_batch_set_mode(ss_batch b, int mode);
 ss_status ss_batch_get_mode(ss_batch b, int* mode);
 

@@ -1163,8 +1163,11 @@ struct ss_batch_s {
   hipGraphExec_t exec = nullptr;
   int64_t graph_steps = 0;
   // 0: grouped launches (two per step); 1: one launch per run (a workgroup
-  // per work item, ordered by a ticket counter)
+  // per work item, ordered by a ticket counter); 2: one cooperative launch
+  // per run (resident workgroups, two device-wide barriers a step)
   int mode = 0;
+  int coop_blocks = 0;      // workgroups of the cooperative launch (0: not sized yet)
+  bool coop_direct = false; // the captured run is the cooperative launch itself (no graph)
   bool mode_set = false;    // chosen by ss_batch_set_mode: the tuner leaves it alone
   unsigned spin_limit = 1u << 22;   // sleeps a wait of the single launch takes before it gives up
 };
@@ -1302,6 +1305,7 @@ ss_status batch_upload(ss_batch b, int threads) {
   SS_TRY(hip_check(hipStreamSynchronize(b->stream), "batch table upload"));
   b->threads = threads;
   b->uploaded = true;
+  b->coop_blocks = 0;
   b->state_at_build.clear();
   for (ss_grid g : b->grids) b->state_at_build.push_back(g->state[0]);
   return SS_OK;
@@ -1363,6 +1367,42 @@ ss_status batch_launch_single(ss_batch b, int64_t nsteps, bool tune_table, ss::L
                    "batch single launch");
 }
 
+// Workgroups of the cooperative launch: as many as are resident at once,
+// at most one per tile of the larger pass.
+template <typename T>
+ss_status batch_coop_size(ss_batch b) {
+  int fit = 0;
+  SS_TRY(hip_check(ss::run_batch_coop<T>(ss::BatchArgs(), ss::BatchSync(), b->threads, std::max(b->lds_x, b->lds_k), 0,
+                                         &fit, b->stream, {}),
+                   "batch: cooperative occupancy"));
+  b->coop_blocks = std::min(fit, std::max(b->x_total, b->k_total));
+  if (b->coop_blocks < 1) return fail(SS_ERR_UNSUPPORTED, "batch: no workgroup of the cooperative launch fits a CU");
+  return SS_OK;
+}
+
+// Steps one cooperative launch can hold: its barrier counter (two arrivals
+// per workgroup and step) counts in 32 bits.
+int64_t batch_coop_max_steps(ss_batch b) {
+  return std::max<int64_t>(1, (int64_t)0xffffffffLL / (2 * (int64_t)std::max(b->coop_blocks, 1)) - 1);
+}
+
+template <typename T>
+ss_status batch_launch_coop(ss_batch b, int64_t nsteps, bool tune_table, ss::LaunchEvents ev) {
+  if (!batch_single_ok(b))
+    return fail(SS_ERR_UNSUPPORTED, "batch: the cooperative launch needs one block size for both passes");
+  if (!b->coop_blocks) SS_TRY(batch_coop_size<T>(b));
+  if (nsteps < 1 || nsteps > batch_coop_max_steps(b))
+    return fail(SS_ERR_ARG, "batch: %lld steps do not fit one launch", (long long)nsteps);
+  ss::BatchArgs a;
+  a.m = (const ss::BatchMember*)((char*)b->ws + (tune_table ? batch_table_bytes(b) : 0));
+  a.count = (int)b->grids.size();
+  a.x_total = b->x_total;
+  a.k_total = b->k_total;
+  return hip_check(ss::run_batch_coop<T>(a, batch_sync(b, nsteps), b->threads, std::max(b->lds_x, b->lds_k),
+                                         b->coop_blocks, nullptr, b->stream, ev),
+                   "batch cooperative launch");
+}
+
 // Synchronise the batch's stream and report a single launch whose bounded
 // wait ran out.
 ss_status batch_check_error(ss_batch b) {
@@ -1377,6 +1417,17 @@ ss_status batch_check_error(ss_batch b) {
 
 ss_status batch_run(ss_batch b, int64_t nsteps) {
   if (nsteps < 1) return SS_OK;
+  if (b->mode == 2) {
+    for (int64_t done = 0; done < nsteps;) {
+      if (!b->coop_blocks)
+        SS_TRY(b->dtype == SS_F64 ? batch_coop_size<double>(b) : batch_coop_size<float>(b));
+      const int64_t n = std::min(nsteps - done, batch_coop_max_steps(b));
+      SS_TRY(b->dtype == SS_F64 ? batch_launch_coop<double>(b, n, false, {})
+                                : batch_launch_coop<float>(b, n, false, {}));
+      done += n;
+    }
+    return SS_OK;
+  }
   if (b->mode == 1) {
     // one launch, or several in a row when the steps exceed one launch's size
     for (int64_t done = 0; done < nsteps;) {
@@ -2361,7 +2412,10 @@ ss_status ss_batch_bind_workspace(ss_batch b, void* device_ptr, size_t bytes) {
   b->ws = device_ptr;
   b->ws_bytes = bytes;
   b->uploaded = false;
-  return SS_OK;
+  // the counters and the error flag start at zero: ss_batch_check reads the
+  // flag whatever form ran (the single launches reset it as they start)
+  return hip_check(hipMemsetAsync((char*)device_ptr + 2 * batch_table_bytes(b), 0, batch_sync_bytes(b), b->stream),
+                   "ss_batch_bind_workspace: clear the counters");
 }
 
 ss_status ss_batch_autotune(ss_batch b, int reps) {
@@ -2413,11 +2467,18 @@ ss_status ss_batch_autotune(ss_batch b, int reps) {
         return b->dtype == SS_F64 ? batch_launch_single<double>(b, nrun, true, ev)
                                   : batch_launch_single<float>(b, nrun, true, ev);
       };
-      float tg, tp;
+      auto coop = [&](ss::LaunchEvents ev) {
+        return b->dtype == SS_F64 ? batch_launch_coop<double>(b, nrun, true, ev)
+                                  : batch_launch_coop<float>(b, nrun, true, ev);
+      };
+      float tg, tp, tc;
       SS_TRY(time_launch(b->grids[0], grouped, reps, &tg));
       SS_TRY(time_launch(b->grids[0], single, reps, &tp));
       SS_TRY(batch_check_error(b));
-      if (tp < tg) b->mode = 1;
+      SS_TRY(time_launch(b->grids[0], coop, reps, &tc));
+      SS_TRY(batch_check_error(b));
+      if (tp < tg && tp < tc) b->mode = 1;
+      else if (tc < tg) b->mode = 2;
     }
   }
   return SS_OK;
@@ -2451,6 +2512,17 @@ ss_status ss_batch_capture(ss_batch b, int64_t nsteps) {
     b->graph = nullptr;
   }
   SS_TRY(batch_refresh(b));   // outside the capture
+  b->coop_direct = false;
+  if (b->mode == 2) {
+    // the run is one launch already: ss_batch_launch issues it directly
+    // (a cooperative launch is not recorded into a graph)
+    if (!b->coop_blocks) SS_TRY(b->dtype == SS_F64 ? batch_coop_size<double>(b) : batch_coop_size<float>(b));
+    if (nsteps > batch_coop_max_steps(b))
+      return fail(SS_ERR_ARG, "ss_batch_capture: %lld steps do not fit one cooperative launch", (long long)nsteps);
+    b->coop_direct = true;
+    b->graph_steps = nsteps;
+    return SS_OK;
+  }
   SS_TRY(hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"));
   ss_status st = batch_run(b, nsteps);
   hipGraph_t graph = nullptr;
@@ -2468,21 +2540,26 @@ ss_status ss_batch_capture(ss_batch b, int64_t nsteps) {
 
 ss_status ss_batch_launch(ss_batch b) {
   if (!b) return fail(SS_ERR_ARG, "ss_batch_launch: null batch");
-  if (!b->exec) return fail(SS_ERR_STATE, "ss_batch_launch: nothing captured");
+  if (!b->exec && !b->coop_direct) return fail(SS_ERR_STATE, "ss_batch_launch: nothing captured");
   SS_TRY(batch_check_members(b));
   SS_TRY(batch_refresh(b));
-  SS_TRY(hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch"));
+  if (b->coop_direct) {
+    if (b->mode != 2) return fail(SS_ERR_STATE, "ss_batch_launch: the mode changed since the capture");
+    SS_TRY(batch_run(b, b->graph_steps));
+  } else {
+    SS_TRY(hip_check(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch"));
+  }
   for (ss_grid g : b->grids) g->log_count += b->graph_steps;
   return SS_OK;
 }
 
 ss_status ss_batch_set_mode(ss_batch b, int mode) {
   if (!b) return fail(SS_ERR_ARG, "ss_batch_set_mode: null batch");
-  if (mode != 0 && mode != 1) return fail(SS_ERR_ARG, "ss_batch_set_mode: mode %d is not 0 or 1", mode);
+  if (mode < 0 || mode > 2) return fail(SS_ERR_ARG, "ss_batch_set_mode: mode %d is not 0, 1 or 2", mode);
   if (!b->ws) return fail(SS_ERR_STATE, "ss_batch_set_mode: bind the batch workspace first");
   if (!b->uploaded) SS_TRY(batch_upload(b, b->threads));
-  if (mode == 1 && !batch_single_ok(b))
-    return fail(SS_ERR_UNSUPPORTED, "ss_batch_set_mode: the single launch needs one block size for both passes");
+  if (mode != 0 && !batch_single_ok(b))
+    return fail(SS_ERR_UNSUPPORTED, "ss_batch_set_mode: the single launches need one block size for both passes");
   b->mode = mode;
   b->mode_set = true;
   return SS_OK;

@@ -21,6 +21,15 @@
 // CUs filled across step boundaries.  Every wait is bounded: when one
 // runs out, an error flag is raised and every later workgroup leaves at
 // once (the host reports it).
+//
+// Cooperative form: one launch runs every step with a fixed set of
+// workgroups, all resident at once (a cooperative launch).  In each step
+// workgroup g takes x tiles g, g + G, g + 2G, ... of the global numbering,
+// meets every other workgroup at a device-wide barrier, takes its k-space
+// tiles the same way and meets them again.  Two barriers a step replace
+// the two kernel boundaries of the grouped form, with none of the
+// single-launch form's per-item waits: for a few small grids, whose steps
+// are otherwise mostly launch gaps.
 #pragma once
 
 #include "ss_kernels.hpp"
@@ -196,6 +205,87 @@ batch_single(BatchArgs b, BatchSync y) {
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(xside ? y.xdone + i : y.kdone + i, 1u);
+}
+
+// ---- cooperative form -----------------------------------------------------------
+// Device-wide barrier number `target / gridDim.x` (the counter only grows):
+// every thread's stores are released to device scope, thread 0 adds one
+// arrival and polls (relaxed, bounded) until every workgroup has arrived,
+// then acquires.  False if the wait ran out or another workgroup's did.
+__device__ __forceinline__ bool coop_barrier(unsigned* ctl, unsigned target, unsigned limit, int* s_go) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(ctl, 1u);
+    unsigned n = 0;
+    int go = 1;
+    while (__hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        go = 0;
+        break;
+      }
+      if (++n > limit) {
+        __hip_atomic_store(ctl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        go = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_go = go;
+  }
+  __syncthreads();
+  return *s_go != 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SS_KWAVES)))
+batch_coop(BatchArgs b, BatchSync y) {
+  extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
+  C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
+  __shared__ int s_go;
+  const unsigned G = gridDim.x;
+  unsigned arrivals = 0;
+  for (int step = 0; step < y.nsteps; ++step) {
+    for (int tile = (int)blockIdx.x; tile < b.x_total; tile += (int)G) {
+      // a fresh copy of the thread index per tile: nothing derived from it
+      // is hoisted out of the loop (each size's set-up would stay live)
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      const int i = batch_find(b.m, b.count, tile, false);
+      const XArgs& a = b.m[i].x;
+      const int64_t blk = tile - b.m[i].x_first;
+      switch (b.m[i].nx) {
+#define SS_CASE(n)                                                \
+  case n:                                                         \
+    xpass_body<T, n, 1, XMODE_STEP, NLIN_POLY>(a, blk, lds, tid); \
+    break;
+        SS_BATCH_SIZES(SS_CASE)
+#undef SS_CASE
+      }
+      __syncthreads();   // the next tile reuses the LDS
+    }
+    arrivals += G;
+    if (!coop_barrier(y.ctl, arrivals, y.spin_limit, &s_go)) return;
+    for (int tile = (int)blockIdx.x; tile < b.k_total; tile += (int)G) {
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      const int i = batch_find(b.m, b.count, tile, true);
+      const KArgs& a = b.m[i].k;
+      const int bx = tile - b.m[i].k_first;
+      switch (b.m[i].ny) {
+#define SS_CASE(n)                                  \
+  case n:                                           \
+    kpass_body<T, n, true>(a, bx, 0, lds, tid);     \
+    break;
+        SS_BATCH_SIZES(SS_CASE)
+#undef SS_CASE
+      }
+      __syncthreads();
+    }
+    arrivals += G;
+    if (!coop_barrier(y.ctl, arrivals, y.spin_limit, &s_go)) return;
+  }
 }
 
 }  // namespace ss

@@ -114,6 +114,11 @@ hipError_t run_batch_k(BatchArgs b, int threads, int blocks, uint32_t lds, hipSt
 // steps, one workgroup per work item
 template <typename T>
 hipError_t run_batch_single(BatchArgs b, BatchSync y, int threads, uint32_t lds, hipStream_t s, LaunchEvents ev);
+// every step in one cooperative launch of `blocks` resident workgroups
+// (blocks = 0: ask how many fit, into *fit)
+template <typename T>
+hipError_t run_batch_coop(BatchArgs b, BatchSync y, int threads, uint32_t lds, int blocks, int* fit, hipStream_t s,
+                          LaunchEvents ev);
 
 // adjoint (Gray-Scott, 2D): sizes 8 .. 1024
 inline int xadj_tile(int esz, int nx, int64_t rows) {
@@ -457,6 +462,40 @@ hipError_t run_batch_single(BatchArgs b, BatchSync y, int threads, uint32_t lds,
   return launch_with(batch_single<T>, dim3((unsigned)items), dim3(threads), lds, s, ev, b, y);
 }
 
+template <typename T>
+hipError_t run_batch_coop(BatchArgs b, BatchSync y, int threads, uint32_t lds, int blocks, int* fit, hipStream_t s,
+                          LaunchEvents ev) {
+  if (threads < 64 || threads > 512) return hipErrorInvalidConfiguration;
+  const void* k = (const void*)batch_coop<T>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (blocks == 0) {
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, lds);
+    if (e != hipSuccess) return e;
+    *fit = per * ncu;
+    return hipSuccess;
+  }
+  if (y.nsteps < 1) return hipErrorInvalidConfiguration;
+  hipError_t e = hipSuccess;
+  if (ev.start) {
+    e = hipEventRecord(ev.start, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(batch_sync_reset<T>, dim3(1), dim3(256), 0, s, b, y);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* args[2] = {(void*)&b, (void*)&y};
+  e = hipLaunchCooperativeKernel(k, dim3((unsigned)blocks), dim3((unsigned)threads), args, lds, s);
+  if (e != hipSuccess) return e;
+  if (ev.stop) e = hipEventRecord(ev.stop, s);
+  return e;
+}
+
 #define SS_ADJ_CASES(M) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024)
 
 template <typename T>
@@ -540,6 +579,7 @@ hipError_t run_small(int n, SmallArgs a, hipStream_t s) {
   template hipError_t run_batch_x<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_batch_k<T>(BatchArgs, int, int, uint32_t, hipStream_t, LaunchEvents); \
   template hipError_t run_batch_single<T>(BatchArgs, BatchSync, int, uint32_t, hipStream_t, LaunchEvents); \
+  template hipError_t run_batch_coop<T>(BatchArgs, BatchSync, int, uint32_t, int, int*, hipStream_t, LaunchEvents); \
   template hipError_t run_xpass<T>(int, int, int, int, XArgs, hipStream_t, LaunchEvents); \
   template hipError_t run_ypass<T>(int, int, YArgs, int64_t, hipStream_t, LaunchEvents);  \
   template hipError_t run_kpass<T>(int, KArgs, int, hipStream_t, LaunchEvents);           \

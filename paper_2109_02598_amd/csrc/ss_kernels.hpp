@@ -363,8 +363,11 @@ struct XThreads {
 // block's threads form G = blockDim/S groups of S threads, G dividing R/2.
 // PRELOADED: the caller has already staged the tile's spectral rows in LDS
 // (the persistent kernel below does, from registers it filled earlier).
+// tid: the thread's index in the block (a caller that loops over tiles
+// passes a copy the compiler cannot see through, so that nothing derived
+// from it is hoisted out of the loop).
 template <typename T, int NX, int NF, int MODE, int NLM, bool PRELOADED = false>
-__device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* lds) {
+__device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* lds, int tid = threadIdx.x) {
   typedef XCfg<T, NX, NF> K;
   constexpr int S = K::S, H = K::H, HB = K::HB, PT = K::P;
   constexpr int REG = K::reg_for(NF);
@@ -372,7 +375,6 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
   const int R = a.rows_per_block;
   const int P = R >> 1;
   const int G = (int)blockDim.x / S;         // thread groups (lines in flight)
-  const int tid = threadIdx.x;
   const int g = tid / S, t = tid - g * S;
   const int64_t s0 = blk * R;
   const int64_t rows = a.rows;
@@ -847,11 +849,10 @@ struct KCfg {
 // CH2 (stepping form only): the field has a second explicit channel whose
 // term G2 (F.nonlin2) is transformed too: U = A S^ + B (N_1 G^ + N_2 G2^).
 template <typename T, int NL, bool HAT = false, int SCH = 0, int P = 8, bool CH2 = false>
-__device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>* lds) {
+__device__ __forceinline__ void kpass_body(const KArgs& a, int bx, int fi, C<T>* lds, int tid = threadIdx.x) {
   static_assert(!CH2 || HAT, "a second channel needs the stepping form");
   typedef KCfg<T, NL, P> K;
   constexpr int S = K::S, REG = K::REG;
-  const int tid = threadIdx.x;
   const int ls = tid / S, t = tid - ls * S;
   const KField F = fi == 0 ? a.fld[0] : a.fld[1];
   const int line0 = bx * a.lines_per_block;

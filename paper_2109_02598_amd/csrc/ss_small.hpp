@@ -4,7 +4,7 @@
 // handful of waves on an otherwise idle GPU, and a step pays two kernel
 // launches.  Here one workgroup holds the whole spectral state of a
 // one-field grid for a run of steps: the carried spectrum S^ in registers
-// (lines along y, 16 points per thread), the row pass's data and every
+// (lines along y, 2 to 8 points per thread), the row pass's data and every
 // exchange in LDS.  A run reads the state once and writes it once; a step
 // costs no launch and no HBM traffic.  The ETD1 factors of every mode do
 // not change between steps: a small kernel computes them once per run into
@@ -40,28 +40,18 @@ struct SmallArgs {
   int64_t log_capacity;
 };
 
-// Square grids N x N, N = 16 .. 128; 16 points per thread in both passes,
-// 8 for FP64 at N = 128 (1024 threads: the carried spectrum and the
-// working line of 16 FP64 points each would not fit the registers).
-#ifndef SS_SMALL_P16
-#define SS_SMALL_P16 16
-#endif
-#ifndef SS_SMALL_P32
-#define SS_SMALL_P32 16
-#endif
-#ifndef SS_SMALL_P64
-#define SS_SMALL_P64 16
-#endif
-#ifndef SS_SMALL_P128F
-#define SS_SMALL_P128F 16
-#endif
-#ifndef SS_SMALL_P128D
-#define SS_SMALL_P128D 8
-#endif
+// Square grids N x N, N = 16 .. 128.  Points per thread: as few as keep
+// the workgroup's lines in registers, so that the step spreads over the
+// CU's four SIMDs (one workgroup has no other waves to hide its latencies
+// behind).  Measured per step (Allen-Cahn, FP64 / FP32, one MI355X):
+//   N = 16:  2 points (64 threads)          2.3 / 2.0 us (16 points: 5.9 / 5.1)
+//   N = 32:  4 / 2 points (128 / 256)       4.2 / 3.4 us (16 points: 11.7 / 10.6)
+//   N = 64:  4 points (512 threads)         7.9 / 5.5 us (16 points: 13.6 / 10.9)
+//   N = 128: 8 points (1024 threads)        23.6 / 14.8 us (FP32, 16 points: 16.0)
+// (the FP64 128 line of 16 points beside the carried spectrum spills).
 template <typename T, int N>
 struct SmallCfg {
-  static constexpr int P = N == 16 ? SS_SMALL_P16 : N == 32 ? SS_SMALL_P32 : N == 64 ? SS_SMALL_P64
-                         : sizeof(T) == 8 ? SS_SMALL_P128D : SS_SMALL_P128F;
+  static constexpr int P = N == 16 ? 2 : N == 32 ? (sizeof(T) == 8 ? 4 : 2) : N == 64 ? 4 : 8;
   static constexpr int H = N / 2;     // k-space lines (kx = 0 .. N/2 - 1, kx = 0 packed with Nyquist)
   static constexpr int S = N / P;     // threads per k-space line = threads per row pair
   static constexpr int W = H * S;     // threads of the workgroup (also (N/2) row pairs x S)

@@ -608,7 +608,8 @@ class Batch:
 
     def set_mode(self, mode):
         """0: grouped launches per step; 1: one launch per run (a workgroup
-        per work item, ordered by a ticket counter)."""
+        per work item, ordered by a ticket counter); 2: one cooperative
+        launch per run (resident workgroups, two barriers a step)."""
         ss_batch_set_mode(self.b, mode)
 
     def mode(self):

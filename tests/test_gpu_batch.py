@@ -93,11 +93,13 @@ def test_batch_graph_replay_equals_eager(dtype):
     bg.close()
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_single_launch_matches_plain_grouped_and_oracle(dtype):
-    """One launch per run (a workgroup per work item, items drawn from a
-    ticket counter, per-member counters ordering the passes) gives the bits
-    of the plain path and of the grouped launches."""
+def test_single_launch_matches_plain_grouped_and_oracle(dtype, mode):
+    """One launch per run gives the bits of the plain path and of the
+    grouped launches: mode 1 (a workgroup per work item, items drawn from a
+    ticket counter, per-member counters ordering the passes) and mode 2
+    (resident workgroups, two device-wide barriers a step)."""
     torch, specstep = need_gpu()
     stream = torch.cuda.Stream()
     ws = make_members(PSIZES, dtype, seed0=4200)
@@ -108,8 +110,8 @@ def test_single_launch_matches_plain_grouped_and_oracle(dtype):
     want = [g.get_field(0).cpu().numpy() for g in plain]
     gp = grids_for(specstep, ws, dtype, stream.cuda_stream)
     bp = specstep.Batch(gp, autotune=False)
-    bp.set_mode(1)
-    assert bp.mode() == 1
+    bp.set_mode(mode)
+    assert bp.mode() == mode
     bp.step(7)
     bp.step(steps - 7)          # two launches: the counters restart per launch
     bp.check()
@@ -120,7 +122,7 @@ def test_single_launch_matches_plain_grouped_and_oracle(dtype):
     torch.cuda.synchronize()
     for i, w in enumerate(ws):
         got = gp[i].get_field(0).cpu().numpy()
-        assert same_as_plain(got, want[i]), (i, w.n, "single launch vs plain")
+        assert same_as_plain(got, want[i]), (i, w.n, "single launch vs plain", mode)
         assert same_as_plain(gg[i].get_field(0).cpu().numpy(), want[i]), (i, w.n, "grouped vs plain")
         ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, steps)[0]
         assert_parity(got, ref, dtype, ("single-launch member", i, w.n))
@@ -128,16 +130,19 @@ def test_single_launch_matches_plain_grouped_and_oracle(dtype):
     bg.close()
 
 
-def test_single_launch_graph_replay_equals_eager():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_single_launch_graph_replay_equals_eager(mode):
+    """Captured runs replayed (mode 1: a graph; mode 2: the cooperative
+    launch issued again) equal eager steps, with other work in between."""
     torch, specstep = need_gpu()
     stream = torch.cuda.Stream()
     ws = make_members(PSIZES[:6], "f32", seed0=4300)
     eager = grids_for(specstep, ws, "f32", stream.cuda_stream)
     be = specstep.Batch(eager, autotune=False)
-    be.set_mode(1)
+    be.set_mode(mode)
     graph = grids_for(specstep, ws, "f32", stream.cuda_stream)
     bg = specstep.Batch(graph, autotune=False)
-    bg.set_mode(1)
+    bg.set_mode(mode)
     bg.capture(5)
     for rep in range(3):
         bg.launch()
@@ -156,14 +161,19 @@ def test_single_launch_refused_without_one_block_size():
     ws = make_members([(64, 64), (256, 128)], "f32", seed0=4500)
     gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
     b = specstep.Batch(gs, autotune=False)
+    for mode in (1, 2):
+        with pytest.raises(specstep.SpecStepError) as e:
+            b.set_mode(mode)
+        assert e.value.code == specstep.SS_ERR_UNSUPPORTED
+        assert b.mode() == 0
     with pytest.raises(specstep.SpecStepError) as e:
-        b.set_mode(1)
-    assert e.value.code == specstep.SS_ERR_UNSUPPORTED
-    assert b.mode() == 0
+        b.set_mode(3)
+    assert e.value.code == specstep.SS_ERR_ARG
     b.close()
 
 
-def test_single_launch_wait_limit_is_reported_and_recovered():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_single_launch_wait_limit_is_reported_and_recovered(mode):
     """A wait bound of zero gives up at the first unmet wait: every
     workgroup leaves, the launch ends, ss_batch_check reports it; with the
     bound restored the batch steps correctly again."""
@@ -172,7 +182,7 @@ def test_single_launch_wait_limit_is_reported_and_recovered():
     ws = make_members(PSIZES[:4], "f32", seed0=4400)
     gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
     b = specstep.Batch(gs, autotune=False)
-    b.set_mode(1)
+    b.set_mode(mode)
     specstep.ss_batch_set_wait_limit(b.b, 0)
     b.step(10)
     with pytest.raises(specstep.SpecStepError) as e:
@@ -211,17 +221,19 @@ def test_batch_64_uneven_members():
     b.check()
     got = [g.get_field(0).cpu().numpy() for g in gs]
     b.close()
-    # the other form of the batched step on the same members: the same bits
-    go = grids_for(specstep, ws, "f32", stream.cuda_stream)
-    bo = specstep.Batch(go, autotune=False)
-    other = 1 - b_mode
-    bo.set_mode(other)
-    bo.capture(steps)
-    bo.launch()
-    bo.check()
-    for i in range(len(ws)):
-        assert same_as_plain(go[i].get_field(0).cpu().numpy(), got[i]), (i, "mode", other)
-    bo.close()
+    # the other forms of the batched step on the same members: the same bits
+    for other in (m for m in (0, 1, 2) if m != b_mode):
+        go = grids_for(specstep, ws, "f32", stream.cuda_stream)
+        bo = specstep.Batch(go, autotune=False)
+        bo.set_mode(other)
+        bo.capture(steps)
+        bo.launch()
+        bo.check()
+        for i in range(len(ws)):
+            assert same_as_plain(go[i].get_field(0).cpu().numpy(), got[i]), (i, "mode", other)
+        bo.close()
+        for g in go:
+            g.close()
     for i, w in enumerate(ws):
         p = specstep.Grid(w.n, w.dx, dtype="f32", model=w.model, coef=w.coef, dt=w.dt,
                           stream=stream.cuda_stream)
@@ -235,3 +247,55 @@ def test_batch_64_uneven_members():
     for i, w in enumerate(ws):
         ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, steps, fft=fft)[0]
         assert_parity(got[i], ref, "f32", ("member", i, w.n, "coef", tuple(round(c, 4) for c in w.coef)))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_member_cooperative_run_of_the_small_workload(dtype):
+    """The Allen-Cahn 128^2 workload (dt 0.5, 100 steps) as a one-member
+    batch in one cooperative launch: the plain path's bits, and the oracle
+    to the parity bar."""
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    w = inputs.allen_cahn_2d(n=128, seed=1)
+    f0 = as_input(w.fields, dtype)
+    p = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=w.dt, stream=stream.cuda_stream)
+    p.set_field(0, f0[0])
+    p.step(100)
+    want = p.get_field(0).cpu().numpy()
+    g = specstep.Grid(w.n, w.dx, dtype=dtype, model=w.model, coef=w.coef, dt=w.dt, stream=stream.cuda_stream)
+    g.set_field(0, f0[0])
+    b = specstep.Batch([g], autotune=False)
+    b.set_mode(2)
+    b.step(40)
+    b.step(60)
+    b.check()
+    got = g.get_field(0).cpu().numpy()
+    say("cooperative one-member batch, workgroups:", b.info())
+    assert same_as_plain(got, want)
+    assert_parity(got, spectral.step_n(f0, w.model, w.coef, w.dt, w.dx, 100)[0], dtype, "cooperative AC 128^2")
+    b.close()
+    g.close()
+    p.close()
+
+
+def test_check_after_grouped_steps_on_a_dirty_workspace():
+    """Binding clears the counters and the error flag, so ss_batch_check
+    after grouped launches (which never touch them) reports no error even
+    when the workspace held other data."""
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    ws = make_members(PSIZES[:3], "f32", seed0=4600)
+    gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    b = specstep.Batch(gs, autotune=False)
+    nbytes = specstep.ss_batch_workspace_size(b.b)
+    dirty = torch.full((nbytes,), 255, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    specstep.ss_batch_bind_workspace(b.b, dirty.data_ptr(), nbytes)
+    b.workspace = dirty
+    b.set_mode(0)
+    b.step(3)
+    b.check()
+    for g, w in zip(gs, ws):
+        ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, 3)[0]
+        assert_parity(g.get_field(0).cpu().numpy(), ref, "f32", ("dirty workspace", w.n))
+    b.close()
