@@ -131,7 +131,7 @@ def run_gpu(w, dtype, steps, warmup, profile_steps, autotune=True):
     return ms, wall, prof, mass
 
 
-def run_batch(steps=500, reps=3):
+def run_batch(steps=500, reps=3, forms=(0, 1, 2)):
     """64 uneven Cahn-Hilliard grids (FP32): one captured run of `steps`
     batched steps in each form (grouped launches in a graph, one launch, one
     cooperative launch), the tuned form eager, and the same members stepped
@@ -147,7 +147,10 @@ def run_batch(steps=500, reps=3):
         g.set_field(0, w.fields[0].astype(np.float32))
         gs.append(g)
     cells = sum(w.cells for w in ws)
-    b = specstep.Batch(gs, autotune=True, reps=reps)
+    b = specstep.Batch(gs, autotune=False)
+    if tuple(sorted(forms)) != (0, 1, 2):
+        b.set_mode(0)               # the tuner then times block sizes only
+    specstep.ss_batch_autotune(b.b, reps)
     tuned_mode = b.mode()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -167,10 +170,14 @@ def run_batch(steps=500, reps=3):
     # cooperative launch need one block size for both passes)
     ms_modes = {0: graph_ms(0), 1: None, 2: None}
     for m in (1, 2):
+        if m not in forms:
+            continue
         try:
             ms_modes[m] = graph_ms(m)
         except specstep.SpecStepError:
             pass
+    if tuned_mode not in forms or ms_modes[tuned_mode] is None:
+        tuned_mode = 0
     b.set_mode(tuned_mode)
     ms_graph = ms_modes[tuned_mode]
     e0.record(stream)
@@ -257,7 +264,7 @@ def run_adjoint(steps=200, K=20, dtype="f32"):
 
 def run_euler(w, dtype, steps=500):
     """The forward-Euler finite-difference solver on the same grid and
-    fields (axis-wise, isotropic and fourth-order Laplacians), with the
+    fields (every Laplacian stencil of the dimension), with the
     fixed-model kernels and with the model's equation read at run time; for
     a 2D workload also Cahn-Hilliard on 256^3 with the 3D stencils.  A
     Cahn-Hilliard step is two launches, mu from psi, then psi + dt M L mu
@@ -279,7 +286,7 @@ def euler_times(w, dtype, steps):
     esz = 8 if dtype == "f64" else 4
     nfa = {"allen_cahn": 2, "cahn_hilliard": 5, "pfc": 8, "gray_scott": 4, "model_c": 6}[w.model]
     text, names = MODEL_TEXT.get(w.model, (None, ()))
-    variants = [(st, eq) for st in ((0, 9, 4) if len(w.n) == 2 else (0, 19, 27, 4))
+    variants = [(st, eq) for st in ((0, 9, 4, 17, 21) if len(w.n) == 2 else (0, 15, 19, 21, 27, 4))
                 for eq in ((False, True) if text else (False,))]
     for st, eq in variants:
         kw = (dict(equations=text, coefs=dict(zip(names, w.coef))) if eq else dict(model=w.model, coef=w.coef))
@@ -297,7 +304,8 @@ def euler_times(w, dtype, steps):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         g.close()
-        name = {0: "axis-wise", 4: "fourth-order axis-wise"}.get(st, "isotropic %d-point" % st)
+        name = {0: "axis-wise", 4: "fourth-order axis-wise"}.get(
+            st, ("fourth-order isotropic %d-point" if len(w.n) == 2 and st in (17, 21) else "isotropic %d-point") % st)
         name += ", equation text" if eq else ""
         # arrays moved per step: the fused Cahn-Hilliard launch (2D axis-wise,
         # grids the row-marching kernel does not tile) moves 2; otherwise one
@@ -424,6 +432,160 @@ def load_traffic(workload, dtype):
     return rec
 
 
+def counter_rows(d):
+    """Rows (kernel name, counter name, value) of a rocprofv3 --pmc output
+    directory, in dispatch order."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit("expected one counter_collection.csv under %s, found %d" % (d, len(files)))
+    rows = []
+    with open(files[0]) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return [(k, c, v) for _, k, c, v in rows]
+
+
+def traffic_record(workload, fetch_dir, write_dir, copyf_dir, copyw_dir, copy_mb=64, out_dir=None):
+    """Write profiles/traffic_<workload>_<dtype>.json from two counter runs of
+    the bench (FETCH_SIZE, then WRITE_SIZE) and two of --copy-calibration:
+    HBM bytes per launch of each pass, the counters (KiB per dispatch)
+    scaled by what they read for a plain device copy of copy_mb MiB.  Only
+    the dispatches after each precision's refresh of the carried spectrum
+    (kfwd_kernel) count: the timed configuration, not the tuner's trials."""
+    import re
+    kib = copy_mb * 1024.0
+
+    def copy_factor(d, name):
+        vals = [v for k, c, v in counter_rows(d) if c == name and "copyBuffer" in k]
+        if not vals:
+            raise SystemExit("no device copy in %s" % d)
+        return kib / (sum(vals) / len(vals))
+
+    ff, fw = copy_factor(copyf_dir, "FETCH_SIZE"), copy_factor(copyw_dir, "WRITE_SIZE")
+    pat = re.compile(r"ss::(kpass|xpass|xpass_pp|ypass|kfwd)_kernel<(double|float), (\d+)(?:, (.*))?>")
+    out = {}
+    for dtype, tname in (("f64", "double"), ("f32", "float")):
+        per = {}
+        for d, cname, factor in ((fetch_dir, "FETCH_SIZE", ff), (write_dir, "WRITE_SIZE", fw)):
+            started = False
+            for k, c, v in counter_rows(d):
+                m = pat.search(k)
+                if c != cname or not m or m.group(2) != tname:
+                    continue
+                kind, rest = m.group(1), m.group(4) or ""
+                if kind == "kfwd":
+                    started = True
+                    continue
+                if not started:
+                    continue
+                if kind == "kpass" and not rest.startswith("true, 0"):
+                    continue
+                if kind in ("xpass", "xpass_pp") and not (rest.startswith("1, 2, 0") or (kind == "xpass_pp" and rest.startswith("1, 0"))):
+                    continue
+                key = "xpass" if kind == "xpass_pp" else kind
+                per.setdefault(key, {}).setdefault(cname, []).append(v * 1024.0 * factor)
+        bpl = {k: sum(sum(x) / len(x) for x in cs.values()) for k, cs in per.items() if len(cs) == 2}
+        rec = {"workload": workload, "dtype": dtype, "source_hash": kernel_source_hash(),
+               "copy_factor_fetch": ff, "copy_factor_write": fw, "bytes_per_launch": bpl,
+               "command": "see profiles/%s_kernels.md" % workload}
+        path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), "traffic_%s_%s.json" % (workload, dtype))
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        out[dtype] = bpl
+    return out
+
+
+def trace_summary(d, last=0):
+    """Markdown table of a rocprofv3 --kernel-trace output directory: per
+    kernel, the dispatches after each precision's refresh of the carried
+    spectrum (kfwd_kernel; the timed configuration, not the tuner's trials
+    before it), or with last > 0 the last `last` dispatches of each kernel;
+    their count, mean and minimum duration in microseconds."""
+    import csv
+    import glob
+    import re
+    files = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit("expected one kernel_trace.csv under %s, found %d" % (d, len(files)))
+    rows = []
+    with open(files[0]) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"],
+                         (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
+    rows.sort()
+    prec = re.compile(r"<(double|float)\b")
+    started, stats = set(), {}
+    for _, k, us in rows:
+        m = prec.search(k)
+        p = m.group(1) if m else None
+        if "ss::kfwd_kernel<" in k:
+            started.add(p)
+        if p not in started and not last:
+            continue
+        stats.setdefault(k, []).append(us)
+    if last:
+        stats = {k: v[-last:] for k, v in stats.items()}
+    lines = ["| kernel | calls | mean us | min us |", "|---|---|---|---|"]
+    for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append("| `%s` | %d | %.2f | %.2f |" % (k[:90], len(v), sum(v) / len(v), min(v)))
+    return "\n".join(lines)
+
+
+def counter_table(workload, fetch_dir, write_dir, copyf_dir, copyw_dir, copy_mb=64):
+    """Markdown table of the memory counters per dispatch of the timed
+    configuration (dispatches after each precision's kfwd_kernel): raw
+    FETCH_SIZE and WRITE_SIZE means (KiB), the bytes they stand for (scaled
+    by a plain device copy of copy_mb MiB) and, for the step's passes, the
+    algorithmic bytes and the ratio."""
+    import re
+    kib = copy_mb * 1024.0
+    fc = [v for k, c, v in counter_rows(copyf_dir) if c == "FETCH_SIZE" and "copyBuffer" in k]
+    wc = [v for k, c, v in counter_rows(copyw_dir) if c == "WRITE_SIZE" and "copyBuffer" in k]
+    ff, fw = kib / (sum(fc) / len(fc)), kib / (sum(wc) / len(wc))
+    w = workloads()[workload]()
+    prec = re.compile(r"<(double|float)\b")
+    kind = re.compile(r"ss::(kpass|xpass|xpass_pp|ypass)_kernel<(double|float), \d+, (.*)>")
+    vals = {}
+    for d, cname in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        started = set()
+        for k, c, v in counter_rows(d):
+            if c != cname:
+                continue
+            m = prec.search(k)
+            p = m.group(1) if m else None
+            if "ss::kfwd_kernel<" in k:
+                started.add(p)
+            if p in started:
+                vals.setdefault(k, {}).setdefault(cname, []).append(v)
+    lines = ["Copy calibration: a %d MiB device copy reads FETCH_SIZE = %.1f KiB (factor %.4f) and "
+             "WRITE_SIZE = %.1f KiB (factor %.4f)." % (copy_mb, kib / ff, ff, kib / fw, fw), "",
+             "| kernel | dispatches | FETCH raw | WRITE raw | scaled bytes | algorithmic bytes | ratio |",
+             "|---|---|---|---|---|---|---|"]
+    for k in sorted(vals, key=lambda k: (prec.search(k).group(1) if prec.search(k) else "", k)):
+        cs = vals[k]
+        if len(cs) != 2:
+            continue
+        f = sum(cs["FETCH_SIZE"]) / len(cs["FETCH_SIZE"])
+        wr = sum(cs["WRITE_SIZE"]) / len(cs["WRITE_SIZE"])
+        scaled = (f * ff + wr * fw) * 1024.0
+        algo, ratio = "", ""
+        m = kind.search(k)
+        if m:
+            esz = 8 if m.group(2) == "double" else 4
+            rest = m.group(3)
+            name = {"kpass": "kpass", "xpass": "xpass", "xpass_pp": "xpass", "ypass": "ypass_inv"}[m.group(1)]
+            step_x = rest.startswith("1, 2, 0") or (m.group(1) == "xpass_pp")
+            if (name == "kpass" and rest.startswith("true, 0")) or (name == "xpass" and step_x) or name == "ypass_inv":
+                a = algorithmic_bytes(name, w, esz)
+                algo, ratio = "%d" % a, "%.3f" % (scaled / a)
+        lines.append("| `%s` | %d | %.1f | %.1f | %.0f | %s | %s |" % (
+            k[:90], len(cs["FETCH_SIZE"]), f, wr, scaled, algo, ratio))
+    return "\n".join(lines)
+
+
 def host_cpu():
     """CPU model name, logical CPUs and the CPUs this process may use."""
     model = None
@@ -494,10 +656,34 @@ def main():
     ap.add_argument("--only", choices=["equations", "euler", "batch", "adjoint"],
                     help="run only this leg on the workload and print its JSON object (for profiling)")
     ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--batch-forms", default="0,1,2",
+                    help="forms the batch leg times beside the grouped graph (a profiler that "
+                         "cannot follow a cooperative launch takes 0,1)")
+    ap.add_argument("--traffic-record", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
+                    help="only write the traffic records of --workload from rocprofv3 --pmc output "
+                         "directories (FETCH_SIZE and WRITE_SIZE runs of the bench, then of "
+                         "--copy-calibration 64) and exit; no GPU is used")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="only print the kernel table of a rocprofv3 --kernel-trace output "
+                         "directory (the timed configuration's dispatches) and exit; no GPU is used")
+    ap.add_argument("--counter-table", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
+                    help="only print the memory-counter table of --workload from the same four "
+                         "rocprofv3 --pmc output directories as --traffic-record and exit; no GPU is used")
+    ap.add_argument("--trace-last", type=int, default=0, metavar="N",
+                    help="with --trace-summary: the last N dispatches of each kernel instead")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (for scaling "
                          "the memory counters of a profiler) and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.trace_last), flush=True)
+        return
+    if args.counter_table:
+        print(counter_table(args.workload, *args.counter_table), flush=True)
+        return
+    if args.traffic_record:
+        print(json.dumps(traffic_record(args.workload, *args.traffic_record)), flush=True)
+        return
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration * 1024 * 1024
@@ -526,7 +712,8 @@ def main():
     w = workloads()[args.workload]()
     if args.only:
         leg = {"equations": lambda: run_equations(w, args.dtype), "euler": lambda: run_euler(w, args.dtype),
-               "batch": run_batch, "adjoint": run_adjoint}[args.only]
+               "batch": lambda: run_batch(forms=tuple(int(v) for v in args.batch_forms.split(","))),
+               "adjoint": run_adjoint}[args.only]
         print(json.dumps({args.only: leg()}), flush=True)
         return
     print("bench: workload %s cells %d dtype %s steps %d warmup %d" %

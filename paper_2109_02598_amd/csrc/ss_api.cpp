@@ -792,7 +792,8 @@ ss_status sf_run(ss_grid g, int field, double* s_out, int64_t* n_out, int nbins)
     return fail(SS_ERR_UNSUPPORTED, "ss_structure_factor: no line tiling fits this grid");
   a.lines_per_block = L;
   // per-block partial histograms in the staging array
-  const int64_t per_block = (int64_t)nbins * (int64_t)(sizeof(double) + sizeof(uint32_t));
+  a.pstride = (nbins + 31) & ~31;   // rows of whole 128-byte lines
+  const int64_t per_block = (int64_t)a.pstride * (int64_t)(sizeof(double) + sizeof(uint32_t));
   const int64_t cap = (int64_t)g->field_bytes() / per_block;
   int64_t nblk = a.nlines / L;
   if (nblk > 512) nblk = 512;
@@ -800,7 +801,7 @@ ss_status sf_run(ss_grid g, int field, double* s_out, int64_t* n_out, int nbins)
   if (nblk < 1) return fail(SS_ERR_UNSUPPORTED, "ss_structure_factor: grid too small for %d bins", nbins);
   a.nblocks = (int)nblk;
   a.part_sum = (double*)g->staging;
-  a.part_cnt = (uint32_t*)((char*)g->staging + (size_t)nblk * nbins * sizeof(double));
+  a.part_cnt = (uint32_t*)((char*)g->staging + (size_t)nblk * a.pstride * sizeof(double));
   a.s_out = s_out;
   a.n_out = n_out;
   SS_TRY(hip_check(ss::run_sfpass<T>(nl, a, g->stream), "structure factor pass launch"));

@@ -305,7 +305,7 @@ hipError_t run_sfpass(int nl, SFArgs a, hipStream_t s) {
 
 template <typename T>
 hipError_t run_sfreduce(SFArgs a, hipStream_t s) {
-  return launch_with(sf_reduce_kernel<T>, dim3((unsigned)((a.nbins + 7) / 8)), dim3(256), 0, s,
+  return launch_with(sf_reduce_kernel<T>, dim3((unsigned)((a.nbins + 31) / 32)), dim3(1024), 0, s,
                      LaunchEvents(), a);
 }
 

@@ -1091,11 +1091,12 @@ __global__ void __launch_bounds__(512) kfwd_kernel(KArgs a) {
 // ---------------------------------------------------------------------------
 struct SFArgs {
   const void* spec;        // transformed occupancy, layout of the state
-  double* part_sum;        // [gridDim.x][nbins] per-block sums of |rho_hat|^2 / N
-  uint32_t* part_cnt;      // [gridDim.x][nbins] per-block mode counts
+  double* part_sum;        // [gridDim.x][pstride] per-block sums of |rho_hat|^2 / N
+  uint32_t* part_cnt;      // [gridDim.x][pstride] per-block mode counts
   double* s_out;           // [nbins] radial average (sf_reduce)
   int64_t* n_out;          // [nbins] modes per bin (sf_reduce)
   int nbins;
+  int pstride;             // row stride of the partials: nbins rounded up to 32 (whole lines)
   int nblocks;             // rows of the partials
   int nlines, J, lines_per_block, nx, three_d, lb;
   double inv_n;            // 1/N
@@ -1203,29 +1204,31 @@ __global__ void __launch_bounds__(512) sfpass_kernel(SFArgs a) {
   const int ntiles = a.nlines / a.lines_per_block;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) sf_tile<T, NL>(a, tile, lds, hs, hc);
   __syncthreads();
-  double* ps = a.part_sum + (int64_t)blockIdx.x * a.nbins;
-  uint32_t* pc = a.part_cnt + (int64_t)blockIdx.x * a.nbins;
+  double* ps = a.part_sum + (int64_t)blockIdx.x * a.pstride;
+  uint32_t* pc = a.part_cnt + (int64_t)blockIdx.x * a.pstride;
   for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) {
     ps[i] = hs[i];
     pc[i] = hc[i];
   }
 }
 
-// Reduction of the partials: a block takes 8 bins; thread (slice j, bin i)
-// adds rows j, j + 32, j + 64, ... of bin i in order, then the 32 slice
-// sums of each bin are added in slice order (the same order every call).
+// Reduction of the partials: a block takes 32 bins (a row segment of 256
+// bytes of sums and 128 of counts: whole cache lines, the rows being
+// padded to a multiple of 32 bins, which the block reads alone); thread (slice j, bin i) adds rows j, j + 32, j + 64, ... of
+// bin i in order, then the 32 slice sums of each bin are added in slice
+// order (the same order every call).
 template <typename T>
-__global__ void __launch_bounds__(256) sf_reduce_kernel(SFArgs a) {
-  __shared__ double ps[32][8];
-  __shared__ int64_t pn[32][8];
-  const int i = threadIdx.x & 7, j = threadIdx.x >> 3;
-  const int b = blockIdx.x * 8 + i;
+__global__ void __launch_bounds__(1024) sf_reduce_kernel(SFArgs a) {
+  __shared__ double ps[32][32];
+  __shared__ int64_t pn[32][32];
+  const int i = threadIdx.x & 31, j = threadIdx.x >> 5;
+  const int b = blockIdx.x * 32 + i;
   double s = 0.0;
   int64_t n = 0;
   if (b < a.nbins) {
     for (int k = j; k < a.nblocks; k += 32) {
-      s += a.part_sum[(int64_t)k * a.nbins + b];
-      n += a.part_cnt[(int64_t)k * a.nbins + b];
+      s += a.part_sum[(int64_t)k * a.pstride + b];
+      n += a.part_cnt[(int64_t)k * a.pstride + b];
     }
   }
   ps[j][i] = s;

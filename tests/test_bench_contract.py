@@ -81,3 +81,63 @@ def test_cpu_baseline_uses_the_host_cores():
     assert r["cores"] == max(1, min(16, r["host"]["usable_cpus"]))
     assert r["single_thread"]["cores"] == 1 and r["single_thread"]["value"] > 0
     assert r["host"]["cpu_model"] and r["host"]["nproc"] >= 1
+
+
+def write_counters(d, rows):
+    """A rocprofv3 counter_collection.csv with the given (kernel, counter,
+    value) rows, in dispatch order."""
+    import csv
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "x_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(["Correlation_Id", "Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow([i + 1, i + 1, k, c, float(v)])
+
+
+def test_traffic_record_from_counter_runs(tmp_path):
+    """Counters per dispatch (KiB) scaled by the copy calibration; only the
+    timed configuration's dispatches (after each precision's refresh of the
+    carried spectrum) count, and the tuner's trials before it do not."""
+    kp64 = "void ss::kpass_kernel<double, 2048, true, 0>(ss::KArgs)"
+    xp64 = "void ss::xpass_kernel<double, 2048, 1, 2, 0>(ss::XArgs)"
+    sf64 = "void ss::xpass_kernel<double, 2048, 1, 2, 3>(ss::XArgs)"
+    kf64 = "void ss::kfwd_kernel<double, 2048>(ss::KArgs)"
+    kp32 = "void ss::kpass_kernel<float, 2048, true, 0>(ss::KArgs)"
+    xp32 = "void ss::xpass_kernel<float, 2048, 1, 2, 0>(ss::XArgs)"
+    kf32 = "void ss::kfwd_kernel<float, 2048>(ss::KArgs)"
+    for c, v64, v32 in (("FETCH_SIZE", (65000.0, 33000.0), (33000.0, 16500.0)),
+                        ("WRITE_SIZE", (65536.0, 32768.0), (32768.0, 16384.0))):
+        rows = [(kp64, c, 1.0), (xp64, c, 1.0), (kf64, c, 1.0),          # trials, then the refresh
+                (xp64, c, v64[1]), (kp64, c, v64[0]), (sf64, c, 5.0), (xp64, c, v64[1]), (kp64, c, v64[0]),
+                (kp32, c, 1.0), (kf32, c, 1.0), (xp32, c, v32[1]), (kp32, c, v32[0])]
+        write_counters(str(tmp_path / c), rows)
+    copy = "__amd_rocclr_copyBuffer"
+    write_counters(str(tmp_path / "cf"), [(copy, "FETCH_SIZE", 32768.0)] * 3)
+    write_counters(str(tmp_path / "cw"), [(copy, "WRITE_SIZE", 65536.0)] * 3)
+    out = bench.traffic_record("ch2048", str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE"),
+                               str(tmp_path / "cf"), str(tmp_path / "cw"), out_dir=str(tmp_path))
+    assert out["f64"]["kpass"] == pytest.approx((65000.0 * 2 + 65536.0) * 1024)
+    assert out["f64"]["xpass"] == pytest.approx((33000.0 * 2 + 32768.0) * 1024)
+    assert out["f32"]["kpass"] == pytest.approx((33000.0 * 2 + 32768.0) * 1024)
+    rec = bench.json.load(open(tmp_path / "traffic_ch2048_f64.json"))
+    assert rec["source_hash"] == bench.kernel_source_hash()
+    assert rec["copy_factor_fetch"] == pytest.approx(2.0) and rec["copy_factor_write"] == pytest.approx(1.0)
+
+
+def test_trace_summary_counts_the_timed_configuration(tmp_path):
+    import csv
+    rows = [("void ss::kpass_kernel<double, 2048, true, 0>(ss::KArgs)", 0, 50000),   # a trial
+            ("void ss::kfwd_kernel<double, 2048>(ss::KArgs)", 100000, 118000),
+            ("void ss::kpass_kernel<double, 2048, true, 0>(ss::KArgs)", 200000, 224000),
+            ("void ss::kpass_kernel<double, 2048, true, 0>(ss::KArgs)", 300000, 326000),
+            ("void ss::kpass_kernel<float, 2048, true, 0>(ss::KArgs)", 400000, 414000)]   # before its refresh
+    os.makedirs(tmp_path / "kt")
+    with open(tmp_path / "kt" / "x_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        for i, (k, a, b) in enumerate(rows):
+            w.writerow([i + 1, k, a, b])
+    table = bench.trace_summary(str(tmp_path / "kt"))
+    assert "| `void ss::kpass_kernel<double, 2048, true, 0>(ss::KArgs)` | 2 | 25.00 | 24.00 |" in table
+    assert "float" not in table

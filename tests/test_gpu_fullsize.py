@@ -147,7 +147,7 @@ def gpu_euler_run(w, stencil, steps, dt, text=None):
     return out
 
 
-@pytest.mark.parametrize("stencil", [0, 9, 4])
+@pytest.mark.parametrize("stencil", [0, 9, 4, 17, 21])
 def test_euler_cahn_hilliard_2048(stencil):
     """The forward-Euler leg's 2D workload (dt 0.01), fixed-model kernels and
     the equation text, 10 steps element by element."""
@@ -158,7 +158,7 @@ def test_euler_cahn_hilliard_2048(stencil):
         assert_parity(got, want, "f64", ("euler CH 2048^2 stencil", stencil, "text" if text else "fixed"))
 
 
-@pytest.mark.parametrize("stencil", [0, 19, 27, 4])
+@pytest.mark.parametrize("stencil", [0, 15, 19, 21, 27, 4])
 def test_euler_cahn_hilliard_256_cubed(stencil):
     """The forward-Euler leg's 3D workload (256^3, dt 0.01), fixed-model
     kernels and the equation text, 2 steps element by element."""
