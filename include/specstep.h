@@ -489,6 +489,15 @@ ss_status ss_bind_mass_log(ss_grid g, double* device_ptr, int64_t capacity);
 /* Number of steps taken since the mass log was bound. */
 ss_status ss_mass_log_count(ss_grid g, int64_t* count);
 
+/* The logged rows copied to host memory: min(max, steps logged) rows of
+ * nfields doubles (row i = step i since the log was bound), after the
+ * grid's stream has finished the steps enqueued so far (synchronises the
+ * stream).  *rows (may be NULL) receives the number copied.  dst_host is
+ * only written during the call.  Errors: SS_ERR_ARG (null grid, negative
+ * max, null dst_host with max > 0), SS_ERR_STATE (no log bound),
+ * SS_ERR_DEVICE. */
+ss_status ss_mass_log(ss_grid g, double* dst_host, int64_t max, int64_t* rows);
+
 /* ---- Structure factor (Sec. 3, coarsening check against Porod's law) ----
  *
  * The radially averaged static structure factor of one field: the

@@ -2361,6 +2361,21 @@ ss_status ss_mass_log_count(ss_grid g, int64_t* count) {
   return SS_OK;
 }
 
+ss_status ss_mass_log(ss_grid g, double* dst_host, int64_t max, int64_t* rows) {
+  if (rows) *rows = 0;
+  if (!g) return fail(SS_ERR_ARG, "ss_mass_log: null grid");
+  if (max < 0) return fail(SS_ERR_ARG, "ss_mass_log: negative max");
+  if (!dst_host && max > 0) return fail(SS_ERR_ARG, "ss_mass_log: null destination");
+  if (!g->mass_log) return fail(SS_ERR_STATE, "ss_mass_log: no mass log is bound");
+  const int64_t n = std::min(max, std::min(g->log_count, g->log_cap));
+  SS_TRY(hip_check(hipStreamSynchronize(g->stream), "ss_mass_log: synchronise"));
+  if (n > 0)
+    SS_TRY(hip_check(hipMemcpy(dst_host, g->mass_log, sizeof(double) * (size_t)n * (size_t)g->nf,
+                               hipMemcpyDeviceToHost), "ss_mass_log: copy"));
+  if (rows) *rows = n;
+  return SS_OK;
+}
+
 ss_status ss_set_stream(ss_grid g, void* stream) {
   if (!g) return fail(SS_ERR_ARG, "ss_set_stream: null grid");
   g->stream = (hipStream_t)stream;
@@ -2472,11 +2487,15 @@ ss_status ss_batch_autotune(ss_batch b, int reps) {
         return b->dtype == SS_F64 ? batch_launch_coop<double>(b, nrun, true, ev)
                                   : batch_launch_coop<float>(b, nrun, true, ev);
       };
-      float tg, tp, tc;
+      float tg, tp, tc = 1e30f;
       SS_TRY(time_launch(b->grids[0], grouped, reps, &tg));
       SS_TRY(time_launch(b->grids[0], single, reps, &tp));
       SS_TRY(batch_check_error(b));
-      SS_TRY(time_launch(b->grids[0], coop, reps, &tc));
+      // a device that refuses the cooperative launch leaves that form out
+      if (time_launch(b->grids[0], coop, reps, &tc) != SS_OK) {
+        (void)hipGetLastError();
+        tc = 1e30f;
+      }
       SS_TRY(batch_check_error(b));
       if (tp < tg && tp < tc) b->mode = 1;
       else if (tc < tg) b->mode = 2;

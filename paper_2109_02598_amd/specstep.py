@@ -64,6 +64,7 @@ def lib():
         "ss_get_tiles": [vp, ctypes.POINTER(cint)],
         "ss_set_tiles": [vp, ctypes.POINTER(cint)],
         "ss_mass_log_count": [vp, ctypes.POINTER(i64)],
+        "ss_mass_log": [vp, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)],
         "ss_structure_factor_nbins": [vp, ctypes.POINTER(cint)],
         "ss_set_solver": [vp, cint, cint],
         "ss_get_step_arrangement": [vp, ctypes.POINTER(cint)],
@@ -238,6 +239,17 @@ def ss_mass_log_count(h):
     c = ctypes.c_int64()
     _check(lib().ss_mass_log_count(h, ctypes.byref(c)))
     return c.value
+
+
+def ss_mass_log(h, max_rows, nfields):
+    """The logged rows copied to the host (synchronises the grid's stream):
+    an array of shape (rows, nfields)."""
+    import numpy as np
+    out = np.zeros(max(int(max_rows), 0) * int(nfields), dtype=np.float64)
+    rows = ctypes.c_int64()
+    _check(lib().ss_mass_log(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(max_rows),
+                             ctypes.byref(rows)))
+    return out[: rows.value * int(nfields)].reshape(rows.value, int(nfields))
 
 
 def ss_structure_factor_nbins(h):

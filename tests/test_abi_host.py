@@ -175,3 +175,20 @@ def test_noalloc_validation(L):
         assert "scratch" in ss.ss_last_error()
     finally:
         ss.ss_destroy_grid(big)
+
+
+def test_mass_log_copy_validation(L):
+    """ss_mass_log (the host copy of the per-step log) checks its arguments
+    and the bound log before touching the device."""
+    buf = (ctypes.c_double * 8)()
+    rows = ctypes.c_int64(7)
+    assert L.ss_mass_log(None, buf, 8, ctypes.byref(rows)) == ss.SS_ERR_ARG
+    assert rows.value == 0
+    h = ss.ss_create_grid((64, 32), (1, 1), ss.SS_F64)
+    try:
+        assert L.ss_mass_log(h, buf, -1, None) == ss.SS_ERR_ARG
+        assert L.ss_mass_log(h, None, 4, None) == ss.SS_ERR_ARG
+        assert L.ss_mass_log(h, buf, 4, ctypes.byref(rows)) == ss.SS_ERR_STATE   # no log bound
+        assert "no mass log" in ss.ss_last_error()
+    finally:
+        ss.ss_destroy_grid(h)

@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from tests._common import (COEF, TOL, as_input, assert_parity, oracle_run, rel_l2, run_gpu, say,
+from tests._common import (COEF, TOL, as_input, assert_parity, need_gpu, oracle_run, rel_l2, run_gpu, say,
                            synth_fields)
 
 pytestmark = pytest.mark.gpu
@@ -168,3 +168,22 @@ def test_step_arrangements_are_bitwise_identical(n, model, dtype):
     with pytest.raises(specstep.SpecStepError):
         specstep.ss_set_step_arrangement(specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model],
                                                        dt=0.05).h, 3)
+
+
+def test_mass_log_host_copy():
+    """ss_mass_log copies the logged rows to the host: the steps up to the
+    bound capacity, at most `max` of them, equal to the device log."""
+    torch, specstep = need_gpu()
+    n, dx = (64, 64), (1.0, 1.0)
+    f0 = synth_fields("cahn_hilliard", n, dx, 66)
+    g = specstep.Grid(n, dx, dtype="f64", model="cahn_hilliard", coef=COEF["cahn_hilliard"], dt=0.1)
+    g.set_field(0, torch.from_numpy(f0[0]).to("cuda:0"))
+    g.enable_mass_log(30)
+    g.step(40)
+    dev = g.mass_log()
+    host = specstep.ss_mass_log(g.h, 100, 1)
+    assert host.shape == (30, 1) and np.array_equal(host, dev)
+    assert np.array_equal(specstep.ss_mass_log(g.h, 10, 1), dev[:10])
+    assert specstep.ss_mass_log(g.h, 0, 1).shape == (0, 1)
+    assert abs(float(host[-1, 0]) - float(np.mean(f0[0]))) <= 1e-15
+    g.close()
