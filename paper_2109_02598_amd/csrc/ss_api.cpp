@@ -1210,7 +1210,7 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     const int esz = esz_of(g);
     const int nx = (int)g->n[0], ny = (int)g->n[1];
     const int R = batch_x_rows(g, threads_x);
-    const int L = threads / (ny / 8);
+    const int L = threads / (ny / ss::k_pts(esz, ny));
     if (R < 2) return false;
     if (L < 1 || !ss::k_tile_ok(esz, ny, nx / 2, false, L)) return false;
     ss::BatchMember m;

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SS_KWA
     switch (b.m[i].ny) {
 #define SS_CASE(n)                  \
   case n:                           \
-    kpass_body<T, n, true>(a, bx, 0, lds); \
+    kpass_body<T, n, true, 0, k_pts((int)sizeof(C<T>), n)>(a, bx, 0, lds); \
     break;
       SS_BATCH_SIZES(SS_CASE)
 #undef SS_CASE
@@ -195,7 +195,7 @@ batch_single(BatchArgs b, BatchSync y) {
     switch (b.m[i].ny) {
 #define SS_CASE(n)                         \
   case n:                                  \
-    kpass_body<T, n, true>(a, bx, 0, lds); \
+    kpass_body<T, n, true, 0, k_pts((int)sizeof(C<T>), n)>(a, bx, 0, lds); \
     break;
       SS_BATCH_SIZES(SS_CASE)
 #undef SS_CASE
@@ -276,7 +276,7 @@ batch_coop(BatchArgs b, BatchSync y) {
       switch (b.m[i].ny) {
 #define SS_CASE(n)                                  \
   case n:                                           \
-    kpass_body<T, n, true>(a, bx, 0, lds, tid);     \
+    kpass_body<T, n, true, 0, k_pts((int)sizeof(C<T>), n)>(a, bx, 0, lds, tid);     \
     break;
         SS_BATCH_SIZES(SS_CASE)
 #undef SS_CASE

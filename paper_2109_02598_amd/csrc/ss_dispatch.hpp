@@ -86,12 +86,12 @@ inline int y_tile_default(int esz, int ny, int64_t nz) {
 
 // k-space pass: `lines` lines per block (even in 3D: mirror pairs)
 inline bool k_tile_ok(int esz, int nl, int64_t nlines, bool three_d, int lines) {
-  const int S = nl / 8;
+  const int S = nl / k_pts(esz, nl);   // the stepping form's threads per line (>= nl / 8)
   return is_pow2(lines) && lines <= nlines && nlines % lines == 0 && lines * S <= k_max_threads() &&
          (!three_d || lines >= 2) && k_lds(esz, nl, lines) <= LDS_BUDGET;
 }
 inline int k_tile_default(int esz, int nl, int64_t nlines, bool three_d) {
-  const int S = nl / 8;
+  const int S = nl / k_pts(esz, nl);
   int l = 256 / S > 1 ? 256 / S : 1;
   if (three_d && l < 2) l = 2;
   while (l > 1 && !k_tile_ok(esz, nl, nlines, three_d, l)) l /= 2;

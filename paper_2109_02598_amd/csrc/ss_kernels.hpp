@@ -99,8 +99,12 @@ constexpr int k_nw(int nl, int p = 8) {
 }
 // points per thread of the stepping-form k-space pass.  Eight: with 16 the
 // FP64 pass spills even at 256 VGPRs, and the FP32 pass drops to two waves
-// per SIMD and ran 6% slower at 2048 points.
-constexpr int k_pts(int, int) { return 8; }
+// per SIMD and ran 6% slower at 2048 points.  Four on lines of up to 512
+// points, where a step has too few lines to fill the GPU and a line's
+// serial chain of loads and transform stages sets the time (Allen-Cahn
+// 128^2 FP64 16.2 -> 13.7 us per step, 256^2 16.8 -> 13.3, 512^2 18.4 ->
+// 16.5; PFC 256^3, whose lines are 256 points long but many, unchanged).
+constexpr int k_pts(int, int nl) { return nl <= 512 ? 4 : 8; }
 // FP64 k-space blocks keep the twiddle bases of the stepping-form pass in
 // LDS after the line regions
 // (sized for 8 points per thread, the three-transform form's, or the
@@ -184,13 +188,46 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int remap) {
 // elements tid + q*nthr, so a wave reads R consecutive rows of consecutive
 // kx.  When nthr >= R the thread's row r = tid mod R is fixed: its global
 // index is one row offset plus kx*B (B = 2^lb row block) and kx advances by
-// nthr/R per element.  Eight loads are issued before their LDS writes; the
-// arrays are walked one after the other so that each pointer is chosen at
-// compile time.  Elements per thread and array: H*R/nthr, a multiple of 8
-// for the x-pass launch shapes (nthr = G*NX/P with G dividing R/2).
+// nthr/R per element.  Eight loads (four when a thread's share is not a
+// multiple of eight) are issued before their LDS writes; the arrays are
+// walked one after the other so that each pointer is chosen at compile
+// time.  Elements per thread and array: H*R/nthr = R*P/(2*G), a multiple
+// of 4 for the x-pass launch shapes (nthr = G*NX/P with G dividing R/2, P
+// at least 4).
 template <int H>
 __device__ __forceinline__ int64_t xstage_row(int64_t s, int lb) {
   return (((s >> lb) * H) << lb) + (s & ((int64_t(1) << lb) - 1));
+}
+
+// QB loads in flight before their LDS writes; per (a thread's elements of
+// the tile) is a multiple of QB.
+template <typename T, int QB>
+__device__ __forceinline__ void xstage_in_run(C<T>* lrow, const C<T>* g, int per, int k0, int kstep, int lb) {
+  for (int c = 0; c < per; c += QB, k0 += QB * kstep) {
+    T vr[QB], vi[QB];   // scalar arrays: promoted to registers
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const C<T> v = g[(int64_t)(k0 + q * kstep) << lb];
+      vr[q] = v.x;
+      vi[q] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) lrow[k0 + q * kstep] = mk<T>(vr[q], vi[q]);
+  }
+}
+template <typename T, int QB>
+__device__ __forceinline__ void xstage_out_run(C<T>* g, const C<T>* lrow, int per, int k0, int kstep, int lb) {
+  for (int c = 0; c < per; c += QB, k0 += QB * kstep) {
+    T vr[QB], vi[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const C<T> v = lrow[k0 + q * kstep];
+      vr[q] = v.x;
+      vi[q] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) g[(int64_t)(k0 + q * kstep) << lb] = mk<T>(vr[q], vi[q]);
+  }
 }
 
 template <typename T, int H, int NS, int NR, int F0, int REG, int HB>
@@ -206,17 +243,8 @@ __device__ __forceinline__ void xstage_in(C<T>* lds, const C<T>* const (&src)[NS
     for (int f = 0; f < NS; ++f) {
       const C<T>* g = src[f] + row;
       C<T>* lrow = lds + ((r >> 1) * NR + F0 + f) * REG + (r & 1) * HB;
-      for (int c = 0, k0 = tid >> lr; c < per; c += 8, k0 += 8 * kstep) {
-        T vr[8], vi[8];   // scalar arrays: promoted to registers
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const C<T> v = g[(int64_t)(k0 + q * kstep) << lb];
-          vr[q] = v.x;
-          vi[q] = v.y;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) lrow[k0 + q * kstep] = mk<T>(vr[q], vi[q]);
-      }
+      if (per % 8 == 0) xstage_in_run<T, 8>(lrow, g, per, tid >> lr, kstep, lb);
+      else xstage_in_run<T, 4>(lrow, g, per, tid >> lr, kstep, lb);
     }
   } else {
 #pragma unroll
@@ -243,17 +271,8 @@ __device__ __forceinline__ void xstage_out(C<T>* const (&dst)[NS], const C<T>* l
     for (int f = 0; f < NS; ++f) {
       C<T>* g = dst[f] + row;
       const C<T>* lrow = lds + ((r >> 1) * NR + F0 + f) * REG + (r & 1) * HB;
-      for (int c = 0, k0 = tid >> lr; c < per; c += 8, k0 += 8 * kstep) {
-        T vr[8], vi[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const C<T> v = lrow[k0 + q * kstep];
-          vr[q] = v.x;
-          vi[q] = v.y;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) g[(int64_t)(k0 + q * kstep) << lb] = mk<T>(vr[q], vi[q]);
-      }
+      if (per % 8 == 0) xstage_out_run<T, 8>(g, lrow, per, tid >> lr, kstep, lb);
+      else xstage_out_run<T, 4>(g, lrow, per, tid >> lr, kstep, lb);
     }
   } else {
 #pragma unroll
