@@ -1181,8 +1181,9 @@ bool batch_size_ok(int64_t n) { return n >= 64 && n <= 2048 && ss::is_pow2(n); }
 int batch_x_rows(ss_grid g, int tx) {
   const int esz = esz_of(g);
   const int nx = (int)g->n[0], ny = (int)g->n[1];
-  const int R = 2 * tx / (nx / ss::x_pts(esz, nx, 1));
-  if (R < 2 || !ss::x_tile_ok(esz, nx, 1, ny, R) || ss::x_threads(esz, nx, 1, R) != tx) return 0;
+  const bool sp = ss::x_small(esz, nx, 1, ny);
+  const int R = 2 * tx / (nx / ss::x_pts_for(esz, nx, 1, sp));
+  if (R < 2 || !ss::x_tile_ok(esz, nx, 1, ny, R) || ss::x_threads(esz, nx, 1, R, sp) != tx) return 0;
   return R;
 }
 
@@ -1246,6 +1247,7 @@ bool build_batch_table(ss_batch b, int threads, std::vector<ss::BatchMember>& ta
     m.k.lb = g->lb;
     m.nx = nx;
     m.ny = ny;
+    m.xsp = ss::x_small(esz, nx, 1, ny) ? 1 : 0;   // as the plain path's x pass
     m.x_first = x_total;
     m.x_tiles = ny / R;
     m.k_first = k_total;

@@ -42,6 +42,7 @@ struct BatchMember {
   int nx, ny;
   int x_first, x_tiles;   // tiles [x_first, x_first + x_tiles) of the x launch
   int k_first, k_tiles;
+  int xsp;          // x pass at the small grids' 4 points per thread (x_small)
 };
 
 struct BatchArgs {
@@ -65,6 +66,18 @@ __device__ __forceinline__ int batch_find(const BatchMember* __restrict__ m, int
 
 #define SS_BATCH_SIZES(M) M(64) M(128) M(256) M(512) M(1024) M(2048)
 
+// one x tile of a member of N-point rows, with the member's points per thread
+template <typename T, int N>
+__device__ __forceinline__ void batch_x_tile(const BatchMember& m, int64_t blk, C<T>* lds, int tid) {
+  if constexpr (N <= 512) {
+    if (m.xsp) {
+      xpass_body<T, N, 1, XMODE_STEP, NLIN_POLY, false, true>(m.x, blk, lds, tid);
+      return;
+    }
+  }
+  xpass_body<T, N, 1, XMODE_STEP, NLIN_POLY>(m.x, blk, lds, tid);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512) xpass_grouped(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
@@ -72,12 +85,11 @@ __global__ void __launch_bounds__(512) xpass_grouped(BatchArgs b) {
   const int tile = blockIdx.x;
   if (tile < b.x_total) {
     const int i = batch_find(b.m, b.count, tile, false);
-    const XArgs& a = b.m[i].x;   // read from the table as used
     const int64_t blk = tile - b.m[i].x_first;
     switch (b.m[i].nx) {
 #define SS_CASE(n)                                                  \
   case n:                                                           \
-    xpass_body<T, n, 1, XMODE_STEP, NLIN_POLY>(a, blk, lds);        \
+    batch_x_tile<T, n>(b.m[i], blk, lds, threadIdx.x);             \
     break;
       SS_BATCH_SIZES(SS_CASE)
 #undef SS_CASE
@@ -179,12 +191,11 @@ batch_single(BatchArgs b, BatchSync y) {
   const int tile = xside ? (int)r : (int)(r - b.x_total);
   const int i = batch_find(b.m, b.count, tile, !xside);
   if (xside) {
-    const XArgs& a = b.m[i].x;
     const int64_t blk = tile - b.m[i].x_first;
     switch (b.m[i].nx) {
 #define SS_CASE(n)                                           \
   case n:                                                    \
-    xpass_body<T, n, 1, XMODE_STEP, NLIN_POLY>(a, blk, lds); \
+    batch_x_tile<T, n>(b.m[i], blk, lds, threadIdx.x);      \
     break;
       SS_BATCH_SIZES(SS_CASE)
 #undef SS_CASE
@@ -253,12 +264,11 @@ batch_coop(BatchArgs b, BatchSync y) {
       int tid = threadIdx.x;
       asm volatile("" : "+v"(tid));
       const int i = batch_find(b.m, b.count, tile, false);
-      const XArgs& a = b.m[i].x;
-      const int64_t blk = tile - b.m[i].x_first;
+        const int64_t blk = tile - b.m[i].x_first;
       switch (b.m[i].nx) {
 #define SS_CASE(n)                                                \
   case n:                                                         \
-    xpass_body<T, n, 1, XMODE_STEP, NLIN_POLY>(a, blk, lds, tid); \
+    batch_x_tile<T, n>(b.m[i], blk, lds, tid);                    \
     break;
         SS_BATCH_SIZES(SS_CASE)
 #undef SS_CASE

@@ -34,9 +34,9 @@ inline bool x_tile_ok(int esz, int nx, int nf, int64_t nrows, int rows) {
   return is_pow2(rows) && rows >= 2 && rows <= 64 && rows <= nrows && nrows % rows == 0 &&
          x_lds(esz, nx, nf, rows) <= LDS_BUDGET;
 }
-inline int x_threads(int esz, int nx, int nf, int rows) {
-  const int S = nx / x_pts(esz, nx, nf);
-  int G = x_block_threads(esz, nx, nf) / S;
+inline int x_threads(int esz, int nx, int nf, int rows, bool sp = false) {
+  const int S = nx / x_pts_for(esz, nx, nf, sp);
+  int G = x_block_threads(esz, nx, nf, sp) / S;
   if (G > rows / 2) G = rows / 2;
   if (G < 1) G = 1;
   return G * S;
@@ -47,7 +47,7 @@ inline int x_threads(int esz, int nx, int nf, int rows) {
 inline bool x_pp_ok(int esz, int nx, int nf, int64_t nrows, int rows) {
   const int S = nx / x_pts(esz, nx, nf);
   return x_tile_ok(esz, nx, nf, nrows, rows) && (rows / 2) * S <= 512 && (rows / 2) * S >= 64 &&
-         !(esz == 16 && nf == 2) && x_pts(esz, nx, nf) == 8;
+         !(esz == 16 && nf == 2) && x_pts(esz, nx, nf) == 8 && !x_small(esz, nx, nf, nrows);
 }
 inline int x_tile_default(int esz, int nx, int nf, int64_t nrows) {
   // at most 128 contiguous bytes per staged chunk, at most half the LDS
@@ -186,8 +186,12 @@ hipError_t launch_x(XArgs a, hipStream_t s, LaunchEvents ev) {
   const int R = a.rows_per_block;
   if (!x_tile_ok(ESZ, NX, NF, a.rows, R)) return hipErrorInvalidConfiguration;
   const int ntiles = (int)(a.rows / R);
-  const int threads = x_threads(ESZ, NX, NF, R);
+  const bool sp = x_small(ESZ, NX, NF, a.rows);
+  const int threads = x_threads(ESZ, NX, NF, R, sp);
   const uint32_t lds = (uint32_t)x_lds(ESZ, NX, NF, R);
+  if constexpr (NX >= 8 && NX <= 512) {
+    if (sp) return launch_with(xpass_kernel<T, NX, NF, MODE, NLM, true>, dim3(ntiles), dim3(threads), lds, s, ev, a);
+  }
   if constexpr (MODE == XMODE_STEP && !(sizeof(T) == 8 && NF == 2) && XCfg<T, NX, NF>::P == 8) {
     if (a.tiles_per_block > 1 && x_pp_ok(ESZ, NX, NF, a.rows, R)) {
       const int grid = (ntiles + a.tiles_per_block - 1) / a.tiles_per_block;

@@ -127,9 +127,17 @@ constexpr int64_t k_lds(int esz, int nl, int lines) { return (int64_t)lines * (k
 constexpr int x_pts(int esz, int nx, int nf) {
   return (SS_XPTS16 && nx >= 16 && !(esz == 16 && nf == 2)) ? 16 : 8;
 }
+// A small grid's x pass takes 4 points per thread: rows of 8 to 512 points
+// when a launch at the count above would hold fewer than 64K threads (too
+// few waves to hide each one's chain of loads and transform stages).
+// Chosen at run time from the grid (both kernels are built for such rows).
+constexpr bool x_small(int esz, int nx, int nf, int64_t nrows) {
+  return nx >= 8 && nx <= 512 && (nrows / 2) * (nx / x_pts(esz, nx, nf)) < 65536;
+}
+constexpr int x_pts_for(int esz, int nx, int nf, bool sp) { return sp ? 4 : x_pts(esz, nx, nf); }
 // threads per x-pass block: 512, or 1024 for FP32 with 8 points per thread
-constexpr int x_block_threads(int esz, int nx, int nf) {
-  return (esz == 8 && x_pts(esz, nx, nf) == 8) ? 1024 : 512;
+constexpr int x_block_threads(int esz, int nx, int nf, bool sp = false) {
+  return (esz == 8 && x_pts_for(esz, nx, nf, sp) == 8) ? 1024 : 512;
 }
 
 // ---------------------------------------------------------------------------
@@ -162,9 +170,9 @@ struct XArgs {
   NTab tab;                 // NLIN_TABLE: the explicit terms as monomials
 };
 
-template <typename T, int NX, int NF>
+template <typename T, int NX, int NF, bool SP = false>
 struct XCfg {
-  static constexpr int P = x_pts((int)sizeof(C<T>), NX, NF);   // points per thread
+  static constexpr int P = x_pts_for((int)sizeof(C<T>), NX, NF, SP);   // points per thread
   static constexpr int S = NX / P;                  // threads per line
   static constexpr int H = NX / 2;                  // stored kx count
   static constexpr int ESZ = (int)sizeof(C<T>);
@@ -373,9 +381,9 @@ __device__ __forceinline__ void nonlinear_table(C<T> (&c)[NF][PT], const NTab& t
 }
 
 // threads per block of the x pass (launch bound)
-template <typename T, int NX, int NF>
+template <typename T, int NX, int NF, bool SP = false>
 struct XThreads {
-  static constexpr int value = x_block_threads((int)sizeof(C<T>), NX, NF);
+  static constexpr int value = x_block_threads((int)sizeof(C<T>), NX, NF, SP);
 };
 
 // One x-pass tile: rows blk*R .. blk*R+R-1 of the spectral layout.  The
@@ -385,9 +393,10 @@ struct XThreads {
 // tid: the thread's index in the block (a caller that loops over tiles
 // passes a copy the compiler cannot see through, so that nothing derived
 // from it is hoisted out of the loop).
-template <typename T, int NX, int NF, int MODE, int NLM, bool PRELOADED = false>
+// SP: the small grids' 4 points per thread (x_small).
+template <typename T, int NX, int NF, int MODE, int NLM, bool PRELOADED = false, bool SP = false>
 __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* lds, int tid = threadIdx.x) {
-  typedef XCfg<T, NX, NF> K;
+  typedef XCfg<T, NX, NF, SP> K;
   constexpr int S = K::S, H = K::H, HB = K::HB, PT = K::P;
   constexpr int REG = K::reg_for(NF);
 
@@ -526,11 +535,11 @@ __device__ __forceinline__ void xpass_body(const XArgs& a, int64_t blk, C<T>* ld
   }
 }
 
-template <typename T, int NX, int NF, int MODE, int NLM>
-__global__ void __launch_bounds__((XThreads<T, NX, NF>::value)) xpass_kernel(XArgs a) {
+template <typename T, int NX, int NF, int MODE, int NLM, bool SP = false>
+__global__ void __launch_bounds__((XThreads<T, NX, NF, SP>::value)) xpass_kernel(XArgs a) {
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
-  xpass_body<T, NX, NF, MODE, NLM>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap),
-                                   reinterpret_cast<C<T>*>(ss_dyn_lds));
+  xpass_body<T, NX, NF, MODE, NLM, false, SP>(a, xcd_block(blockIdx.x, gridDim.x, a.xcd_remap),
+                                              reinterpret_cast<C<T>*>(ss_dyn_lds));
 }
 
 // Register prefetch of one x-pass tile for the persistent kernel: the

@@ -155,21 +155,32 @@ def test_single_launch_graph_replay_equals_eager(mode):
     bg.close()
 
 
-def test_single_launch_refused_without_one_block_size():
+def test_single_launch_forms_take_small_members_and_refuse_bad_modes():
+    """Members of 64-point rows share the block size of the others (their x
+    pass takes 4 points per thread), so both single-launch forms accept a
+    mixed batch and give the plain path's bits; unknown forms are refused."""
     torch, specstep = need_gpu()
     stream = torch.cuda.Stream()
     ws = make_members([(64, 64), (256, 128)], "f32", seed0=4500)
-    gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
-    b = specstep.Batch(gs, autotune=False)
+    plain = grids_for(specstep, ws, "f32", stream.cuda_stream)
+    for g in plain:
+        g.step(6)
+    want = [g.get_field(0).cpu().numpy() for g in plain]
     for mode in (1, 2):
-        with pytest.raises(specstep.SpecStepError) as e:
-            b.set_mode(mode)
-        assert e.value.code == specstep.SS_ERR_UNSUPPORTED
-        assert b.mode() == 0
-    with pytest.raises(specstep.SpecStepError) as e:
-        b.set_mode(3)
-    assert e.value.code == specstep.SS_ERR_ARG
-    b.close()
+        gs = grids_for(specstep, ws, "f32", stream.cuda_stream)
+        b = specstep.Batch(gs, autotune=False)
+        b.set_mode(mode)
+        assert b.mode() == mode
+        b.step(6)
+        b.check()
+        for g, w in zip(gs, want):
+            assert same_as_plain(g.get_field(0).cpu().numpy(), w), mode
+        for bad in (3, -1):
+            with pytest.raises(specstep.SpecStepError) as e:
+                b.set_mode(bad)
+            assert e.value.code == specstep.SS_ERR_ARG
+        assert b.mode() == mode
+        b.close()
 
 
 @pytest.mark.parametrize("mode", [1, 2])
