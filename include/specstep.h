@@ -241,7 +241,13 @@ ss_status ss_get_field(ss_grid g, int field, void* dst, int dst_on_device);
  * (Eq. 8): per step the nonlinear terms of all fields are evaluated from
  * the current fields (Sec. 2.2.4, equation() before step()), transformed,
  * and combined with the transformed fields through A and B N_i.
- * Asynchronous on the grid's stream.
+ * Asynchronous on the grid's stream; it enqueues kernels only (no
+ * memset, copy or synchronisation), so a caller may capture it into a HIP
+ * graph on that stream and replay the graph, each replay taking the same
+ * steps with the same bits, provided the carried spectrum is current when
+ * captured (a step taken since the last ss_set_field), the captured step
+ * count is even (the tuned arrangement may swap two arrays each step) and
+ * no mass log is bound (its row index is fixed in the graph).
  * Errors: SS_ERR_STATE (model, workspace or a field missing), SS_ERR_ARG,
  * SS_ERR_DEVICE. */
 ss_status ss_step_n(ss_grid g, int64_t nsteps);
