@@ -81,9 +81,14 @@ __device__ __forceinline__ AdjCoef<T> adj_coeffs(const KAdjField& f, double k2, 
 template <typename T>
 __device__ __forceinline__ T re_conj_mul(C<T> a, C<T> b) { return a.x * b.x + a.y * b.y; }
 
+// Points per thread of the reverse sweep's transforms along an axis of n
+// points: four up to 512 (twice the waves in flight, as the forward passes
+// take on small grids), eight above.
+constexpr int adj_pts(int n) { return n <= 512 ? 4 : 8; }
+
 template <typename T, int NL>
 __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T>* lds, double* red) {
-  constexpr int S = NL / 8;
+  constexpr int PT = adj_pts(NL), S = NL / PT;
   constexpr int REG = k_reg((int)sizeof(C<T>), NL);
   const int tid = threadIdx.x;
   const int ls = tid / S, t = tid - ls * S;
@@ -98,11 +103,11 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
   C<T>* xl = lds + (0 * L + ls) * REG;
   C<T>* xq = lds + (1 * L + ls) * REG;
   C<T>* xg = lds + (2 * L + ls) * REG;
-  const Twiddles<T, NL> tw = make_twiddles<T, NL>(t);
+  const Twiddles<T, NL, PT> tw = make_twiddles<T, NL, PT>(t);
 
-  C<T> cl[1][8], cq[1][8], cg[1][8];
+  C<T> cl[1][PT], cq[1][PT], cg[1][PT];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < PT; ++e) {
     const int64_t ix = sidx(kxi, t + e * S, hx, a.lb);
     cl[0][e] = pl[ix];
     cq[0][e] = pq[ix];
@@ -110,9 +115,9 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
   }
   {
     C<T>* x1[1] = {xl};
-    fft_lines<T, NL, -1, 1>(cl, x1, t, tw);
-    fft_lines<T, NL, -1, 1>(cq, x1, t, tw);
-    fft_lines<T, NL, -1, 1>(cg, x1, t, tw);
+    fft_lines<T, NL, -1, 1, PT>(cl, x1, t, tw);
+    fft_lines<T, NL, -1, 1, PT>(cq, x1, t, tw);
+    fft_lines<T, NL, -1, 1, PT>(cg, x1, t, tw);
   }
   const bool packed_block = bx == 0;   // line kx = 0 holds kx = 0 and Nyquist
   const bool packed = kxi == 0;
@@ -121,10 +126,10 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
   const T nxd = (T)a.nxd;
   const T as = (T)a.a_scale;
   double s0 = 0.0, s1 = 0.0, dcs = 0.0;
-  C<T> oa[1][8], om[1][8];
+  C<T> oa[1][PT], om[1][PT];
   if (packed_block) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < PT; ++e) {
       xl[pidx<T>(t + e * S)] = cl[0][e];
       xq[pidx<T>(t + e * S)] = cq[0][e];
       xg[pidx<T>(t + e * S)] = cg[0][e];
@@ -132,7 +137,7 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
     __syncthreads();
   }
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < PT; ++e) {
     const int p = t + e * S;
     const int m = p <= NL / 2 ? p : p - NL;
     const double ky = (double)m * a.sy;
@@ -171,13 +176,13 @@ __device__ __forceinline__ void kadj_body(const KAdjArgs& a, int bx, int fi, C<T
   if (packed_block) __syncthreads();
   {
     C<T>* x1[1] = {xl};
-    fft_lines<T, NL, +1, 1>(oa, x1, t, tw);
-    fft_lines<T, NL, +1, 1>(om, x1, t, tw);
+    fft_lines<T, NL, +1, 1, PT>(oa, x1, t, tw);
+    fft_lines<T, NL, +1, 1, PT>(om, x1, t, tw);
   }
   C<T>* pa = (C<T>*)F.out_a;
   C<T>* pm = (C<T>*)F.out_m;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < PT; ++e) {
     const int64_t ix = sidx(kxi, t + e * S, hx, a.lb);
     pa[ix] = oa[0][e];
     pm[ix] = om[0][e];
@@ -230,19 +235,19 @@ constexpr int64_t xadj_lds(int esz, int nx, int rows) { return (int64_t)(rows / 
 
 template <typename T, int NX>
 __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
-  constexpr int S = NX / 8, H = NX / 2, HB = H + 1;
+  constexpr int PT = adj_pts(NX), S = NX / PT, H = NX / 2, HB = H + 1;
   constexpr int NA = 6;
   constexpr int REG = x_reg((int)sizeof(C<T>), NX, NA);
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
   C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
   const int R = a.rows_per_block;
-  const int P = R >> 1;
+  const int NP = R >> 1;                      // row pairs of the tile
   const int G = (int)blockDim.x / S;
   const int tid = threadIdx.x;
   const int g = tid / S, t = tid - g * S;
   const int64_t s0 = (int64_t)blockIdx.x * R;
   const int64_t rows = a.rows;
-  const Twiddles<T, NX> tw = make_twiddles<T, NX>(t);
+  const Twiddles<T, NX, PT> tw = make_twiddles<T, NX, PT>(t);
 
   {
     const C<T>* src[NA] = {(const C<T>*)a.m[0], (const C<T>*)a.m[1], (const C<T>*)a.q[0],
@@ -250,16 +255,16 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
     xstage_in<T, H, NA, NA, 0, REG, HB>(lds, src, s0, R, a.lb, tid, (int)blockDim.x);
   }
   __syncthreads();
-  for (int it = 0; it < P / G; ++it) {
+  for (int it = 0; it < NP / G; ++it) {
     const int pr = it * G + g;
     C<T>* x[NA];
 #pragma unroll
     for (int f = 0; f < NA; ++f) x[f] = lds + (pr * NA + f) * REG;
-    C<T> c[4][8];
+    C<T> c[4][PT];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < PT; ++e) {
         const int k = t + e * S;
         C<T> z;
         if (k == 0) {
@@ -281,12 +286,12 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
     __syncthreads();
     {
       C<T>* const xi[4] = {x[0], x[1], x[2], x[3]};
-      fft_lines<T, NX, +1, 4>(c, xi, t, tw);
+      fft_lines<T, NX, +1, 4, PT>(c, xi, t, tw);
     }
     // pointwise transpose of the Jacobian of (g_u, g_v) = (F - u v^2, u v^2)
-    C<T> w[2][8];
+    C<T> w[2][PT];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < PT; ++e) {
       const C<T> mu = c[0][e], mv = c[1][e], u = c[2][e], v = c[3][e];
       const T dx = mv.x - mu.x, dy = mv.y - mu.y;
       w[0][e] = mk<T>(v.x * v.x * dx, v.y * v.y * dy);
@@ -294,22 +299,22 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
     }
     {
       C<T>* const xo[2] = {x[0], x[1]};
-      fft_lines<T, NX, -1, 2>(w, xo, t, tw);
+      fft_lines<T, NX, -1, 2, PT>(w, xo, t, tw);
     }
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) x[f][pidx<T>(t + e * S)] = w[f][e];
+      for (int e = 0; e < PT; ++e) x[f][pidx<T>(t + e * S)] = w[f][e];
     }
     __syncthreads();
     const T sc = (T)1 / (T)NX;
     const T half = (T)0.5 * sc;
-    C<T> fa[2][4], fb[2][4];
+    C<T> fa[2][PT / 2], fb[2][PT / 2];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k = t + e * S;
+      for (int e = 0; e < PT / 2; ++e) {
+        const int k = t + e * S;               // 0 .. H-1
         C<T> wk = x[f][pidx<T>(k)];
         C<T> ra, rb;
         if (k == 0) {
@@ -330,7 +335,7 @@ __global__ void __launch_bounds__(512) xadj_kernel(XAdjArgs a) {
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < PT / 2; ++e) {
         const int k = t + e * S;
         x[4 + f][k] = fa[f][e];
         x[4 + f][HB + k] = fb[f][e];

@@ -126,14 +126,15 @@ inline int xadj_tile(int esz, int nx, int64_t rows) {
   for (int r = 2; r <= 64; r *= 2) {
     if (r > rows || rows % r) break;
     if (xadj_lds(esz, nx, r) > (int64_t)LDS_BUDGET * 7 / 10) break;
-    if ((r / 2) * (nx / 8) > 512) break;
+    if ((r / 2) * (nx / adj_pts(nx)) > 512) break;
     best = r;
   }
   if (!best && xadj_lds(esz, nx, 2) <= LDS_BUDGET) best = 2;
   return best;
 }
 inline int kadj_tile(int nl, int64_t nlines) {
-  int l = 256 / (nl / 8) > 1 ? 256 / (nl / 8) : 1;
+  const int S = nl / adj_pts(nl);
+  int l = 256 / S > 1 ? 256 / S : 1;
   while (l > nlines) l /= 2;
   return l;
 }
@@ -506,7 +507,7 @@ template <typename T>
 hipError_t run_kadj(int nl, KAdjArgs a, hipStream_t s) {
   constexpr int ESZ = (int)sizeof(C<T>);
   const int L = a.lines_per_block;
-  const int threads = L * (nl / 8);
+  const int threads = L * (nl / adj_pts(nl));
   if (L < 1 || a.nlines % L || threads > 512) return hipErrorInvalidConfiguration;
   const int64_t lds = kadj_lds(ESZ, nl, L, threads);
   if (lds > LDS_BUDGET) return hipErrorInvalidConfiguration;
@@ -528,10 +529,11 @@ hipError_t run_xadj(int nx, XAdjArgs a, hipStream_t s) {
   if (R < 2 || !is_pow2(R) || a.rows % R) return hipErrorInvalidConfiguration;
   const int64_t lds = xadj_lds(ESZ, nx, R);
   if (lds > LDS_BUDGET) return hipErrorInvalidConfiguration;
-  int G = 512 / (nx / 8);
+  const int S = nx / adj_pts(nx);
+  int G = 512 / S;
   if (G > R / 2) G = R / 2;
   if (G < 1) G = 1;
-  dim3 grid((unsigned)(a.rows / R)), block((unsigned)(G * (nx / 8)));
+  dim3 grid((unsigned)(a.rows / R)), block((unsigned)(G * S));
   switch (nx) {
 #define SS_CASE(n) \
   case n:          \
