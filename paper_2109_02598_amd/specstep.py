@@ -506,13 +506,19 @@ class Grid:
         if self.stream != cur.cuda_stream:
             cur.synchronize()
 
+    def _grid_stream_done(self):
+        """Results the library wrote on the grid's stream are about to be
+        used on torch's current stream: when the two differ, wait for the
+        device first."""
+        if self.stream != self.torch.cuda.current_stream(self.device).cuda_stream:
+            self.torch.cuda.synchronize(self.device)
+
     def get_field(self, field, out=None):
         torch = self.torch
         if out is None:
             out = torch.empty(self.shape, dtype=self.tdtype, device=self.device)
         ss_get_field(self.h, field, out.data_ptr(), True)
-        if self.stream != torch.cuda.current_stream(self.device).cuda_stream:
-            torch.cuda.synchronize(self.device)
+        self._grid_stream_done()
         return out
 
     def get_field_host(self, field):
@@ -566,6 +572,7 @@ class Grid:
     def enable_mass_log(self, capacity):
         self.mass_buf = self.torch.zeros(capacity * self.nfields, dtype=self.torch.float64,
                                          device=self.device)
+        self._after_current_stream()   # the zeros land before the grid's steps write the log
         ss_bind_mass_log(self.h, self.mass_buf.data_ptr(), capacity)
 
     def structure_factor(self, field=0):
@@ -575,9 +582,11 @@ class Grid:
         s = self.torch.empty(nb, dtype=self.torch.float64, device=self.device)
         n = self.torch.empty(nb, dtype=self.torch.int64, device=self.device)
         ss_structure_factor(self.h, field, s.data_ptr(), n.data_ptr(), nb)
+        self._grid_stream_done()
         return s, n
 
     def mass_log(self):
+        self._grid_stream_done()
         cnt = min(ss_mass_log_count(self.h), self.mass_buf.numel() // self.nfields)
         return self.mass_buf[: cnt * self.nfields].view(cnt, self.nfields).cpu().numpy()
 
