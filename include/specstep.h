@@ -224,7 +224,8 @@ ss_status ss_workspace_size(ss_grid g, size_t* bytes);
 
 /* Bind caller-owned device memory of at least ss_workspace_size bytes,
  * 256-byte aligned.  The library keeps the pointer; the caller keeps it
- * alive until the handle is destroyed or rebound.
+ * alive until the handle is destroyed or rebound and the work already
+ * enqueued on the grid's stream has finished (neither waits for it).
  * Errors: SS_ERR_STATE (no model), SS_ERR_ARG (null, too small, misaligned). */
 ss_status ss_bind_workspace(ss_grid g, void* device_ptr, size_t bytes);
 
@@ -483,6 +484,9 @@ ss_status ss_batch_launch(ss_batch b);
  * member), info[1], info[2] = blocks of the grouped x and k launches. */
 ss_status ss_batch_info(ss_batch b, int info[3]);
 
+/* Wait for the batch's stream (a captured run may still be executing),
+ * then free the handle and its graph (not the caller's memory or the
+ * member grids).  NULL is a no-op. */
 ss_status ss_batch_destroy(ss_batch b);
 
 /* Bind a device buffer of capacity * nfields doubles for the per-step
@@ -531,10 +535,13 @@ ss_status ss_mass_log(ss_grid g, double* dst_host, int64_t max, int64_t* rows);
 ss_status ss_structure_factor_nbins(ss_grid g, int* nbins);
 ss_status ss_structure_factor(ss_grid g, int field, double* s_out, int64_t* n_out, int nbins);
 
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on.  Work enqueued earlier on the
+ * old stream is not waited for: the caller orders the two streams. */
 ss_status ss_set_stream(ss_grid g, void* stream);
 
-/* Free the handle (not the caller's device memory).  NULL is a no-op. */
+/* Free the handle (not the caller's device memory).  Does not wait for
+ * work enqueued on the grid's stream, which may still use the caller's
+ * buffers.  NULL is a no-op. */
 ss_status ss_destroy_grid(ss_grid g);
 
 /* Message of the last failed call on this thread ("" if none). */

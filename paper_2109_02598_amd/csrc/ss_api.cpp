@@ -2614,6 +2614,9 @@ ss_status ss_batch_info(ss_batch b, int info[3]) {
 
 ss_status ss_batch_destroy(ss_batch b) {
   if (!b) return SS_OK;
+  // a launched graph may still be running: its nodes read the batch's
+  // tables and the caller's buffers
+  (void)hipStreamSynchronize(b->stream);
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
   delete b;

@@ -462,6 +462,7 @@ class Grid:
         return tuple(reversed(self.n))
 
     def set_model(self, model, coef, dt):
+        self._grid_stream_done()   # a replaced workspace may still be in use there
         mid = MODELS[model] if isinstance(model, str) else int(model)
         ss_set_model(self.h, mid, coef, dt)
         self.dt = float(dt)
@@ -473,6 +474,7 @@ class Grid:
             ss_bind_workspace(self.h, self.workspace.data_ptr(), nbytes)
 
     def set_equations(self, equations, coefs, dt, scheme="etd1"):
+        self._grid_stream_done()
         nf = len(ss_split_equations(equations, coefs))
         ss_set_equations(self.h, equations, coefs, dt, scheme)
         self.dt = float(dt)
@@ -548,6 +550,7 @@ class Grid:
     def bind_adjoint(self, nsteps, K):
         """Allocate (torch) and bind the reverse-mode workspace."""
         nbytes = ss_adjoint_workspace_size(self.h, nsteps, K)
+        self._grid_stream_done()
         self.adj_workspace = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
         ss_bind_adjoint_workspace(self.h, self.adj_workspace.data_ptr(), nbytes, nsteps, K)
         self.adj_cfg = (int(nsteps), int(K))
@@ -570,6 +573,7 @@ class Grid:
         return ss_check_finite(self.h)
 
     def enable_mass_log(self, capacity):
+        self._grid_stream_done()
         self.mass_buf = self.torch.zeros(capacity * self.nfields, dtype=self.torch.float64,
                                          device=self.device)
         self._after_current_stream()   # the zeros land before the grid's steps write the log
@@ -592,6 +596,9 @@ class Grid:
 
     def close(self):
         if getattr(self, "h", None):
+            # the workspaces are freed with this object: the grid's
+            # stream must be done with them
+            self._grid_stream_done()
             ss_destroy_grid(self.h)
             self.h = None
 
