@@ -515,6 +515,16 @@ class Grid:
         if self.stream != self.torch.cuda.current_stream(self.device).cuda_stream:
             self.torch.cuda.synchronize(self.device)
 
+    def set_stream(self, stream=None):
+        """Later calls enqueue on ``stream`` (a raw HIP stream handle; None:
+        torch's current stream).  Work already enqueued anywhere on the
+        device is waited for first, so the move needs no other ordering."""
+        if stream is None:
+            stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        self.torch.cuda.synchronize(self.device)
+        ss_set_stream(self.h, stream)
+        self.stream = stream
+
     def get_field(self, field, out=None):
         torch = self.torch
         if out is None:

@@ -65,3 +65,26 @@ def test_structure_factor_on_a_side_stream():
     g1.close()
     assert np.array_equal(n0, n1)
     assert np.allclose(s1, s0, rtol=1e-13, atol=0.0)
+
+
+def test_moving_a_grid_between_streams():
+    """ss_set_stream between calls: the run continues with the bits of a
+    run on one stream."""
+    torch, specstep = need_gpu()
+    case = ("gray_scott", (128, 128), 1.0, "f64")
+    ref = make(specstep, case, None, 95)
+    ref.step(30)
+    want, wlog = read(ref)
+    ref.close()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    g = make(specstep, case, s1.cuda_stream, 95)
+    g.step(10)
+    g.set_stream(s2.cuda_stream)
+    g.step(10)
+    g.set_stream()
+    g.step(10)
+    got, log = read(g)
+    g.close()
+    assert np.array_equal(log, wlog)
+    for a, b in zip(got, want):
+        assert np.array_equal(a, b)
