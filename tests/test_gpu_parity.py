@@ -57,6 +57,15 @@ def test_parity_3d(model, n, dtype):
     case(model, n, dtype)
 
 
+# 3D grids with one long axis: x rows and y lines of 1024 and 2048 points,
+# z lines of 1024 (the longest z the library takes)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(2048, 16, 8), (16, 2048, 8), (8, 16, 1024), (1024, 8, 16), (8, 1024, 16)])
+@pytest.mark.parametrize("model", ["cahn_hilliard", "gray_scott"])
+def test_parity_3d_long_axes(model, n, dtype):
+    case(model, n, dtype)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n", [(8, 8), (64, 32), (2048, 8), (16, 8, 32)])
 def test_set_get_round_trip(n, dtype):
