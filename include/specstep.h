@@ -100,7 +100,8 @@ ss_status ss_set_model(ss_grid g, ss_model model, const double* coef, int ncoef,
  * with numbers (decimal, optional exponent), the coefficient names of
  * names[] (values[] holds their values), field names, + - * /, '^' or '**'
  * with an integer literal exponent 0..16, parentheses, lap(e) and bilap(e)
- * = lap(lap(e)).  Division only by constant expressions.  Example
+ * = lap(lap(e)); parentheses, lap/bilap and unary signs nested at most
+ * 200 deep.  Division only by constant expressions.  Example
  * (Cahn-Hilliard):  "psi' = M*lap(c2*psi^3 - c1*psi - kappa*lap(psi))".
  *
  * The right-hand side is expanded into terms c lap^p (monomial in the

@@ -174,10 +174,12 @@ class Reader {
   Poly signed_factor() {
     if (at_op("-")) {
       next();
+      Nest nest(*this);
       return mul(Poly::num(-1.0), signed_factor());
     }
     if (at_op("+")) {
       next();
+      Nest nest(*this);
       return signed_factor();
     }
     return power();
@@ -208,6 +210,7 @@ class Reader {
       next();
       if (n == "lap" || n == "bilap") {
         expect_op("(");
+        Nest nest(*this);
         Poly in = sum();
         expect_op(")");
         return lap(in, n == "lap" ? 1 : 2);
@@ -226,6 +229,7 @@ class Reader {
     }
     if (at_op("(")) {
       next();
+      Nest nest(*this);
       Poly r = sum();
       expect_op(")");
       return r;
@@ -285,6 +289,17 @@ class Reader {
     fail(1, "unexpected character '%c'", ch);
   }
 
+  // Parentheses, lap(...) and unary signs recurse: their nesting is
+  // bounded so that no text can exhaust the caller's stack.
+  static constexpr int kMaxDepth = 200;
+  struct Nest {
+    Reader& r;
+    explicit Nest(Reader& rd) : r(rd) {
+      if (++r.depth_ > kMaxDepth) fail(1, "expression nested deeper than %d levels", kMaxDepth);
+    }
+    ~Nest() { --r.depth_; }
+  };
+
   const std::string& s_;
   const std::vector<std::string>& fields_;
   const std::vector<std::string>& names_;
@@ -293,6 +308,7 @@ class Reader {
   Tok kind_ = T_END;
   std::string tok_;
   double num_ = 0;
+  int depth_ = 0;
 };
 
 bool is_ident(const char* s) {
