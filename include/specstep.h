@@ -415,9 +415,11 @@ ss_status ss_adjoint_n(ss_grid g, const void* const dJ_dqT[], void* const dJ_dq0
 typedef struct ss_batch_s* ss_batch;
 
 /* Create a batch over count >= 1 grids (copied handle list); the stream is
- * that of the first grid.  Errors: SS_ERR_ARG (null, mixed dtype or
- * stream), SS_ERR_UNSUPPORTED (3D, two-field model, size), SS_ERR_STATE
- * (member without model or workspace). */
+ * that of the first grid.  Members are stepped in parallel, so no two may
+ * share workspace memory (a grid listed twice included).  Errors:
+ * SS_ERR_ARG (null, mixed dtype or stream, shared workspace memory),
+ * SS_ERR_UNSUPPORTED (3D, two-field model, size), SS_ERR_STATE (member
+ * without model or workspace). */
 ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out);
 
 /* Device bytes the batch needs for its member tables and the counters of

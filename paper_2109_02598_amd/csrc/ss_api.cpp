@@ -2403,6 +2403,21 @@ ss_status ss_batch_create(const ss_grid* grids, int count, ss_batch* out) {
     if (g->dtype != grids[0]->dtype) return fail(SS_ERR_ARG, "ss_batch_create: mixed dtypes");
     if (g->stream != grids[0]->stream) return fail(SS_ERR_ARG, "ss_batch_create: mixed streams");
   }
+  // Members step in parallel within a launch: none may share state with
+  // another (a grid listed twice, or two grids bound to overlapping
+  // workspaces, would be written by two work items at once).
+  {
+    std::vector<std::pair<uintptr_t, uintptr_t>> used((size_t)count);
+    for (int i = 0; i < count; ++i) {
+      size_t need = 0;
+      SS_TRY(ss_workspace_size(grids[i], &need));
+      used[(size_t)i] = {(uintptr_t)grids[i]->ws, (uintptr_t)grids[i]->ws + need};
+    }
+    std::sort(used.begin(), used.end());
+    for (size_t i = 1; i < used.size(); ++i)
+      if (used[i].first < used[i - 1].second)
+        return fail(SS_ERR_ARG, "ss_batch_create: two members share workspace memory (a grid listed twice?)");
+  }
   ss_batch b = new (std::nothrow) ss_batch_s();
   if (!b) return fail(SS_ERR_ARG, "ss_batch_create: out of host memory");
   b->grids.assign(grids, grids + count);

@@ -101,10 +101,10 @@ def test_batch_validation(L):
     fake = 1 << 40
     hs = []
     try:
-        for n, model in [((64, 128), 2), ((256, 256), 2), ((32, 64), 2)]:
+        for i, (n, model) in enumerate([((64, 128), 2), ((256, 256), 2), ((32, 64), 2)]):
             h = ss.ss_create_grid(n, (1, 1), ss.SS_F32)
             ss.ss_set_model(h, model, (1, 1, 1, 1), 0.1)
-            ss.ss_bind_workspace(h, fake, ss.ss_workspace_size(h))
+            ss.ss_bind_workspace(h, fake + (i << 32), ss.ss_workspace_size(h))
             hs.append(h)
         b = ss.ss_batch_create(hs[:2])
         assert ss.ss_batch_workspace_size(b) >= 2 * 2 * 100
@@ -113,14 +113,21 @@ def test_batch_validation(L):
         assert code_of(ss.ss_batch_launch, b) == ss.SS_ERR_STATE
         ss.ss_batch_destroy(b)
         assert code_of(ss.ss_batch_create, hs) == ss.SS_ERR_UNSUPPORTED  # 32 < 64
+        # members share no state: a repeated grid, overlapping workspaces
+        assert code_of(ss.ss_batch_create, [hs[0], hs[1], hs[0]]) == ss.SS_ERR_ARG
+        assert "share workspace" in ss.ss_last_error()
+        ss.ss_bind_workspace(hs[1], fake + ss.ss_workspace_size(hs[0]) - 256, ss.ss_workspace_size(hs[1]))
+        assert code_of(ss.ss_batch_create, hs[:2]) == ss.SS_ERR_ARG
+        ss.ss_bind_workspace(hs[1], fake + ss.ss_workspace_size(hs[0]), ss.ss_workspace_size(hs[1]))
+        ss.ss_batch_destroy(ss.ss_batch_create(hs[:2]))                  # adjacent: fine
         h64 = ss.ss_create_grid((64, 64), (1, 1), ss.SS_F64)
         ss.ss_set_model(h64, 2, (1, 1, 1, 1), 0.1)
-        ss.ss_bind_workspace(h64, fake, ss.ss_workspace_size(h64))
+        ss.ss_bind_workspace(h64, fake + (8 << 32), ss.ss_workspace_size(h64))
         hs.append(h64)
         assert code_of(ss.ss_batch_create, [hs[0], h64]) == ss.SS_ERR_ARG  # mixed dtype
         hgs = ss.ss_create_grid((64, 64), (1, 1), ss.SS_F32)
         ss.ss_set_model(hgs, 4, (0.16, 0.08, 0.035, 0.065), 1.0)
-        ss.ss_bind_workspace(hgs, fake, ss.ss_workspace_size(hgs))
+        ss.ss_bind_workspace(hgs, fake + (9 << 32), ss.ss_workspace_size(hgs))
         hs.append(hgs)
         assert code_of(ss.ss_batch_create, [hs[0], hgs]) == ss.SS_ERR_UNSUPPORTED  # two fields
         h3 = ss.ss_create_grid((64, 64, 64), (1, 1, 1), ss.SS_F32)
