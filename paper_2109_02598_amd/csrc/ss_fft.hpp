@@ -1,7 +1,8 @@
 // Register-resident Stockham FFT for gfx950, exchanged through LDS.
 //
 // One line of N (power of two, 8..4096) complex points is owned by S = N/P
-// consecutive threads (P = 8 or 16 points per thread); thread t holds the P
+// consecutive threads (P = 2, 4, 8 or 16 points per thread; the kernels take
+// 4 on short lines of small grids, 8 or 16 otherwise); thread t holds the P
 // points x[t + e*S], e = 0..P-1.  Every stage of the Stockham autosort
 // reads that same set of positions, so the first stage can take its
 // operands straight from global memory (coalesced) and, because the last
