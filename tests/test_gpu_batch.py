@@ -1,4 +1,5 @@
-"""Batched step: many uneven Cahn-Hilliard grids in grouped launches.
+"""Batched step: many uneven grids (Cahn-Hilliard, and every fixed one-field
+model mixed in one batch) in grouped launches.
 
 Each member must match the plain single-grid path bit for bit (both run
 the same per-line code, and multiply-adds are contracted per source
@@ -310,3 +311,49 @@ def test_check_after_grouped_steps_on_a_dirty_workspace():
         ref = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, 3)[0]
         assert_parity(g.get_field(0).cpu().numpy(), ref, "f32", ("dirty workspace", w.n))
     b.close()
+
+
+MIXED = [("allen_cahn", (128, 64), (1.0, 0.7), (1.2, 0.8, 1.0, 1.0), 0.4),
+         ("pfc", (256, 128), (0.785, 0.864), (-0.25, 1.0, 0.3, 1.0), 0.5),
+         ("cahn_hilliard", (64, 256), (0.9, 1.0), (1.0, 1.5, 1.0, 1.0), 0.1),
+         ("pfc", (64, 64), (0.785, 0.785), (-0.25, 1.0, 0.0, 1.0), 0.5),
+         ("allen_cahn", (512, 128), (1.0, 1.0), (1.0, 1.0, 1.0, 1.0), 0.5),
+         ("cahn_hilliard", (1024, 64), (1.0, 1.1), (0.7, 1.3, 1.0, 1.0), 0.1)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_of_mixed_models_and_spacings(dtype):
+    """Allen-Cahn, Cahn-Hilliard and PFC members (every fixed one-field
+    model), each with its own spacings, coefficients and dt, in one batch:
+    every member matches its plain run bit for bit and its oracle run to
+    the bar."""
+    from tests._common import synth_fields
+    torch, specstep = need_gpu()
+    stream = torch.cuda.Stream()
+    steps = 20
+    f0 = [as_input(synth_fields(m, n, dx, 300 + i), dtype) for i, (m, n, dx, c, dt) in enumerate(MIXED)]
+
+    def grids():
+        out = []
+        for (m, n, dx, c, dt), f in zip(MIXED, f0):
+            g = specstep.Grid(n, dx, dtype=dtype, model=m, coef=c, dt=dt, stream=stream.cuda_stream)
+            g.set_field(0, f[0])
+            out.append(g)
+        return out
+
+    plain = grids()
+    for g in plain:
+        g.step(steps)
+    want = [g.get_field(0).cpu().numpy() for g in plain]
+    gs = grids()
+    b = specstep.Batch(gs, autotune=True, reps=2)
+    b.step(steps)
+    torch.cuda.synchronize()
+    for i, ((m, n, dx, c, dt), g) in enumerate(zip(MIXED, gs)):
+        got = g.get_field(0).cpu().numpy()
+        assert same_as_plain(got, want[i]), (i, m, n)
+        ref = spectral.step_n(f0[i], m, c, dt, dx, steps)[0]
+        assert_parity(got, ref, dtype, ("mixed member", i, m, n))
+    b.close()
+    for g in plain + gs:
+        g.close()
