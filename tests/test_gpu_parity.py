@@ -196,3 +196,34 @@ def test_mass_log_host_copy():
     assert specstep.ss_mass_log(g.h, 0, 1).shape == (0, 1)
     assert abs(float(host[-1, 0]) - float(np.mean(f0[0]))) <= 1e-15
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model,n", [("gray_scott", (64, 32)), ("model_c", (32, 64)), ("allen_cahn", (16, 8, 32)),
+                                     ("gray_scott", (16, 16, 8)), ("pfc", (32, 32))])
+def test_mass_log_is_each_fields_mean_after_each_step(model, n, dtype):
+    """The per-step log of every field of every model (conserved or not) is
+    the mean of that field after the step, as the oracle steps it, across
+    calls of the step."""
+    torch, specstep = need_gpu()
+    dx = (1.0,) * len(n)
+    dt = {"allen_cahn": 0.5, "pfc": 0.5, "gray_scott": 1.0, "model_c": 0.05}[model]
+    f0 = as_input(synth_fields(model, n, dx, 67), dtype)
+    g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model], dt=dt)
+    for i, f in enumerate(f0):
+        g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
+    g.enable_mass_log(12)
+    g.step(5)
+    g.step(7)
+    log = g.mass_log()
+    g.close()
+    assert log.shape == (12, len(f0))
+    cur = f0
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    worst = 0.0
+    for s in range(12):
+        cur = oracle_run(model, n, dx, dt, 1, cur)
+        for f, c in enumerate(cur):
+            worst = max(worst, abs(float(log[s, f]) - float(np.mean(c))))
+    say(model, n, dtype, "max |log - oracle mean| %.3e" % worst)
+    assert worst <= tol
