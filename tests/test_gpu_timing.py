@@ -69,3 +69,23 @@ def test_pass_timing_leaves_stored_fields_alone(model, n, dt, dtype):
     b.close()
     for x, y in zip(got, want):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("model,n,dt,dtype", CASES)
+def test_autotune_leaves_stored_fields_alone(model, n, dt, dtype):
+    """ss_autotune on a grid whose fields are stored (mid-run) keeps them and
+    the carried spectrum: the run continues with the bits of an untuned run
+    (results do not depend on the tiling)."""
+    torch, specstep = need_gpu()
+    a = grid(specstep, model, n, dt, dtype, 122)
+    a.step(8)
+    want = fields(a)
+    a.close()
+    b = grid(specstep, model, n, dt, dtype, 122)
+    b.step(3)
+    b.autotune(1)
+    b.step(5)
+    got = fields(b)
+    b.close()
+    for x, y in zip(got, want):
+        assert np.array_equal(x, y)
