@@ -1,9 +1,10 @@
-"""The measurement entry points time the production work and leave the
-fields alone: ss_step_n_profiled gives the bits of ss_step_n and counts the
-launches of each pass kind (per step: one x and one k-space launch for all
-fields, one y launch of each kind per field in 3D), and ss_time_pass on a
-grid whose fields are stored does not change them (the bench relies on
-both)."""
+"""Calls between steps leave the run intact: ss_step_n_profiled gives the
+bits of ss_step_n and counts the launches of each pass kind (per step: one
+x and one k-space launch for all fields, one y launch of each kind per
+field in 3D); ss_time_pass and ss_autotune on a grid whose fields are
+stored do not change them (the bench relies on this); new coefficients
+and dt through ss_set_model keep the fields and continue as the oracle
+does."""
 import numpy as np
 import pytest
 
@@ -89,3 +90,27 @@ def test_autotune_leaves_stored_fields_alone(model, n, dt, dtype):
     b.close()
     for x, y in zip(got, want):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("model,n,dt,dtype", CASES)
+def test_new_coefficients_and_dt_mid_run(model, n, dt, dtype):
+    """ss_set_model with the same model and new coefficients and dt keeps
+    the fields: 5 steps with the first set, 5 with the second, as the oracle
+    takes them."""
+    from oracle import spectral
+    from tests._common import as_input, assert_parity
+    torch, specstep = need_gpu()
+    dx = (1.0,) * len(n)
+    f0 = as_input(synth_fields(model, n, dx, 123), dtype)
+    c2 = tuple(c * s for c, s in zip(COEF[model], (1.1, 0.9, 1.05, 0.95, 1.2)))
+    g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model], dt=dt)
+    for i, f in enumerate(f0):
+        g.set_field(i, f)
+    g.step(5)
+    g.set_model(model, c2, 0.7 * dt)
+    g.step(5)
+    got = fields(g)
+    g.close()
+    mid = spectral.step_n(f0, model, COEF[model], dt, dx, 5)
+    want = spectral.step_n(mid, model, c2, 0.7 * dt, dx, 5)
+    assert_parity(got, want, dtype, ("coefficients changed mid-run", model, n))
