@@ -110,7 +110,10 @@ LINEAR_OFF = {
 
 @pytest.mark.parametrize("model", sorted(LINEAR_OFF))
 @pytest.mark.parametrize("shape,dx,ms", [((32, 64), (1.0, 0.5), (3, -5)),
-                                         ((16, 8, 8), (math.pi / 4,) * 3, (1, 2, 3))])
+                                         ((16, 8, 8), (math.pi / 4,) * 3, (1, 2, 3)),
+                                         # unequal spacings: the (x, y, z) order of dx in 3D
+                                         ((16, 8, 32), (0.7, 1.1, 1.9), (5, -2, 3)),
+                                         ((8, 16, 8), (1.3, 0.6, 0.9), (-3, 1, 2))])
 def test_single_mode_exact_decay(model, shape, dx, ms):
     coef = LINEAR_OFF[model]
     dt, n = 0.1, 7
