@@ -58,17 +58,19 @@ def test_adjoint_f64_vs_oracle_small(n, steps, K):
         assert e <= 1e-9
 
 
-@pytest.mark.parametrize("nx,ny", [(8, 16), (32, 8), (16, 1024), (1024, 16), (512, 64)])
-def test_adjoint_f64_vs_oracle_shapes(nx, ny):
+@pytest.mark.parametrize("nx,ny,dt", [(8, 16, 1.0), (32, 8, 0.6), (16, 1024, 1.0), (1024, 16, 1.7),
+                                      (512, 64, 0.6)])
+def test_adjoint_f64_vs_oracle_shapes(nx, ny, dt):
     """Uneven grids with unequal spacings: the k-space and x sweeps take
     different points per thread (4 on axes up to 512, 8 above), the
-    smallest axes, and the transposed spectral layout."""
+    smallest axes, and the transposed spectral layout; dt other than the
+    workload's 1 exposes the powers of dt in the coefficient gradients."""
     torch, specstep = need_gpu()
     steps, K, dx = 9, 4, (0.9, 1.3)
     u0 = 1.0 - 0.5 * inputs.uniform_field(71, (ny, nx), 0.0, 1.0)
     v0 = 0.25 * inputs.uniform_field(72, (ny, nx), 0.0, 1.0)
     vstar = inputs.uniform_field(73, (ny, nx), 0.0, 0.5)
-    g = specstep.Grid((nx, ny), dx, dtype="f64", model="gray_scott", coef=COEF, dt=1.0)
+    g = specstep.Grid((nx, ny), dx, dtype="f64", model="gray_scott", coef=COEF, dt=dt)
     g.bind_adjoint(steps, K)
     g.set_field(0, u0)
     g.set_field(1, v0)
@@ -77,7 +79,7 @@ def test_adjoint_f64_vs_oracle_shapes(nx, ny):
     dqT = [torch.zeros_like(vT), vT - torch.from_numpy(vstar).to("cuda")]
     (du0, dv0), dc = g.adjoint(dqT)
     g.close()
-    ref = oadj.gray_scott_misfit_grad(u0, v0, COEF, 1.0, dx, steps, vstar, K=K)
+    ref = oadj.gray_scott_misfit_grad(u0, v0, COEF, dt, dx, steps, vstar, K=K)
     for key, got in (("du0", du0), ("dv0", dv0)):
         got = got.double().cpu().numpy()
         e = rel_l2(got, ref[key])

@@ -26,18 +26,23 @@ def test_dphi1_series_matches_direct_formula_near_switch():
     assert adjoint.dphi1(np.array([0.0]))[0] == 0.5
 
 
-def test_adjoint_coefficients_vs_central_fd():
+# the workload's dt = 1 and dx = 1 hide mistakes in powers of dt or in the
+# spacings: the pins also run with dt != 1 and unequal spacings
+@pytest.mark.parametrize("dt,dx", [(None, None), (0.4, (1.0, 0.8)), (1.7, (0.9, 1.2))])
+def test_adjoint_coefficients_vs_central_fd(dt, dx):
     w, vstar = small_case()
+    dt = w.dt if dt is None else dt
+    dx = w.dx if dx is None else dx
     u0, v0 = w.fields
-    res = adjoint.gray_scott_misfit_grad(u0, v0, COEF, w.dt, w.dx, w.steps, vstar, K=7)
+    res = adjoint.gray_scott_misfit_grad(u0, v0, COEF, dt, dx, w.steps, vstar, K=7)
     for i in range(4):
         h = 1e-6 * COEF[i]
         cp = list(COEF); cp[i] += h
         cm = list(COEF); cm[i] -= h
-        jp = adjoint.gray_scott_misfit(u0, v0, cp, w.dt, w.dx, w.steps, vstar)
-        jm = adjoint.gray_scott_misfit(u0, v0, cm, w.dt, w.dx, w.steps, vstar)
+        jp = adjoint.gray_scott_misfit(u0, v0, cp, dt, dx, w.steps, vstar)
+        jm = adjoint.gray_scott_misfit(u0, v0, cm, dt, dx, w.steps, vstar)
         fd = (jp - jm) / (2 * h)
-        assert abs(res["dcoef"][i] - fd) <= 1e-5 * abs(fd), (i, res["dcoef"][i], fd)
+        assert abs(res["dcoef"][i] - fd) <= 1e-5 * abs(fd), (i, dt, dx, res["dcoef"][i], fd)
 
 
 def test_adjoint_initial_field_vs_central_fd():

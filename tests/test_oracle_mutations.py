@@ -16,6 +16,7 @@ PIN_FILES = {
     "spectral.py": ["tests/test_oracle_pins.py", "tests/test_oracle_split.py", "tests/test_oracle_adjoint.py",
                     "tests/test_oracle_structure.py"],
     "fd_euler.py": ["tests/test_oracle_fd.py", "tests/test_oracle_pins.py"],
+    "adjoint.py": ["tests/test_oracle_adjoint.py"],
 }
 
 MUTATIONS = [
@@ -79,6 +80,13 @@ MUTATIONS = [
     ("fd_euler.py", "F * (1.0 - u)", "F * (1.0 + u)"),
     ("fd_euler.py", "2.0 * q0 ** 2 * lp", "q0 ** 2 * lp"),
     ("fd_euler.py", "+ 2.0 * c5 * p * m,", "+ c5 * p * m,"),
+    # reverse mode: Jacobian transpose, coefficient sums, phi1 derivative
+    ("adjoint.py", "- 2.0 * u * v * mu_u + 2.0 * u * v * mu_v", "- 2.0 * u * v * mu_u + u * v * mu_v"),
+    ("adjoint.py", "- v * v * mu_u + v * v * mu_v", "- v * v * mu_u - v * v * mu_v"),
+    ("adjoint.py", "+ np.sum(mu_u)", "- np.sum(mu_u)"),
+    ("adjoint.py", "g[3] += -np.sum(lam_v * Tv)", "g[3] += -np.sum(lam_u * Tu)"),
+    ("adjoint.py", "dt * dt * dphi1(Lu * dt)", "dt * dphi1(Lu * dt)"),
+    ("adjoint.py", "_apply(Au, lam_u) -", "_apply(Av, lam_u) -"),
 ]
 
 
