@@ -98,3 +98,35 @@ def test_solver_choice_errors():
         with pytest.raises(specstep.SpecStepError):
             call()
     g.close()
+
+
+# distinct coefficients, none equal to 1: a coefficient read in place of
+# another, or a missing power of one, cannot hide behind the value 1
+DISTINCT = {
+    "allen_cahn": (1.3, 0.7, 0.6, 1.4),
+    "cahn_hilliard": (0.8, 1.3, 0.7, 1.6),
+    "pfc": (-0.2, 0.9, 0.4, 1.3),
+    "gray_scott": (0.14, 0.07, 0.04, 0.06),
+    "model_c": (0.8, 1.2, 0.7, 1.3, 0.9),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model", sorted(DISTINCT))
+@pytest.mark.parametrize("n,stencil", [((64, 32), 0), ((32, 64), 9), ((32, 64), 17), ((16, 8, 32), 19),
+                                       ((64, 8, 32), 4), ((256, 16), 0)])
+def test_euler_distinct_coefficients_vs_oracle(model, n, stencil, dtype):
+    dx = (0.9,) * len(n)
+    steps = 20
+    dt = 0.5 * DT[model] * (0.5 if stencil in (4, 17) else 1.0)
+    fields = synth_fields(model, n, dx, 600 + len(n))
+    torch, specstep = need_gpu()
+    g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=DISTINCT[model], dt=dt, solver="euler",
+                      stencil=stencil)
+    for i, f in enumerate(fields):
+        g.set_field(i, f.astype(np.float32) if dtype == "f32" else f)
+    g.step(steps)
+    got = [g.get_field(i).double().cpu().numpy() for i in range(len(fields))]
+    g.close()
+    ref = fd_euler.euler_n(as_input(fields, dtype), model, DISTINCT[model], dt, dx, steps, stencil)
+    assert_parity(got, list(ref), dtype, ("distinct coefficients", model, n, stencil))

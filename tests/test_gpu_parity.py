@@ -227,3 +227,28 @@ def test_mass_log_is_each_fields_mean_after_each_step(model, n, dtype):
             worst = max(worst, abs(float(log[s, f]) - float(np.mean(c))))
     say(model, n, dtype, "max |log - oracle mean| %.3e" % worst)
     assert worst <= tol
+
+
+# distinct coefficients, none equal to 1 (q0 = 0.9 in PFC): a coefficient
+# read in place of another, or a missing power of one, cannot hide behind
+# the value 1 of the workloads' coefficients
+DISTINCT = {
+    "allen_cahn": (1.3, 0.7, 0.6, 1.4),
+    "cahn_hilliard": (0.8, 1.3, 0.7, 1.6),
+    "pfc": (-0.2, 0.9, 0.4, 1.3),
+    "gray_scott": (0.14, 0.07, 0.04, 0.06),
+    "model_c": (0.8, 1.2, 0.7, 1.3, 0.9),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(64, 32), (16, 32, 8)])
+@pytest.mark.parametrize("model", sorted(DISTINCT))
+def test_parity_distinct_coefficients(model, n, dtype):
+    h = DX.get(model, 1.0)
+    dx = tuple(h * (1.0 + 0.1 * i) for i in range(len(n)))
+    dt = {"allen_cahn": 0.3, "cahn_hilliard": 0.05, "pfc": 0.4, "gray_scott": 0.7, "model_c": 0.04}[model]
+    f0 = as_input(synth_fields(model, n, dx, 13), dtype)
+    got, _ = run_gpu(model, n, dx, dt, 50, f0, dtype, coef=DISTINCT[model])
+    want = oracle_run(model, n, dx, dt, 50, f0, coef=DISTINCT[model])
+    assert_parity(got, want, dtype, ("distinct coefficients", model, n))
