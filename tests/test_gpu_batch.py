@@ -313,12 +313,13 @@ def test_check_after_grouped_steps_on_a_dirty_workspace():
     b.close()
 
 
-MIXED = [("allen_cahn", (128, 64), (1.0, 0.7), (1.2, 0.8, 1.0, 1.0), 0.4),
-         ("pfc", (256, 128), (0.785, 0.864), (-0.25, 1.0, 0.3, 1.0), 0.5),
-         ("cahn_hilliard", (64, 256), (0.9, 1.0), (1.0, 1.5, 1.0, 1.0), 0.1),
-         ("pfc", (64, 64), (0.785, 0.785), (-0.25, 1.0, 0.0, 1.0), 0.5),
+# every member its own coefficients (none shared between members of a model)
+MIXED = [("allen_cahn", (128, 64), (1.0, 0.7), (1.2, 0.8, 0.9, 1.1), 0.4),
+         ("pfc", (256, 128), (0.785, 0.864), (-0.25, 0.9, 0.3, 1.2), 0.5),
+         ("cahn_hilliard", (64, 256), (0.9, 1.0), (1.0, 1.5, 0.8, 1.3), 0.1),
+         ("pfc", (64, 64), (0.785, 0.785), (-0.2, 1.1, 0.0, 0.9), 0.5),
          ("allen_cahn", (512, 128), (1.0, 1.0), (1.0, 1.0, 1.0, 1.0), 0.5),
-         ("cahn_hilliard", (1024, 64), (1.0, 1.1), (0.7, 1.3, 1.0, 1.0), 0.1)]
+         ("cahn_hilliard", (1024, 64), (1.0, 1.1), (0.7, 1.3, 1.1, 0.8), 0.1)]
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
