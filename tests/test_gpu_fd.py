@@ -130,3 +130,22 @@ def test_euler_distinct_coefficients_vs_oracle(model, n, stencil, dtype):
     g.close()
     ref = fd_euler.euler_n(as_input(fields, dtype), model, DISTINCT[model], dt, dx, steps, stencil)
     assert_parity(got, list(ref), dtype, ("distinct coefficients", model, n, stencil))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc", "gray_scott", "model_c"])
+@pytest.mark.parametrize("n,dx,stencil", [((64, 32), (1.0, 0.8), 0), ((32, 64), (0.8, 1.25), 4),
+                                          ((16, 8, 32), (1.0, 0.8, 1.3), 0), ((64, 8, 32), (1.3, 1.0, 0.8), 4),
+                                          ((256, 16), (0.9, 1.2), 0), ((64, 16, 16), (1.2, 0.9, 1.0), 0)])
+def test_euler_unequal_spacings_vs_oracle(model, n, dx, stencil, dtype):
+    """The axis-wise stencils take a spacing per axis: with unequal ones a
+    spacing applied to the wrong axis shows (the other tests use 1)."""
+    steps = 20
+    hmin = min(dx)
+    dt = DT[model] * (0.5 if stencil == 4 else 1.0) * hmin ** (6 if model == "pfc" else 4 if model in
+                                                                ("cahn_hilliard", "model_c") else 2)
+    fields = synth_fields(model, n, dx, 700 + len(n))
+    got = gpu_euler(model, n, dx, dt, steps, [f.astype(np.float32) if dtype == "f32" else f for f in fields],
+                    dtype, stencil)
+    ref = fd_euler.euler_n(as_input(fields, dtype), model, COEF_FD[model], dt, dx, steps, stencil)
+    assert_parity(list(got), list(ref), dtype, ("unequal spacings", model, n, dx, stencil))

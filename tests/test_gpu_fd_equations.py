@@ -148,3 +148,21 @@ def test_the_implicit_scheme_is_refused():
     with pytest.raises(specstep.SpecStepError):
         specstep.Grid((32, 32), (1.0, 1.0), equations=text, coefs=coefs, dt=0.01, solver="euler",
                       scheme="implicit")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "gray_scott", "model_c"])
+@pytest.mark.parametrize("n,dx,stencil", [((64, 32), (1.0, 0.8), 0), ((256, 32), (0.9, 1.2), 0),
+                                          ((32, 64), (0.8, 1.25), 4), ((16, 8, 32), (1.0, 0.8, 1.3), 0),
+                                          ((64, 8, 32), (1.3, 1.0, 0.8), 4), ((64, 8, 16), (1.2, 0.9, 1.0), 0)])
+def test_equations_unequal_spacings(model, n, dx, stencil, dtype):
+    """The equation kernels with a spacing per axis (the axis-wise stencils
+    take unequal ones; the other tests use 1): against the oracle's Euler
+    form of the split."""
+    text, coefs = eqs.fixed(model, (0.9, 1.3, 0.7, 1.2, 0.8)[:len(COEF_FD[model])]
+                            if model != "gray_scott" else (0.14, 0.07, 0.04, 0.06))
+    split = osp.parse(text, coefs)
+    dt = stable_dt(split, len(n), stencil, h=min(dx))
+    f0 = as_input(synth_fields(model, n, dx, 800 + len(n)), dtype)
+    got = gpu_euler_eq(text, coefs, n, dx, dt, 20, f0, dtype, stencil)
+    check(got, osp.euler_n(f0, split, dt, dx, 20, stencil), dtype, ("unequal spacings", model, n, dx, stencil))
