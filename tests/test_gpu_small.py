@@ -141,3 +141,22 @@ def test_the_tuner_chooses_a_kernel():
     g.close()
     assert kind in (0, 1)
     assert_parity(got, spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, 100)[0], "f64", "tuned")
+
+
+# distinct coefficients, none equal to 1, and unequal spacings
+DISTINCT = {"allen_cahn": (1.3, 0.7, 0.6, 1.4), "cahn_hilliard": (0.8, 1.3, 0.7, 1.6),
+            "pfc": (-0.2, 0.9, 0.4, 1.3)}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [16, 64, 128])
+@pytest.mark.parametrize("model", sorted(DISTINCT))
+def test_distinct_coefficients_and_spacings_vs_oracle(model, n, dtype):
+    torch, specstep = need_gpu()
+    h = np.pi / 4 if model == "pfc" else 1.0
+    dx = (h, 1.15 * h)
+    dt = {"allen_cahn": 0.3, "cahn_hilliard": 0.05, "pfc": 0.4}[model]
+    f0 = as_input(synth_fields(model, (n, n), dx, 68), dtype)
+    got, _ = run(specstep, torch, model, (n, n), dx, dt, f0, dtype, [20, 30], 1, coef=DISTINCT[model])
+    want = spectral.step_n(f0, model, DISTINCT[model], dt, dx, 50)
+    assert_parity(got, want[0], dtype, ("one workgroup, distinct coefficients", model, n))
