@@ -17,6 +17,8 @@ PIN_FILES = {
                     "tests/test_oracle_structure.py"],
     "fd_euler.py": ["tests/test_oracle_fd.py", "tests/test_oracle_pins.py"],
     "adjoint.py": ["tests/test_oracle_adjoint.py"],
+    "structure.py": ["tests/test_oracle_structure.py"],
+    "operator_split.py": ["tests/test_oracle_split.py"],
 }
 
 MUTATIONS = [
@@ -87,6 +89,19 @@ MUTATIONS = [
     ("adjoint.py", "g[3] += -np.sum(lam_v * Tv)", "g[3] += -np.sum(lam_u * Tu)"),
     ("adjoint.py", "dt * dt * dphi1(Lu * dt)", "dt * dphi1(Lu * dt)"),
     ("adjoint.py", "_apply(Au, lam_u) -", "_apply(Av, lam_u) -"),
+    # structure factor: threshold, normalisation, binning, integer modes
+    ("structure.py", "return (np.asarray(psi) > 0).astype", "return (np.asarray(psi) >= 0).astype"),
+    ("structure.py", "np.abs(np.fft.fftn(rho)) ** 2 / n_cells", "np.abs(np.fft.fftn(rho)) ** 2 / n_cells ** 2"),
+    ("structure.py", "np.floor(np.sqrt(m2.astype(np.float64)) + 0.5)", "np.floor(np.sqrt(m2.astype(np.float64)))"),
+    ("structure.py", "np.fft.fftfreq(n, d=1.0 / n)", "np.fft.fftfreq(n, d=1.0)"),
+    ("structure.py", "sum((n // 2) ** 2 for n in shape)", "sum((n // 2) for n in shape)"),
+    # the split: the Laplacian's symbol, pairing, linear part, factors
+    ("operator_split.py", "out = out + c * (-k2) ** p", "out = out + c * k2 ** p"),
+    ("operator_split.py", "if sum(k[1]) <= 1}", "if sum(k[1]) <= 0}"),
+    ("operator_split.py", "if any(e):                      # the Laplacian of a constant is zero",
+     "if True:"),
+    ("operator_split.py", "return 1.0 / den, dt / den", "return 1.0 / den, dt"),
+    ("operator_split.py", "r._add(k, sign * c)", "r._add(k, c)"),
 ]
 
 

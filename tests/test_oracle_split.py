@@ -197,6 +197,14 @@ def test_split_sets_of_the_procedure():
     assert s.L[1] == {0: -1.0} and s.channels[1] == []
 
 
+def test_laplacian_of_a_constant_is_zero():
+    """lap and bilap of constants vanish (step 3: lap -> -|k|^2 acts on the
+    mean only through k = 0, where the symbol is 0): no channel, no term."""
+    s = osp.parse("psi' = lap(psi + 3) - 2*psi + bilap(5) + lap(c)", {"c": 0.7})
+    assert s.L[0] == {1: 1.0, 0: -2.0}
+    assert s.channels[0] == []
+
+
 @pytest.mark.parametrize("text", [
     "psi' = psi*lap(psi)", "psi' = psi/psi", "psi' = psi^2.5", "psi' = foo", "psi' = 2 psi",
     "psi' = psi^2^2", "psi = psi", "psi' = lap psi", "psi' = psi; psi' = -psi", "psi' = (psi",

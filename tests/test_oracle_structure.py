@@ -64,6 +64,17 @@ def test_parseval_and_k0():
     assert int(c.sum()) == psi.size
 
 
+def test_exact_zeros_are_empty_cells():
+    """rho = [psi > 0]: cells where psi is exactly 0 are not occupied (the
+    k = 0 bin counts the cells with psi > 0 only)."""
+    psi = np.zeros((8, 12))
+    psi[1, 2] = psi[3, 7] = psi[6, 1] = 0.5            # three occupied cells
+    psi[2, 2] = psi[5, 5] = -0.25
+    s, c = osf.structure_factor(psi)
+    assert c[0] == 1 and s[0] == 3 ** 2 / psi.size
+    assert abs(float(np.sum(s * c)) - 3.0) <= 1e-12
+
+
 def test_sampled_square_wave_closed_form():
     """psi = cos(pi (x + 1/2) / 8) on 64 x 64: rho is a square wave of
     period 16 (8 ones), constant along y.  Its DFT is nonzero only at
