@@ -529,9 +529,10 @@ ss_status ss_mass_log(ss_grid g, double* dst_host, int64_t max, int64_t* rows);
  *   nbins elements, written on the grid's stream (no synchronisation).
  *   The field's state is not modified; the grid's nonlinear-term scratch
  *   and staging arrays are overwritten (calls on one grid are ordered on
- *   its stream).  Per-bin sums are added in a fixed order across
- *   workgroups; within a workgroup LDS atomics make the last bits of a sum
- *   depend on scheduling.  Errors: SS_ERR_ARG (null pointer, field out of
+ *   its stream).  Within a workgroup the per-bin sums are kept in fixed
+ *   point (2^-85 per term, exact integer adds), across workgroups they are
+ *   added in a fixed order: a call gives the same bits every time for the
+ *   grid's tiling.  Errors: SS_ERR_ARG (null pointer, field out of
  *   range, nbins not the grid's), SS_ERR_STATE (no model, workspace or
  *   field), SS_ERR_UNSUPPORTED (box lengths N_j dx_j not all equal, or no
  *   tiling fits). */

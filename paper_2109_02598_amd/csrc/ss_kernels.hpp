@@ -1115,7 +1115,8 @@ __global__ void __launch_bounds__(512) kfwd_kernel(KArgs a) {
 // the same length along every axis, so |k| = 2 pi |m| / L).  Each block
 // accumulates a histogram in LDS over its lines (several, persistently) and
 // writes it to its own row of a partials array; sf_reduce adds the rows in
-// block order.
+// block order.  The histogram's sums are kept in fixed point (sf_add), so
+// that no part of the result depends on the order of the atomic adds.
 // ---------------------------------------------------------------------------
 struct SFArgs {
   const void* spec;        // transformed occupancy, layout of the state
@@ -1131,7 +1132,27 @@ struct SFArgs {
 };
 
 constexpr int64_t sf_lds(int esz, int nl, int lines, int nbins) {
-  return (int64_t)lines * k_reg(esz, nl) * esz + (int64_t)nbins * (8 + 4);
+  return (int64_t)lines * k_reg(esz, nl) * esz + (int64_t)nbins * (24 + 4);
+}
+
+// Per-bin sums in fixed point.  A contribution v = |rho_hat|^2 / N (twice
+// that for a +-kx pair) lies in [0, 2^35): |rho_hat| <= N <= 2^34.  It is
+// added as floor(v 2^85) in three 40-bit chunks, each to its own 64-bit LDS
+// counter with an integer atomic; integer sums do not depend on the order
+// of the adds, and up to 2^24 adds per bin and block leave every counter
+// below 2^64.  The truncation costs at most 2^-85 per contribution.
+__device__ __forceinline__ void sf_add(unsigned long long* h, int b, double v) {
+  const double x = v * 0x1p85;                 // exact scaling, below 2^120
+  const double hi = floor(x * 0x1p-80);
+  const double r = x - hi * 0x1p80;            // exact
+  const double mid = floor(r * 0x1p-40);
+  const double lo = floor(r - mid * 0x1p40);
+  atomicAdd(&h[3 * b], (unsigned long long)hi);
+  atomicAdd(&h[3 * b + 1], (unsigned long long)mid);
+  atomicAdd(&h[3 * b + 2], (unsigned long long)lo);
+}
+__device__ __forceinline__ double sf_value(const unsigned long long* h, int b) {
+  return (double)h[3 * b] * 0x1p-5 + (double)h[3 * b + 1] * 0x1p-45 + (double)h[3 * b + 2] * 0x1p-85;
 }
 
 // b = round(sqrt(m2)) for an integer m2 >= 0: the b with b^2 - b < m2 <= b^2 + b
@@ -1143,7 +1164,7 @@ __device__ __forceinline__ int sf_bin(int64_t m2) {
 }
 
 template <typename T, int NL>
-__device__ __forceinline__ void sf_tile(const SFArgs& a, int tile, C<T>* lds, double* hs, uint32_t* hc) {
+__device__ __forceinline__ void sf_tile(const SFArgs& a, int tile, C<T>* lds, unsigned long long* hs, uint32_t* hc) {
   typedef KCfg<T, NL> K;
   constexpr int S = K::S, REG = K::REG;
   const int tid = threadIdx.x;
@@ -1193,9 +1214,9 @@ __device__ __forceinline__ void sf_tile(const SFArgs& a, int tile, C<T>* lds, do
         const double br = 0.5 * ((double)c[0][e].y + (double)cm.y), bi = 0.5 * ((double)cm.x - (double)c[0][e].x);
         const int b0 = sf_bin(mmid2 + ml * ml);
         const int bn = sf_bin(hx * hx + mmid2 + ml * ml);
-        atomicAdd(&hs[b0], (ar * ar + ai * ai) * w);
+        sf_add(hs, b0, (ar * ar + ai * ai) * w);
         atomicAdd(&hc[b0], 1u);
-        atomicAdd(&hs[bn], (br * br + bi * bi) * w);
+        sf_add(hs, bn, (br * br + bi * bi) * w);
         atomicAdd(&hc[bn], 1u);
       }
       done = true;
@@ -1210,7 +1231,7 @@ __device__ __forceinline__ void sf_tile(const SFArgs& a, int tile, C<T>* lds, do
       const int64_t ml = p <= NL / 2 ? p : p - NL;
       const double re = (double)c[0][e].x, im = (double)c[0][e].y;
       const int b = sf_bin(mx2 + mmid2 + ml * ml);
-      atomicAdd(&hs[b], 2.0 * (re * re + im * im) * w);
+      sf_add(hs, b, 2.0 * (re * re + im * im) * w);
       atomicAdd(&hc[b], 2u);
     }
   }
@@ -1222,10 +1243,12 @@ __global__ void __launch_bounds__(512) sfpass_kernel(SFArgs a) {
   typedef KCfg<T, NL> K;
   extern __shared__ __align__(16) unsigned char ss_dyn_lds[];
   C<T>* lds = reinterpret_cast<C<T>*>(ss_dyn_lds);
-  double* hs = reinterpret_cast<double*>(lds + a.lines_per_block * K::REG);
-  uint32_t* hc = reinterpret_cast<uint32_t*>(hs + a.nbins);
+  unsigned long long* hs = reinterpret_cast<unsigned long long*>(lds + a.lines_per_block * K::REG);
+  uint32_t* hc = reinterpret_cast<uint32_t*>(hs + 3 * a.nbins);
   for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) {
-    hs[i] = 0.0;
+    hs[3 * i] = 0ull;
+    hs[3 * i + 1] = 0ull;
+    hs[3 * i + 2] = 0ull;
     hc[i] = 0u;
   }
   __syncthreads();
@@ -1235,7 +1258,7 @@ __global__ void __launch_bounds__(512) sfpass_kernel(SFArgs a) {
   double* ps = a.part_sum + (int64_t)blockIdx.x * a.pstride;
   uint32_t* pc = a.part_cnt + (int64_t)blockIdx.x * a.pstride;
   for (int i = threadIdx.x; i < a.nbins; i += blockDim.x) {
-    ps[i] = hs[i];
+    ps[i] = sf_value(hs, i);
     pc[i] = hc[i];
   }
 }

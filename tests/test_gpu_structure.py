@@ -135,3 +135,23 @@ def test_porod_law(model, n, dt, steps, window, slope, tol):
     got = osf.porod_slope(acc, c, *window)
     say(model, n, "Porod slope %.3f over |m| in %s (law %.1f)" % (got, window, slope))
     assert abs(got - slope) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("model,n,dx", [("cahn_hilliard", (256, 128), (0.5, 1.0)),
+                                        ("allen_cahn", (32, 32, 32), (1.0, 1.0, 1.0))])
+def test_structure_factor_is_bitwise_reproducible(model, n, dx, dtype):
+    """The bins are summed in fixed point within a workgroup and in a fixed
+    order across workgroups: repeated calls on the same field, with other
+    work between them, give the same bits."""
+    torch, specstep = need_gpu()
+    g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=COEF[model], dt=0.05)
+    for i, f in enumerate(synth_fields(model, n, dx, 107)):
+        g.set_field(i, f)
+    g.step(10)
+    first = [t.cpu().numpy() for t in g.structure_factor(0)]
+    for _ in range(3):
+        g.time_pass("kpass", 2)               # other work on the grid's stream
+        again = [t.cpu().numpy() for t in g.structure_factor(0)]
+        assert np.array_equal(again[0], first[0]) and np.array_equal(again[1], first[1])
+    g.close()
