@@ -199,3 +199,19 @@ def test_mass_log_copy_validation(L):
         assert "no mass log" in ss.ss_last_error()
     finally:
         ss.ss_destroy_grid(h)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/specstep.h is a C header (no C++ in the boundary): it compiles
+    as pedantic C99 and C++11 with warnings as errors."""
+    import shutil
+    import subprocess
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "use.c"
+    src.write_text('#include "specstep.h"\nint main(void) { ss_grid g = 0; (void)g; return 0; }\n')
+    for cc, args in (("gcc", ["-std=c99", "-x", "c"]), ("g++", ["-std=c++11", "-x", "c++"])):
+        if not shutil.which(cc):
+            pytest.skip("%s not available" % cc)
+        r = subprocess.run([cc, *args, "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc, "-c", str(src),
+                            "-o", str(tmp_path / "use.o")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
