@@ -528,10 +528,36 @@ def trace_summary(d, last=0):
         stats.setdefault(k, []).append(us)
     if last:
         stats = {k: v[-last:] for k, v in stats.items()}
+    return _trace_table(stats)
+
+
+def _trace_table(stats):
     lines = ["| kernel | calls | mean us | min us |", "|---|---|---|---|"]
     for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
         lines.append("| `%s` | %d | %.2f | %.2f |" % (k[:90], len(v), sum(v) / len(v), min(v)))
     return "\n".join(lines)
+
+
+def trace_per_load(d, n):
+    """One kernel table per refresh of the carried spectrum (kfwd_kernel,
+    which follows every field load) in a rocprofv3 --kernel-trace output:
+    the n dispatches right after it (a grid's first n/2 steps when a step
+    is two launches)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit("expected one kernel_trace.csv under %s, found %d" % (d, len(files)))
+    with open(files[0]) as f:
+        rows = sorted((int(r["Dispatch_Id"]), r["Kernel_Name"],
+                       (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3) for r in csv.DictReader(f))
+    out = []
+    for j, i in enumerate(i for i, r in enumerate(rows) if "ss::kfwd_kernel<" in r[1]):
+        stats = {}
+        for _, k, us in rows[i + 1:i + 1 + n]:
+            stats.setdefault(k, []).append(us)
+        out.append("load %d (dispatch %d)\n\n%s" % (j + 1, rows[i][0], _trace_table(stats)))
+    return "\n\n".join(out)
 
 
 def counter_table(workload, fetch_dir, write_dir, copyf_dir, copyw_dir, copy_mb=64):
@@ -671,12 +697,17 @@ def main():
                          "rocprofv3 --pmc output directories as --traffic-record and exit; no GPU is used")
     ap.add_argument("--trace-last", type=int, default=0, metavar="N",
                     help="with --trace-summary: the last N dispatches of each kernel instead")
+    ap.add_argument("--trace-per-load", type=int, default=0, metavar="N",
+                    help="with --trace-summary: one table per field load, the N dispatches after it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (for scaling "
                          "the memory counters of a profiler) and exit")
     args = ap.parse_args()
     if args.trace_summary:
-        print(trace_summary(args.trace_summary, args.trace_last), flush=True)
+        if args.trace_per_load:
+            print(trace_per_load(args.trace_summary, args.trace_per_load), flush=True)
+        else:
+            print(trace_summary(args.trace_summary, args.trace_last), flush=True)
         return
     if args.counter_table:
         print(counter_table(args.workload, *args.counter_table), flush=True)
