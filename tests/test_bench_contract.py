@@ -141,3 +141,25 @@ def test_trace_summary_counts_the_timed_configuration(tmp_path):
     table = bench.trace_summary(str(tmp_path / "kt"))
     assert "| `void ss::kpass_kernel<double, 2048, true, 0>(ss::KArgs)` | 2 | 25.00 | 24.00 |" in table
     assert "float" not in table
+
+
+def test_trace_per_load_takes_the_dispatches_after_each_load(tmp_path):
+    import csv
+    K = "void ss::kpass_kernel<double, 2048, true, 0>(ss::KArgs)"
+    X = "void ss::xpass_kernel<double, 2048, 1, 2, 0>(ss::XArgs)"
+    F = "void ss::kfwd_kernel<double, 2048>(ss::KArgs)"
+    seq = [(X, 90), (K, 90),                      # trials before the first load
+           (F, 5), (X, 20), (K, 30), (X, 22), (K, 32), (X, 90),
+           (F, 5), (X, 10), (K, 12)]
+    os.makedirs(tmp_path / "kt")
+    with open(tmp_path / "kt" / "x_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        for i, (k, us) in enumerate(seq):
+            w.writerow([i + 1, k, 1000 * i, 1000 * i + 1000 * us])
+    out = bench.trace_per_load(str(tmp_path / "kt"), 4)
+    first, second = out.split("load 2")
+    assert "load 1 (dispatch 3)" in first and "(dispatch 9)" in second
+    assert "| `%s` | 2 | 21.00 | 20.00 |" % X in first and "| `%s` | 2 | 31.00 | 30.00 |" % K in first
+    assert "| `%s` | 1 | 10.00 | 10.00 |" % X in second and "| `%s` | 1 | 12.00 | 12.00 |" % K in second
+    assert "90.00" not in out
