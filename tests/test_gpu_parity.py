@@ -50,6 +50,16 @@ def test_parity_2d_two_fields(model, n, dtype):
     case(model, n, dtype)
 
 
+# two fields on the longest rows and lines: the two-field x pass (8 points
+# per thread in FP64, 16 in FP32) on 2048- and 4096-point rows, and the
+# k-space pass on 2048- and 4096-point lines
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(2048, 16), (4096, 8), (16, 2048), (8, 4096)])
+@pytest.mark.parametrize("model", ["gray_scott", "model_c"])
+def test_parity_2d_two_fields_long_axes(model, n, dtype):
+    case(model, n, dtype)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n", SHAPES_3D)
 @pytest.mark.parametrize("model", ["allen_cahn", "cahn_hilliard", "pfc", "gray_scott", "model_c"])
@@ -61,7 +71,7 @@ def test_parity_3d(model, n, dtype):
 # z lines of 1024 (the longest z the library takes)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n", [(2048, 16, 8), (16, 2048, 8), (8, 16, 1024), (1024, 8, 16), (8, 1024, 16)])
-@pytest.mark.parametrize("model", ["cahn_hilliard", "gray_scott"])
+@pytest.mark.parametrize("model", ["cahn_hilliard", "gray_scott", "model_c"])
 def test_parity_3d_long_axes(model, n, dtype):
     case(model, n, dtype)
 
