@@ -112,10 +112,14 @@ def synth_fields(model, n, dx, seed):
     return [inputs.uniform_field(seed, shape, -0.05, 0.05)]
 
 
-def run_gpu(model, n, dx, dt, steps, fields, dtype, coef=None, mass_capacity=0):
+def run_gpu(model, n, dx, dt, steps, fields, dtype, coef=None, mass_capacity=0, tune=False):
+    """Step `fields` on a fresh grid and read them back.  tune: pick tiles
+    and arrangement with the autotuner first, as the benchmark does."""
     torch, specstep = need_gpu()
     coef = COEF[model] if coef is None else coef
     g = specstep.Grid(n, dx, dtype=dtype, model=model, coef=coef, dt=dt)
+    if tune:
+        say("autotuned tiles", g.autotune(5), "arrangement", specstep.ss_get_step_arrangement(g.h))
     for i, f in enumerate(fields):
         g.set_field(i, torch.from_numpy(np.ascontiguousarray(f)).to("cuda:0"))
     if mass_capacity:

@@ -49,8 +49,11 @@ def test_cahn_hilliard_2048_parity_50_steps(ch2048_oracle50, dtype):
     covers that rounding (3e-8 relative) with four decades to spare."""
     w, want = ch2048_oracle50
     got, mass = run_gpu(w.model, w.n, w.dx, w.dt, 50, w.fields, dtype, coef=w.coef,
-                        mass_capacity=50)
+                        mass_capacity=50, tune=True)
     assert_parity(got, want, dtype, ("cahn_hilliard 2048^2", 50))
+    # the default tiles give the same bits
+    plain, _ = run_gpu(w.model, w.n, w.dx, w.dt, 50, w.fields, dtype, coef=w.coef)
+    assert np.array_equal(plain[0], got[0])
     m0 = float(np.mean(w.fields[0]))
     assert np.max(np.abs(mass[:, 0] - m0)) <= (1e-15 if dtype == "f64" else 1e-8)
 
@@ -94,7 +97,7 @@ def test_pfc_256_parity_50_steps(pfc256_oracle50, dtype):
     w, want2, want50 = pfc256_oracle50
     for steps, want in ((2, want2), (50, want50)):
         got, mass = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef,
-                            mass_capacity=steps)
+                            mass_capacity=steps, tune=steps == 50)
         assert_parity(got, want, dtype, ("pfc 256^3", steps))
 
 
