@@ -38,7 +38,7 @@ def ch2048_oracle50():
 def test_allen_cahn_128(dtype):
     w = inputs.allen_cahn_2d(n=128, seed=1)
     for steps in (50, 100):
-        got, _ = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef)
+        got, _ = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef, tune=True)
         want = spectral.step_n(w.fields, w.model, w.coef, w.dt, w.dx, steps)
         assert_parity(got, want, dtype, ("allen_cahn 128^2", steps))
 
@@ -125,7 +125,7 @@ def test_pfc_256_mass_500_steps(dtype):
 def test_gray_scott_512(dtype):
     w = inputs.gray_scott_2d(n=512)
     steps = 200 if dtype == "f64" else 50
-    got, _ = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef)
+    got, _ = run_gpu(w.model, w.n, w.dx, w.dt, steps, w.fields, dtype, coef=w.coef, tune=True)
     want = oracle_chunked(w, steps, chunk=50, fft=oracle_fft())
     assert_parity(got, want, dtype, ("gray_scott 512^2", steps))
 
