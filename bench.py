@@ -560,6 +560,70 @@ def trace_per_load(d, n):
     return "\n\n".join(out)
 
 
+SQ_KERNELS = [("x pass FP64", "xpass_kernel<double, 2048, 1, 2, 0"),
+              ("k-space pass FP64", "kpass_kernel<double, 2048, true, 0, false>"),
+              ("x pass FP32", "xpass_kernel<float, 2048, 1, 2, 0"),
+              ("k-space pass FP32", "kpass_kernel<float, 2048, true, 0, false>")]
+
+
+def sq_table(dirs):
+    """Markdown table of SQ counters per wave for the two passes of a 2D
+    step at 2048 x 2048 (both precisions), from rocprofv3 --pmc output
+    directories (each pass of counters in its own run), over the dispatches
+    after each precision's refresh of the carried spectrum."""
+    import csv
+    import glob
+    vals = {label: {} for label, _ in SQ_KERNELS}
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if len(files) != 1:
+            raise SystemExit("expected one counter_collection.csv under %s, found %d" % (d, len(files)))
+        disp, names = {}, {}
+        with open(files[0]) as f:
+            for r in csv.DictReader(f):
+                i = int(r["Dispatch_Id"])
+                disp.setdefault(i, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+                names[i] = r["Kernel_Name"]
+        start = {}
+        for i in sorted(disp):
+            for prec in ("double", "float"):
+                if "kfwd_kernel<%s" % prec in names[i]:
+                    start[prec] = i
+        for i in sorted(disp):
+            prec = "double" if "<double" in names[i] else "float"
+            if prec not in start or i <= start[prec]:
+                continue
+            for label, key in SQ_KERNELS:
+                if key in names[i]:
+                    for c, v in disp[i].items():
+                        vals[label].setdefault(c, []).append(v)
+
+    def mean(label, c):
+        v = vals[label].get(c, [])
+        return sum(v) / len(v) if v else float("nan")
+
+    fp = ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+          "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32")
+    lines = ["| kernel | waves | VALU instr | of which FP add/mul/fma | INT32 | LDS instr | SALU | wave cycles | "
+             "VALU active | LDS wait | any wait | LDS conflict / LDS active |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    def num(x, fmt="%d"):
+        return "-" if x != x else fmt % (round(x) if fmt == "%d" else x)
+
+    for label, key in SQ_KERNELS:
+        if not vals[label].get("SQ_WAVES"):
+            continue                                 # kernel absent from these runs
+        w = mean(label, "SQ_WAVES")
+        per = [mean(label, "SQ_INSTS_VALU") / w, sum(mean(label, c) for c in fp) / w]
+        per += [mean(label, c) / w for c in ("SQ_INSTS_VALU_INT32", "SQ_INSTS_LDS", "SQ_INSTS_SALU",
+                                             "SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_WAIT_INST_LDS",
+                                             "SQ_WAIT_INST_ANY")]
+        lines.append("| %s (`%s`) | %d | %s | %s |" % (
+            label, key + ("" if key.endswith(">") else "...>"), round(w), " | ".join(num(x) for x in per),
+            num(mean(label, "SQ_LDS_BANK_CONFLICT") / mean(label, "SQ_ACTIVE_INST_LDS"), "%.2f")))
+    return "\n".join(lines)
+
+
 def counter_table(workload, fetch_dir, write_dir, copyf_dir, copyw_dir, copy_mb=64):
     """Markdown table of the memory counters per dispatch of the timed
     configuration (dispatches after each precision's kfwd_kernel): raw
@@ -697,12 +761,17 @@ def main():
                          "rocprofv3 --pmc output directories as --traffic-record and exit; no GPU is used")
     ap.add_argument("--trace-last", type=int, default=0, metavar="N",
                     help="with --trace-summary: the last N dispatches of each kernel instead")
+    ap.add_argument("--sq-table", nargs="+", metavar="PMC_DIR",
+                    help="only print the per-wave SQ counter table of the 2048^2 passes from --pmc runs")
     ap.add_argument("--trace-per-load", type=int, default=0, metavar="N",
                     help="with --trace-summary: one table per field load, the N dispatches after it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (for scaling "
                          "the memory counters of a profiler) and exit")
     args = ap.parse_args()
+    if args.sq_table:
+        print(sq_table(args.sq_table), flush=True)
+        return
     if args.trace_summary:
         if args.trace_per_load:
             print(trace_per_load(args.trace_summary, args.trace_per_load), flush=True)

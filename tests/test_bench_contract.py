@@ -163,3 +163,25 @@ def test_trace_per_load_takes_the_dispatches_after_each_load(tmp_path):
     assert "| `%s` | 2 | 21.00 | 20.00 |" % X in first and "| `%s` | 2 | 31.00 | 30.00 |" % K in first
     assert "| `%s` | 1 | 10.00 | 10.00 |" % X in second and "| `%s` | 1 | 12.00 | 12.00 |" % K in second
     assert "90.00" not in out
+
+
+def test_sq_table_per_wave_after_the_refresh(tmp_path):
+    import csv
+    X = "void ss::xpass_kernel<double, 2048, 1, 2, 0, false>(ss::XArgs)"
+    F = "void ss::kfwd_kernel<double, 2048>(ss::KArgs)"
+    runs = {"a": {"SQ_WAVES": 2048, "SQ_INSTS_VALU": 2048 * 100, "SQ_INSTS_LDS": 2048 * 10},
+            "b": {"SQ_ACTIVE_INST_LDS": 400, "SQ_LDS_BANK_CONFLICT": 100}}
+    dirs = []
+    for name, counters in runs.items():
+        os.makedirs(tmp_path / name)
+        with open(tmp_path / name / "x_counter_collection.csv", "w", newline="") as f:
+            w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+            w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            for c, v in counters.items():
+                w.writerow([1, X, c, 7 * v])        # a trial before the refresh
+                w.writerow([2, F, c, 1])
+                w.writerow([3, X, c, v])
+        dirs.append(str(tmp_path / name))
+    row = [l for l in bench.sq_table(dirs).splitlines() if l.startswith("| x pass FP64")][0].split("|")
+    assert row[2].strip() == "2048" and row[3].strip() == "100" and row[6].strip() == "10"
+    assert row[-2].strip() == "0.25"
